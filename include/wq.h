@@ -1,0 +1,174 @@
+/*
+ * wq.h -- C ABI of the MI355X (gfx950) weighted-quadrature library (libwq.so).
+ *
+ * Weighted quadrature (WQ) on unstructured bicubic splines: each test function N_i
+ * gets its own quadrature rule Q_i(g) = sum_q w_iq g(x_q) over points placed in the
+ * physical domain (Section 4.1, Eqs. (8)-(10)); the weights solve underdetermined
+ * exactness systems by truncated SVD (Section 4.3, Eqs. (19)-(22)); Galerkin matrices
+ * are then formed row by row (Eqs. (9), (11), (12), (36)).
+ *
+ * Conventions for every entry point:
+ *  - Returns wq_status; WQ_OK == 0. No exceptions cross the ABI. On error, outputs are
+ *    left untouched and wq_last_error() returns a thread-local message.
+ *  - "host" pointers are read during the call only (the caller keeps ownership).
+ *    "device" pointers are HIP device memory owned by the caller; they must stay valid
+ *    until the work queued on `stream` has completed.
+ *  - Handles (wq_mesh, wq_points, wq_weights) own their device memory and are released
+ *    by the matching *_destroy call. A handle is used on the device that was current
+ *    when it was created.
+ *  - build_points and solve_weights synchronise their stream (they return counts);
+ *    assemble_* calls are asynchronous on `stream` (0 = the null stream).
+ *  - Indices are 0-based. Floating point is IEEE FP64 unless stated.
+ */
+#ifndef WQ_H
+#define WQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wq_mesh wq_mesh;
+typedef struct wq_points wq_points;
+typedef struct wq_weights wq_weights;
+typedef void* wq_stream; /* a hipStream_t */
+
+typedef enum {
+  WQ_OK = 0,
+  WQ_EINVAL = -1,      /* bad argument, inconsistent sizes, unsupported option       */
+  WQ_ENOMEM = -2,      /* device allocation failed                                   */
+  WQ_EILLPOSED = -3,   /* some row has fewer points than constraints (r_i < n_i)     */
+  WQ_ESVD = -4,        /* a Jacobi SVD did not converge within its sweep limit       */
+  WQ_ENOCONV = -5,     /* an iterative solve did not converge                        */
+  WQ_EDEVICE = -6      /* a HIP runtime call failed                                  */
+} wq_status;
+
+/* Weight families (bit mask): exactness for N_j, dN_j/dx, dN_j/dy, Lap N_j
+ * (Eq. (9), the two planar terms of Eq. (11), Eq. (12)). */
+typedef enum { WQ_FAM_MASS = 1, WQ_FAM_DX = 2, WQ_FAM_DY = 4, WQ_FAM_LAP = 8 } wq_family;
+
+/* Arithmetic of the row contraction. FP64 everywhere else, always. */
+typedef enum { WQ_FP64 = 0, WQ_SPLIT_FP16 = 1, WQ_SPLIT_BF16 = 2 } wq_precision;
+
+/* ------------------------------------------------------------------ input mesh
+ * Control mesh and Bezier extraction of the spline space (Section 3). All arrays are
+ * host arrays, copied to the device by wq_mesh_create.
+ *   face_vtx  [nf*4]  counter-clockwise vertex ids of each quad face
+ *   split     [nf]    1: the face is split 2x2 into Bezier sub-elements (irregular)
+ *   ext_ptr   [nf+1]  offsets into ext_fn; face f carries m_f = ext_ptr[f+1]-ext_ptr[f]
+ *   ext_fn    [.]     global ids of the functions on each face, ascending
+ *   coef_ptr  [nf+1]  offsets (in doubles) into coef
+ *   coef      [.]     per face nsub x m_f x 16 Bernstein coefficients, index k + 4 l
+ *                     (k along corner0->corner1); nsub = 4 if split (sub-element
+ *                     sx + 2 sy covers [sx/2,(sx+1)/2] x [sy/2,(sy+1)/2]), else 1
+ *   ctrl      [n_fn*2] control points; the geometry map is x = sum_j ctrl_j N_j
+ * Faces touching the boundary are passive (zero parametric area) and carry m_f = 0. */
+typedef struct {
+  int32_t nv, nf, n_fn;
+  const int32_t* face_vtx;
+  const uint8_t* split;
+  const int64_t* ext_ptr;
+  const int32_t* ext_fn;
+  const int64_t* coef_ptr;
+  const double* coef;
+  const double* ctrl;
+} wq_mesh_desc;
+
+wq_status wq_mesh_create(const wq_mesh_desc* desc, wq_mesh** out);
+void wq_mesh_destroy(wq_mesh* mesh);
+
+/* ------------------------------------------------------------------ build_points
+ * Classifies elements (Section 3 definitions) and chooses s_e x s_e points per element
+ * from Table 2 (non-enriched transition: 3x3, 4x4 next to EPs of valence >= 7 or EPs
+ * of two different irregular neighbourhoods), checks the well-posedness r_i >= n_i of
+ * Section 4.2 and, where it fails, applies the min-max allocation of Eq. (18).
+ * Then builds, on the device:
+ *  - the points: s x s per element at ((2a+1)/(2s), (2b+1)/(2s)) of its parametric
+ *    square, numbered Bezier cell by cell (split elements contribute 4 cells), inside a
+ *    cell by (b, a) row-major; basis values N, dN/dx, dN/dy (and Lap N if
+ *    want_laplacian) of every cell function at every point, x, and det J;
+ *  - the CSR pattern of Eq. (10): row i holds S_i (functions nonzero on some cell of
+ *    supp N_i), columns ascending;
+ *  - the point sets Q_i: the point ranges of the cells of supp N_i, cells ascending.
+ * Outputs the sizes (host scalars). Synchronises `stream`. */
+wq_status build_points(wq_mesh* mesh, int want_laplacian, wq_stream stream, wq_points** out,
+                       int64_t* n_rows, int64_t* nnz, int64_t* n_points);
+void wq_points_destroy(wq_points* pts);
+
+/* As build_points, but starting from the caller's points per direction s[nf] (host,
+ * uint8, 0 for passive faces) instead of Table 2; the well-posedness check and the
+ * min-max allocation of Eq. (18) still apply. For studies of point allocations. */
+wq_status build_points_with_s(wq_mesh* mesh, const uint8_t* s_host, int want_laplacian, wq_stream stream,
+                              wq_points** out, int64_t* n_rows, int64_t* nnz, int64_t* n_points);
+
+/* Copies of the device arrays built above into caller device buffers (for checks and
+ * for users that need the pattern). `what` selects the array and its element type:
+ *   WQ_ARR_ROW_PTR  int64[n+1]   WQ_ARR_COL   int32[nnz]
+ *   WQ_ARR_QPTR     int64[n+1]   WQ_ARR_QIDX  int32[sum r_i]
+ *   WQ_ARR_ETYPE    uint8[nf]  (0 passive, 1 regular, 2 boundary, 3 irregular, 4 transition)
+ *   WQ_ARR_S        uint8[nf]    points per direction (0: passive)
+ *   WQ_ARR_X        double[2*np] WQ_ARR_DETJ double[np]
+ * wq_points_size() returns the element count of each array. */
+typedef enum {
+  WQ_ARR_ROW_PTR = 0, WQ_ARR_COL = 1, WQ_ARR_QPTR = 2, WQ_ARR_QIDX = 3,
+  WQ_ARR_ETYPE = 4, WQ_ARR_S = 5, WQ_ARR_X = 6, WQ_ARR_DETJ = 7
+} wq_array;
+int64_t wq_points_size(const wq_points* pts, wq_array what);
+wq_status wq_points_get(const wq_points* pts, wq_array what, void* dst_device, wq_stream stream);
+
+/* ------------------------------------------------------------------ solve_weights
+ * For every row i and every family in fam_mask: the right-hand side b (the exact
+ * integrals, Section 2: "precomputed") by 4x4 Gauss quadrature on every Bezier cell
+ * (Section 4.2), then the truncated-SVD weights of Eqs. (20)-(22):
+ *   A = U S V^T, keep sigma_k > tsvd_rel_cutoff * sigma_1,
+ *   w = Z^2 V_t (V_t^T Z^2 V_t)^{-1} S_t^{-1} U_t^T b,  Z = diag(N_i(x_q)),
+ * with the inverse applied through a QR factorisation of Z V_t (as Eq. (7) does for
+ * A Z^2 A^T). One-sided Jacobi SVD in FP64. Weights are stored aligned with Q_i.
+ * report (host, nullable): per family counts and worst cases, see wq_solve_report.
+ * Synchronises `stream`. Returns WQ_ESVD if a Jacobi SVD hit its sweep limit. */
+typedef struct {
+  int64_t systems;          /* number of (row, family) systems solved                 */
+  int64_t truncated;        /* systems with t < n_i                                   */
+  int32_t max_sweeps;       /* largest number of Jacobi sweeps used                   */
+  double min_kept_ratio;    /* smallest sigma_t / sigma_1 kept                        */
+  double max_dropped_ratio; /* largest sigma_{t+1} / sigma_1 dropped                  */
+} wq_solve_report;
+
+wq_status solve_weights(wq_mesh* mesh, wq_points* pts, unsigned fam_mask, double tsvd_rel_cutoff,
+                        wq_stream stream, wq_weights** out, wq_solve_report* report);
+void wq_weights_destroy(wq_weights* w);
+
+/* Device copies of the weights of one family (double[sum r_i], aligned with QIDX) and of
+ * the Gauss right-hand sides of one family (double[nnz], aligned with COL). */
+wq_status wq_weights_get(const wq_weights* w, wq_family fam, double* dst_device, wq_stream stream);
+wq_status wq_rhs_get(const wq_weights* w, wq_family fam, double* dst_device, wq_stream stream);
+
+/* ------------------------------------------------------------------ assembly
+ * Row-wise WQ formation on the fixed pattern (Section 6.1: formed row by row).
+ *   assemble_mass:       M_ij = sum_{q in Q_i} w^0_iq c(x_q) N_j(x_q)            (Eq. 9)
+ *   assemble_stiffness:  K_ij = sum_q k(x_q) (w^x_iq dN_j/dx + w^y_iq dN_j/dy)   (Eq. 11)
+ *   assemble_biharmonic: B_ij = sum_q d(x_q) w^L_iq Lap N_j(x_q)                 (Eq. 12)
+ *   assemble_mass_stiffness: both M and K in one pass over the weights.
+ * coef_at_points: device double[n_points] or NULL (coefficient 1).
+ * vals: device output aligned with COL, double[nnz] for WQ_FP64, float[nnz] for the
+ * split precisions (operands split into two FP16 / three BF16 terms, products on MFMA
+ * with FP32 accumulation). Asynchronous on `stream`. */
+wq_status assemble_mass(const wq_points* pts, const wq_weights* w, const double* coef_at_points,
+                        void* vals, wq_precision prec, wq_stream stream);
+wq_status assemble_stiffness(const wq_points* pts, const wq_weights* w, const double* coef_at_points,
+                             void* vals, wq_precision prec, wq_stream stream);
+wq_status assemble_biharmonic(const wq_points* pts, const wq_weights* w, const double* coef_at_points,
+                              void* vals, wq_precision prec, wq_stream stream);
+wq_status assemble_mass_stiffness(const wq_points* pts, const wq_weights* w, const double* c_at_points,
+                                  const double* k_at_points, void* mass_vals, void* stiff_vals,
+                                  wq_precision prec, wq_stream stream);
+
+/* ------------------------------------------------------------------ errors */
+const char* wq_strerror(wq_status s);
+const char* wq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WQ_H */

@@ -182,7 +182,7 @@ def overlap_sets(fx, cl, supp):
     return out
 
 
-def points_per_element(fx, cls):
+def points_per_element(fx, cls, s_init=None):
     """Table 2 counts, then the well-posedness check r_i >= n_i and, where it fails,
     the "min-max" allocation of Eq. (18) for the non-regular, non-boundary elements.
 
@@ -191,7 +191,7 @@ def points_per_element(fx, cls):
     row is well posed. supp(N_i) in Eq. (18) is the set of elements holding a cell of
     the support; m_k counts the functions of element k.
     """
-    s = cls["s"].copy()
+    s = (cls["s"] if s_init is None else np.asarray(s_init, dtype=np.int64)).copy()
     etype = cls["etype"]
     m = np.array([fx["ext_ptr"][f + 1] - fx["ext_ptr"][f] for f in range(len(s))])
     for _ in range(16):

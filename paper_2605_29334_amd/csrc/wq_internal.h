@@ -1,0 +1,131 @@
+// Internal definitions shared by the libwq translation units (gfx950, HIP).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/wq.h"
+
+namespace wq {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+
+#define WQ_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::wq::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+      return WQ_EDEVICE;                                                          \
+    }                                                                             \
+  } while (0)
+
+#define WQ_CHECK(cond, code, msg)                                                 \
+  do {                                                                            \
+    if (!(cond)) {                                                                \
+      ::wq::set_error(msg);                                                       \
+      return code;                                                                \
+    }                                                                             \
+  } while (0)
+
+#define WQ_TRY(expr)                                                              \
+  do {                                                                            \
+    wq_status s_ = (expr);                                                        \
+    if (s_ != WQ_OK) return s_;                                                   \
+  } while (0)
+
+// ------------------------------------------------------------------ device buffers
+// A device allocation owned by a handle; freed by release().
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+wq_status dalloc(DBuf& b, size_t bytes);
+void dfree(DBuf& b);
+
+template <class T> inline wq_status dalloc_n(DBuf& b, size_t n) { return dalloc(b, n * sizeof(T)); }
+
+// element type codes (WQ_ARR_ETYPE)
+enum : uint8_t { ET_PASSIVE = 0, ET_REGULAR = 1, ET_BOUNDARY = 2, ET_IRREGULAR = 3, ET_TRANSITION = 4 };
+
+}  // namespace wq
+
+struct wq_mesh {
+  int device = 0;
+  int32_t nv = 0, nf = 0, n_fn = 0;
+  int64_t n_ext = 0, n_coef = 0;
+  wq::DBuf face_vtx, split, ext_ptr, ext_fn, coef_ptr, coef, ctrl;
+  // host copies needed by the (rare) min-max fallback of Eq. (18)
+  std::vector<int64_t> h_ext_ptr;
+};
+
+struct wq_points {
+  wq_mesh* mesh = nullptr;
+  int32_t ncell = 0;
+  int64_t n_rows = 0, nnz = 0, n_points = 0, n_pairs = 0, n_slots = 0, n_cfn = 0, n_basis = 0;
+  int32_t max_row = 0;     // max n_i
+  int32_t max_r = 0;       // max r_i
+  int32_t max_cell_m = 0;  // max functions on a cell
+  int32_t max_cell_np = 0; // max points on a cell
+  int has_lap = 0;
+  // per face
+  wq::DBuf etype, s;
+  // per cell
+  wq::DBuf cell_face, cell_sub, cell_pt_off /*int64 [ncell+1]*/, cfn_ptr /*int64 [ncell+1]*/,
+      cfn /*int32*/, cfn_loc /*uint8*/, dptr /*int64 [ncell+1]*/;
+  // per function (row)
+  wq::DBuf supp_ptr /*int64 [n+1]*/, supp_cell /*int32*/, row_ptr /*int64*/, col /*int32*/,
+      qptr /*int64*/, qidx /*int32*/;
+  // per (row, cell) pair = supp entry
+  wq::DBuf soff /*int64 [pairs+1]*/, slot /*uint8*/, kself /*uint8*/;
+  // per point
+  wq::DBuf x /*double [2 np]*/, detJ /*double [np]*/;
+  // per (cell, point, cell function)
+  wq::DBuf DN, DX, DY, DL;
+};
+
+struct wq_weights {
+  wq_points* pts = nullptr;
+  unsigned fam_mask = 0;
+  wq::DBuf W[4];    // weights per family, aligned with qidx
+  wq::DBuf rhs[4];  // Gauss right-hand sides per family, aligned with col
+};
+
+// ------------------------------------------------------------------ device helpers
+namespace wq {
+
+__host__ __device__ inline int fam_index(unsigned fam) {
+  return fam == WQ_FAM_MASS ? 0 : fam == WQ_FAM_DX ? 1 : fam == WQ_FAM_DY ? 2 : 3;
+}
+
+// cubic Bernstein values and derivatives
+__device__ inline void bern3(double t, double b[4], double d[4], double s[4]) {
+  const double u = 1.0 - t;
+  b[0] = u * u * u;
+  b[1] = 3.0 * t * u * u;
+  b[2] = 3.0 * t * t * u;
+  b[3] = t * t * t;
+  d[0] = -3.0 * u * u;
+  d[1] = 3.0 * u * u - 6.0 * t * u;
+  d[2] = 6.0 * t * u - 3.0 * t * t;
+  d[3] = 3.0 * t * t;
+  s[0] = 6.0 * u;
+  s[1] = -12.0 * u + 6.0 * t;
+  s[2] = 6.0 * u - 12.0 * t;
+  s[3] = 6.0 * t;
+}
+
+// exclusive scan of n int64 values in place on the device. *total receives the result at
+// index n-1, i.e. the sum of the first n-1 inputs (callers scan count+1 entries).
+wq_status exclusive_scan_i64(int64_t* d, int64_t n, int64_t* total, hipStream_t st);
+
+// 64-bit index launch helper
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace wq

@@ -1,0 +1,599 @@
+// solve_weights: exact right-hand sides by Gauss quadrature (Section 2, Section 4.2)
+// and truncated-SVD weights (Section 4.3, Eqs. (19)-(22)) for every (row, family).
+#include "wq_internal.h"
+
+#include <cmath>
+#include <cstring>
+
+using namespace wq;
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int GQ_GROUP = 16;   // lanes per row in the Gauss row kernel
+constexpr int MAX_SWEEPS = 40;
+
+// 4-point Gauss-Legendre on [0, 1]
+__constant__ double c_gp[4] = {0.0694318442029737124, 0.3300094782075718676, 0.6699905217924281324,
+                               0.9305681557970262876};
+__constant__ double c_gw[4] = {0.1739274225687269287, 0.3260725774312730713, 0.3260725774312730713,
+                               0.1739274225687269287};
+
+__device__ inline void eval_fn(const double* C, const double b1[4], const double d1[4], const double s1[4],
+                               const double b2[4], const double d2[4], const double s2[4], double out[6]) {
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int l = 0; l < 4; ++l) {
+    double r0 = 0, r1 = 0, r2 = 0;
+    for (int k = 0; k < 4; ++k) {
+      const double c = C[k + 4 * l];
+      r0 += c * b1[k];
+      r1 += c * d1[k];
+      r2 += c * s1[k];
+    }
+    v[0] += r0 * b2[l];
+    v[1] += r1 * b2[l];
+    v[2] += r0 * d2[l];
+    v[3] += r2 * b2[l];
+    v[4] += r1 * d2[l];
+    v[5] += r0 * s2[l];
+  }
+  for (int q = 0; q < 6; ++q) out[q] = v[q];
+}
+
+// Basis data at the 16 Gauss points of every cell: G?[c*16*? ...] laid out like the WQ
+// data (point-major, cell functions contiguous), plus gw = weight * |det J|.
+__global__ void k_gauss_basis(int32_t ncell, const int32_t* cell_face, const uint8_t* cell_sub,
+                              const int64_t* ext_ptr, const int64_t* coef_ptr, const double* coef,
+                              const double* ctrl, const int64_t* cfn_ptr, const int32_t* cfn, const uint8_t* cfn_loc,
+                              double* GN, double* GX, double* GY, double* GL, double* gw) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= 16LL * ncell) return;
+  const int64_t c = t / 16;
+  const int g = (int)(t % 16);
+  const int32_t f = cell_face[c];
+  const int sub = cell_sub[c];
+  double b1[4], d1[4], s1[4], b2[4], d2[4], s2[4];
+  bern3(c_gp[g % 4], b1, d1, s1);
+  bern3(c_gp[g / 4], b2, d2, s2);
+  const int mf = (int)(ext_ptr[f + 1] - ext_ptr[f]);
+  const double* Cf = coef + coef_ptr[f] + (int64_t)sub * mf * 16;
+  const int64_t f0 = cfn_ptr[c];
+  const int m = (int)(cfn_ptr[c + 1] - f0);
+  double J[2][2] = {{0, 0}, {0, 0}}, H[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  for (int k = 0; k < m; ++k) {
+    double v[6];
+    eval_fn(Cf + 16 * (int)cfn_loc[f0 + k], b1, d1, s1, b2, d2, s2, v);
+    const int32_t j = cfn[f0 + k];
+    for (int a = 0; a < 2; ++a) {
+      const double P = ctrl[2 * (int64_t)j + a];
+      J[a][0] += P * v[1];
+      J[a][1] += P * v[2];
+      H[a][0] += P * v[3];
+      H[a][1] += P * v[4];
+      H[a][2] += P * v[5];
+    }
+  }
+  const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double id = 1.0 / det;
+  const double Ji[2][2] = {{J[1][1] * id, -J[0][1] * id}, {-J[1][0] * id, J[0][0] * id}};
+  const double G00 = Ji[0][0] * Ji[0][0] + Ji[0][1] * Ji[0][1];
+  const double G01 = Ji[0][0] * Ji[1][0] + Ji[0][1] * Ji[1][1];
+  const double G11 = Ji[1][0] * Ji[1][0] + Ji[1][1] * Ji[1][1];
+  gw[16 * c + g] = c_gw[g % 4] * c_gw[g / 4] * fabs(det);
+  const int64_t o = 16 * f0 + (int64_t)g * m;
+  for (int k = 0; k < m; ++k) {
+    double v[6];
+    eval_fn(Cf + 16 * (int)cfn_loc[f0 + k], b1, d1, s1, b2, d2, s2, v);
+    const double nx = Ji[0][0] * v[1] + Ji[1][0] * v[2];
+    const double ny = Ji[0][1] * v[1] + Ji[1][1] * v[2];
+    GN[o + k] = v[0];
+    GX[o + k] = nx;
+    GY[o + k] = ny;
+    if (GL) {
+      const double h00 = v[3] - nx * H[0][0] - ny * H[1][0];
+      const double h01 = v[4] - nx * H[0][1] - ny * H[1][1];
+      const double h11 = v[5] - nx * H[0][2] - ny * H[1][2];
+      GL[o + k] = h00 * G00 + 2.0 * h01 * G01 + h11 * G11;
+    }
+  }
+}
+
+// Row i of the Gauss matrices on the CSR pattern, one 16-lane group per row:
+// b^f_i[slot(j)] = sum_{cells c in supp i} sum_g gw_g D^f N_i(g) D^f N_j(g).
+// Cells are visited in ascending order and each lane owns distinct slots at every
+// step, so the summation order is fixed (deterministic, no atomics).
+__global__ void k_gauss_rows(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cfn_ptr,
+                             const int64_t* soff, const uint8_t* slot, const uint8_t* kself, const int64_t* row_ptr,
+                             const double* G0, const double* G1, const double* G2, const double* G3,
+                             const double* gw, unsigned mask, int max_row, double* R0, double* R1, double* R2,
+                             double* R3) {
+  extern __shared__ double sh_acc[];
+  const int grp = threadIdx.x / GQ_GROUP;
+  const int lane = threadIdx.x % GQ_GROUP;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / GQ_GROUP) + grp;
+  double* acc = sh_acc + (size_t)grp * 4 * max_row;
+  const double* Gs[4] = {G0, G1, G2, G3};
+  double* Rs[4] = {R0, R1, R2, R3};
+  const bool active = i < n;
+  for (int t = lane; t < 4 * max_row; t += GQ_GROUP) acc[t] = 0.0;
+  __syncthreads();
+  if (active) {
+    for (int64_t p = sptr[i]; p < sptr[i + 1]; ++p) {
+      const int32_t c = scell[p];
+      const int64_t f0 = cfn_ptr[c];
+      const int m = (int)(cfn_ptr[c + 1] - f0);
+      const int ks = kself[p];
+      const uint8_t* sl = slot + soff[p];
+      for (int k = lane; k < m; k += GQ_GROUP) {
+        const int sk = sl[k];
+        for (int fam = 0; fam < 4; ++fam) {
+          if (!(mask & (1u << fam))) continue;
+          const double* G = Gs[fam] + 16 * f0;
+          double v = 0.0;
+          for (int g = 0; g < 16; ++g) v += (gw[16 * (int64_t)c + g] * G[g * m + ks]) * G[g * m + k];
+          acc[fam * max_row + sk] += v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+    const int ni = (int)(row_ptr[i + 1] - row_ptr[i]);
+    for (int fam = 0; fam < 4; ++fam) {
+      if (!(mask & (1u << fam))) continue;
+      for (int t = lane; t < ni; t += GQ_GROUP) Rs[fam][row_ptr[i] + t] = acc[fam * max_row + t];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ TSVD
+struct SysClass {
+  int max_n, max_r;
+};
+
+__global__ void k_sys_class(int64_t n, const int64_t* row_ptr, const int64_t* qptr, int64_t* small, int* mx) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ni = (int)(row_ptr[i + 1] - row_ptr[i]);
+  const int ri = (int)(qptr[i + 1] - qptr[i]);
+  const bool sm = (ni <= 64 && ri <= 64);
+  small[i] = sm ? 1 : 0;
+  if (sm) {
+    atomicMax(&mx[0], ni);
+    atomicMax(&mx[1], ri);
+  } else {
+    atomicMax(&mx[2], ni);
+    atomicMax(&mx[3], ri);
+  }
+}
+
+__global__ void k_sys_lists(int64_t n, const int64_t* small, const int64_t* pos, int32_t* list0, int32_t* list1) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (small[i]) list0[pos[i]] = (int32_t)i;
+  else list1[i - pos[i]] = (int32_t)i;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// order-preserving bit pattern of a non-negative double for atomicMin/atomicMax
+__device__ inline unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+struct TsvdArgs {
+  const int32_t* rows;
+  int64_t nsys;
+  int ld;  // leading dimension (doubles) of a column in LDS, odd, >= r_max + 1
+  int fam;
+  double tau;
+  const int64_t* sptr;
+  const int32_t* scell;
+  const int64_t* cfn_ptr;
+  const int64_t* cell_pt_off;
+  const int64_t* dptr;
+  const int64_t* soff;
+  const uint8_t* slot;
+  const uint8_t* kself;
+  const int64_t* row_ptr;
+  const int64_t* qptr;
+  const double* D;    // basis data of the family
+  const double* DN;   // values (for Z)
+  const double* rhs;  // Gauss right-hand side of the family, aligned with col
+  double* W;          // output weights aligned with qidx
+  int* max_sweeps;
+  unsigned long long* min_kept;     // bits of a double
+  unsigned long long* max_dropped;  // bits of a double
+  unsigned long long* truncated;
+  int* fail;
+};
+
+// One wavefront per (row, family) system. LDS: G (n columns of length ld: the r point
+// values of column l = A[l, :]^T, followed by b_l), z (r), and work vectors.
+// Steps: gather A and b; one-sided Jacobi (Hestenes) on A^T, rotating b along, so that
+// the final columns are V S and the rotated b is U^T b; keep sigma_l > tau sigma_max;
+// c = S_t^{-1} U_t^T b; x_l = Z v_l; CGS2 QR of the kept x_l with the forward
+// substitution y = R^{-T} c carried along; w = Z Q y.
+__global__ void __launch_bounds__(64) k_tsvd(TsvdArgs a) {
+  extern __shared__ double sh[];
+  const int64_t sys = blockIdx.x;
+  if (sys >= a.nsys) return;
+  const int lane = threadIdx.x;
+  const int64_t i = a.rows[sys];
+  const int n = (int)(a.row_ptr[i + 1] - a.row_ptr[i]);
+  const int r = (int)(a.qptr[i + 1] - a.qptr[i]);
+  const int ld = a.ld;
+  double* Gm = sh;                       // n * ld
+  double* z = Gm + (size_t)n * ld;       // r
+  double* wacc = z + r;                  // r
+  double* sig = wacc + r;                // n
+  double* Rk = sig + n;                  // n (column k of R)
+  double* yv = Rk + n;                   // n
+  int* keep = (int*)(yv + n);            // n
+  // 1. gather
+  for (int t = lane; t < n * ld; t += 64) Gm[t] = 0.0;
+  __syncthreads();
+  {
+    int moff = 0;
+    for (int64_t p = a.sptr[i]; p < a.sptr[i + 1]; ++p) {
+      const int32_t c = a.scell[p];
+      const int m = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
+      const int np = (int)(a.cell_pt_off[c + 1] - a.cell_pt_off[c]);
+      const double* Dc = a.D + a.dptr[c];
+      const double* Nc = a.DN + a.dptr[c];
+      const uint8_t* sl = a.slot + a.soff[p];
+      const int ks = a.kself[p];
+      for (int t = lane; t < np * m; t += 64) {
+        const int q = t / m, k = t % m;
+        Gm[(size_t)sl[k] * ld + moff + q] = Dc[t];
+      }
+      for (int q = lane; q < np; q += 64) z[moff + q] = Nc[q * m + ks];
+      moff += np;
+    }
+    for (int l = lane; l < n; l += 64) Gm[(size_t)l * ld + r] = a.rhs[a.row_ptr[i] + l];
+  }
+  __syncthreads();
+  // 2. one-sided Jacobi, round-robin (circle) ordering, LPP lanes per pair
+  const int nn = n + (n & 1);
+  const int npair = nn / 2;
+  int lpp = 1;
+  while (lpp * 2 * npair <= 64 && lpp < 8) lpp *= 2;
+  const int pk = lane / lpp, sub = lane % lpp;
+  int sweeps = 0;
+  bool converged = false;
+  for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
+    int rotated = 0;
+    for (int rd = 0; rd < nn - 1; ++rd) {
+      if (pk < npair) {
+        const int pa = pk, pb = nn - 1 - pk;
+        const int P = (pa == 0) ? 0 : 1 + (pa - 1 + rd) % (nn - 1);
+        const int Q = 1 + (pb - 1 + rd) % (nn - 1);
+        if (P < n && Q < n) {
+          double* gp = Gm + (size_t)P * ld;
+          double* gq = Gm + (size_t)Q * ld;
+          double al = 0, be = 0, ga = 0;
+          for (int m = sub; m < r; m += lpp) {
+            const double u = gp[m], v = gq[m];
+            al += u * u;
+            be += v * v;
+            ga += u * v;
+          }
+          for (int off = 1; off < lpp; off <<= 1) {
+            al += __shfl_xor(al, off, 64);
+            be += __shfl_xor(be, off, 64);
+            ga += __shfl_xor(ga, off, 64);
+          }
+          if (fabs(ga) > 1e-15 * sqrt(al * be) && al * be > 0.0) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t);
+            const double sn = cs * t;
+            for (int m = sub; m <= r; m += lpp) {
+              const double u = gp[m], v = gq[m];
+              gp[m] = cs * u - sn * v;
+              gq[m] = sn * u + cs * v;
+            }
+            rotated = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    converged = !__any(rotated);
+  }
+  if (!converged) atomicOr(a.fail, 1);
+  if (lane == 0) atomicMax(a.max_sweeps, sweeps);
+  // 3. singular values and truncation
+  double smax = 0.0;
+  for (int l = lane; l < n; l += 64) {
+    const double* g = Gm + (size_t)l * ld;
+    double s2 = 0.0;
+    for (int m = 0; m < r; ++m) s2 += g[m] * g[m];
+    sig[l] = sqrt(s2);
+    smax = fmax(smax, sig[l]);
+  }
+  for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
+  __syncthreads();
+  if (lane == 0) {
+    int t = 0;
+    double kmin = INFINITY, dmax = 0.0;
+    for (int l = 0; l < n; ++l) {
+      if (sig[l] > a.tau * smax) {
+        keep[t++] = l;
+        kmin = fmin(kmin, sig[l] / smax);
+      } else {
+        dmax = fmax(dmax, sig[l] / smax);
+      }
+    }
+    yv[0] = (double)t;          // stash t
+    atomicMin(a.min_kept, dbits(kmin));
+    atomicMax(a.max_dropped, dbits(dmax));
+    if (t < n) atomicAdd(a.truncated, 1ULL);
+  }
+  __syncthreads();
+  const int t = (int)yv[0];
+  __syncthreads();
+  // 4. c_l = (U^T b)_l / sigma_l stored in sig[]; x_l = Z v_l = z * g_l / sigma_l
+  for (int k = 0; k < t; ++k) {
+    const int l = keep[k];
+    double* g = Gm + (size_t)l * ld;
+    const double inv = 1.0 / sig[l];
+    for (int m = lane; m < r; m += 64) g[m] = z[m] * g[m] * inv;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    for (int k = 0; k < t; ++k) {
+      const int l = keep[k];
+      Rk[k] = Gm[(size_t)l * ld + r] / sig[l];  // c_k (temporarily in Rk)
+    }
+    for (int k = 0; k < t; ++k) yv[k] = Rk[k];
+  }
+  for (int m = lane; m < r; m += 64) wacc[m] = 0.0;
+  __syncthreads();
+  // 5. CGS2 on the kept columns; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk; w += y_k q_k
+  for (int k = 0; k < t; ++k) {
+    double* x = Gm + (size_t)keep[k] * ld;
+    for (int j = lane; j < k; j += 64) Rk[j] = 0.0;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int j = lane; j < k; j += 64) {
+        const double* qj = Gm + (size_t)keep[j] * ld;
+        double d = 0.0;
+        for (int m = 0; m < r; ++m) d += qj[m] * x[m];
+        Rk[j] += d;
+        sig[j] = d;  // this pass's coefficients (sig[] no longer needed for j < k)
+      }
+      __syncthreads();
+      for (int m = lane; m < r; m += 64) {
+        double v = x[m];
+        for (int j = 0; j < k; ++j) v -= Gm[(size_t)keep[j] * ld + m] * sig[j];
+        x[m] = v;
+      }
+      __syncthreads();
+    }
+    double nrm = 0.0;
+    for (int m = lane; m < r; m += 64) nrm += x[m] * x[m];
+    nrm = sqrt(wave_sum(nrm));
+    double acc = 0.0;
+    for (int j = lane; j < k; j += 64) acc += Rk[j] * yv[j];
+    acc = wave_sum(acc);
+    const double yk = (yv[k] - acc) / nrm;  // yv[k] still holds c_k
+    __syncthreads();
+    const double inv = 1.0 / nrm;
+    for (int m = lane; m < r; m += 64) {
+      const double qm = x[m] * inv;
+      x[m] = qm;
+      wacc[m] += qm * yk;
+    }
+    if (lane == 0) yv[k] = yk;
+    __syncthreads();
+  }
+  double* W = a.W + a.qptr[i];
+  for (int m = lane; m < r; m += 64) W[m] = z[m] * wacc[m];
+}
+
+void release_weights(wq_weights* w) {
+  for (int f = 0; f < 4; ++f) {
+    dfree(w->W[f]);
+    dfree(w->rhs[f]);
+  }
+}
+
+}  // namespace
+
+extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, double tau, wq_stream stream,
+                                   wq_weights** out, wq_solve_report* rep) {
+  WQ_CHECK(M && P && out && P->mesh == M, WQ_EINVAL, "solve_weights: bad arguments");
+  WQ_CHECK(fam_mask && !(fam_mask & ~15u), WQ_EINVAL, "solve_weights: bad family mask");
+  WQ_CHECK(!(fam_mask & WQ_FAM_LAP) || P->has_lap, WQ_EINVAL,
+           "solve_weights: Laplacian weights need build_points(want_laplacian=1)");
+  WQ_CHECK(tau > 0.0 && tau < 1.0, WQ_EINVAL, "solve_weights: cutoff must be in (0,1)");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = P->n_rows;
+  wq_weights* w = new wq_weights();
+  w->pts = P;
+  w->fam_mask = fam_mask;
+  wq_status s = WQ_OK;
+  // Gauss data
+  DBuf G[4], gw;
+  const int64_t ng = 16 * P->n_cfn;
+  for (int f = 0; f < 4 && s == WQ_OK; ++f)
+    if (f < 3 || (fam_mask & WQ_FAM_LAP)) s = dalloc_n<double>(G[f], ng);
+  if (s == WQ_OK) s = dalloc_n<double>(gw, 16 * (size_t)P->ncell);
+  if (s == WQ_OK) {
+    k_gauss_basis<<<nblocks(16LL * P->ncell, BS), BS, 0, st>>>(
+        P->ncell, P->cell_face.as<int32_t>(), P->cell_sub.as<uint8_t>(), M->ext_ptr.as<int64_t>(),
+        M->coef_ptr.as<int64_t>(), M->coef.as<double>(), M->ctrl.as<double>(), P->cfn_ptr.as<int64_t>(),
+        P->cfn.as<int32_t>(), P->cfn_loc.as<uint8_t>(), G[0].as<double>(), G[1].as<double>(), G[2].as<double>(),
+        (fam_mask & WQ_FAM_LAP) ? G[3].as<double>() : nullptr, gw.as<double>());
+    if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
+  }
+  for (int f = 0; f < 4 && s == WQ_OK; ++f)
+    if (fam_mask & (1u << f)) s = dalloc_n<double>(w->rhs[f], P->nnz);
+  if (s == WQ_OK) {
+    const int rows_per_block = BS / GQ_GROUP;
+    const size_t lds = (size_t)rows_per_block * 4 * P->max_row * sizeof(double);
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)k_gauss_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+      s = WQ_EDEVICE;
+    if (s == WQ_OK) k_gauss_rows<<<nblocks(n, rows_per_block), BS, lds, st>>>(
+        n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(), P->cfn_ptr.as<int64_t>(), P->soff.as<int64_t>(),
+        P->slot.as<uint8_t>(), P->kself.as<uint8_t>(), P->row_ptr.as<int64_t>(), G[0].as<double>(),
+        G[1].as<double>(), G[2].as<double>(), G[3].as<double>(), gw.as<double>(), fam_mask, P->max_row,
+        w->rhs[0].as<double>(), w->rhs[1].as<double>(), w->rhs[2].as<double>(), w->rhs[3].as<double>());
+    if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
+  }
+  // systems by size class
+  DBuf small, lists, stats;
+  int64_t n_small = 0;
+  int mx[4] = {0, 0, 0, 0};
+  if (s == WQ_OK) s = dalloc_n<int64_t>(small, n + 1);
+  if (s == WQ_OK) s = dalloc(stats, 64);
+  if (s == WQ_OK && hipMemsetAsync(stats.p, 0, 64, st) != hipSuccess) s = WQ_EDEVICE;
+  if (s == WQ_OK && hipMemsetAsync(small.p, 0, (n + 1) * 8, st) != hipSuccess) s = WQ_EDEVICE;
+  if (s == WQ_OK) {
+    k_sys_class<<<nblocks(n, BS), BS, 0, st>>>(n, P->row_ptr.as<int64_t>(), P->qptr.as<int64_t>(),
+                                                small.as<int64_t>(), stats.as<int>());
+    if (hipMemcpyAsync(mx, stats.p, 4 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) s = WQ_EDEVICE;
+  }
+  DBuf pos;
+  if (s == WQ_OK) s = dalloc_n<int64_t>(pos, n + 1);
+  if (s == WQ_OK && hipMemcpyAsync(pos.p, small.p, (n + 1) * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    s = WQ_EDEVICE;
+  if (s == WQ_OK) s = exclusive_scan_i64(pos.as<int64_t>(), n + 1, &n_small, st);
+  if (s == WQ_OK) s = dalloc_n<int32_t>(lists, n);
+  if (s == WQ_OK) {
+    k_sys_lists<<<nblocks(n, BS), BS, 0, st>>>(n, small.as<int64_t>(), pos.as<int64_t>(), lists.as<int32_t>(),
+                                                lists.as<int32_t>() + n_small);
+    if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
+  }
+  // report accumulators: [0] fail, [1] max sweeps, [2..3] min kept bits, [4..5] max dropped, [6..7] truncated
+  struct Rep {
+    int fail, max_sweeps;
+    unsigned long long min_kept, max_dropped, truncated;
+  };
+  DBuf drep;
+  if (s == WQ_OK) s = dalloc(drep, sizeof(Rep));
+  if (s == WQ_OK) {
+    Rep init{0, 0, 0x7ff0000000000000ULL /* +inf */, 0ULL, 0ULL};
+    if (hipMemcpyAsync(drep.p, &init, sizeof(Rep), hipMemcpyHostToDevice, st) != hipSuccess) s = WQ_EDEVICE;
+  }
+  for (int f = 0; f < 4 && s == WQ_OK; ++f) {
+    if (!(fam_mask & (1u << f))) continue;
+    s = dalloc_n<double>(w->W[f], (size_t)(P->qidx.bytes / sizeof(int32_t)));
+    const double* D = f == 0 ? P->DN.as<double>() : f == 1 ? P->DX.as<double>() : f == 2 ? P->DY.as<double>()
+                                                                                        : P->DL.as<double>();
+    for (int cls = 0; cls < 2 && s == WQ_OK; ++cls) {
+      const int64_t ns = cls == 0 ? n_small : n - n_small;
+      if (ns == 0) continue;
+      const int mn = cls == 0 ? mx[0] : mx[2];
+      const int mr = cls == 0 ? mx[1] : mx[3];
+      int ld = mr + 1;
+      if (!(ld & 1)) ++ld;
+      const size_t lds = ((size_t)mn * ld + 2 * (size_t)mr + 3 * (size_t)mn) * sizeof(double) + mn * sizeof(int);
+      if (lds > 160 * 1024) {
+        set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
+                  ") does not fit in LDS");
+        s = WQ_EINVAL;
+        break;
+      }
+      Rep* R = drep.as<Rep>();
+      TsvdArgs ta;
+      ta.rows = lists.as<int32_t>() + (cls == 0 ? 0 : n_small);
+      ta.nsys = ns;
+      ta.ld = ld;
+      ta.fam = f;
+      ta.tau = tau;
+      ta.sptr = P->supp_ptr.as<int64_t>();
+      ta.scell = P->supp_cell.as<int32_t>();
+      ta.cfn_ptr = P->cfn_ptr.as<int64_t>();
+      ta.cell_pt_off = P->cell_pt_off.as<int64_t>();
+      ta.dptr = P->dptr.as<int64_t>();
+      ta.soff = P->soff.as<int64_t>();
+      ta.slot = P->slot.as<uint8_t>();
+      ta.kself = P->kself.as<uint8_t>();
+      ta.row_ptr = P->row_ptr.as<int64_t>();
+      ta.qptr = P->qptr.as<int64_t>();
+      ta.D = D;
+      ta.DN = P->DN.as<double>();
+      ta.rhs = w->rhs[f].as<double>();
+      ta.W = w->W[f].as<double>();
+      ta.max_sweeps = &R->max_sweeps;
+      ta.min_kept = &R->min_kept;
+      ta.max_dropped = &R->max_dropped;
+      ta.truncated = &R->truncated;
+      ta.fail = &R->fail;
+      if (lds > 64 * 1024) {
+        if (hipFuncSetAttribute((const void*)k_tsvd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess) {
+          s = WQ_EDEVICE;
+          break;
+        }
+      }
+      k_tsvd<<<(unsigned)ns, 64, lds, st>>>(ta);
+      if (hipGetLastError() != hipSuccess) {
+        set_error("solve_weights: TSVD launch failed");
+        s = WQ_EDEVICE;
+      }
+    }
+  }
+  Rep hrep{};
+  if (s == WQ_OK && hipMemcpyAsync(&hrep, drep.p, sizeof(Rep), hipMemcpyDeviceToHost, st) != hipSuccess)
+    s = WQ_EDEVICE;
+  if (s == WQ_OK && hipStreamSynchronize(st) != hipSuccess) s = WQ_EDEVICE;
+  for (int f = 0; f < 4; ++f) dfree(G[f]);
+  dfree(gw);
+  dfree(small);
+  dfree(lists);
+  dfree(stats);
+  dfree(pos);
+  dfree(drep);
+  if (s == WQ_OK && hrep.fail) {
+    set_error("solve_weights: a Jacobi SVD did not converge in 40 sweeps");
+    s = WQ_ESVD;
+  }
+  if (s != WQ_OK) {
+    release_weights(w);
+    delete w;
+    return s;
+  }
+  if (rep) {
+    int nf = 0;
+    for (int f = 0; f < 4; ++f) nf += (fam_mask >> f) & 1;
+    rep->systems = n * nf;
+    rep->truncated = (int64_t)hrep.truncated;
+    rep->max_sweeps = hrep.max_sweeps;
+    double v;
+    std::memcpy(&v, &hrep.min_kept, 8);
+    rep->min_kept_ratio = v;
+    std::memcpy(&v, &hrep.max_dropped, 8);
+    rep->max_dropped_ratio = v;
+  }
+  *out = w;
+  return WQ_OK;
+}
+
+extern "C" void wq_weights_destroy(wq_weights* w) {
+  if (!w) return;
+  release_weights(w);
+  delete w;
+}
+
+extern "C" wq_status wq_weights_get(const wq_weights* w, wq_family fam, double* dst, wq_stream stream) {
+  WQ_CHECK(w && dst, WQ_EINVAL, "wq_weights_get: null argument");
+  const int f = fam_index(fam);
+  WQ_CHECK(w->fam_mask & fam, WQ_EINVAL, "wq_weights_get: family not solved");
+  WQ_HIP(hipMemcpyAsync(dst, w->W[f].p, w->W[f].bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return WQ_OK;
+}
+
+extern "C" wq_status wq_rhs_get(const wq_weights* w, wq_family fam, double* dst, wq_stream stream) {
+  WQ_CHECK(w && dst, WQ_EINVAL, "wq_rhs_get: null argument");
+  const int f = fam_index(fam);
+  WQ_CHECK(w->fam_mask & fam, WQ_EINVAL, "wq_rhs_get: family not solved");
+  WQ_HIP(hipMemcpyAsync(dst, w->rhs[f].p, (size_t)w->pts->nnz * sizeof(double), hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return WQ_OK;
+}

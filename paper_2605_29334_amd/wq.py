@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libwq.so (C ABI declared in include/wq.h).
+
+Argument marshalling only: every step of the weighted-quadrature path runs in the HIP
+kernels of libwq.so. PyTorch supplies device memory (tensors) and streams. The library
+must have been built (paper_2605_29334_amd/build.py); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwq.so")
+
+WQ_FAM_MASS, WQ_FAM_DX, WQ_FAM_DY, WQ_FAM_LAP = 1, 2, 4, 8
+WQ_FP64, WQ_SPLIT_FP16, WQ_SPLIT_BF16 = 0, 1, 2
+ARR_ROW_PTR, ARR_COL, ARR_QPTR, ARR_QIDX, ARR_ETYPE, ARR_S, ARR_X, ARR_DETJ = range(8)
+_ARR_DTYPE = {ARR_ROW_PTR: torch.int64, ARR_COL: torch.int32, ARR_QPTR: torch.int64, ARR_QIDX: torch.int32,
+              ARR_ETYPE: torch.uint8, ARR_S: torch.uint8, ARR_X: torch.float64, ARR_DETJ: torch.float64}
+
+
+class WQError(RuntimeError):
+    def __init__(self, status, where):
+        lib = _lib()
+        super().__init__(f"{where}: {lib.wq_strerror(status).decode()} ({status}): {lib.wq_last_error().decode()}")
+        self.status = status
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("nf", C.c_int32), ("n_fn", C.c_int32),
+                ("face_vtx", C.c_void_p), ("split", C.c_void_p), ("ext_ptr", C.c_void_p),
+                ("ext_fn", C.c_void_p), ("coef_ptr", C.c_void_p), ("coef", C.c_void_p), ("ctrl", C.c_void_p)]
+
+
+class SolveReport(C.Structure):
+    _fields_ = [("systems", C.c_int64), ("truncated", C.c_int64), ("max_sweeps", C.c_int32),
+                ("min_kept_ratio", C.c_double), ("max_dropped_ratio", C.c_double)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2605_29334_amd/build.py")
+        lib = C.CDLL(LIB_PATH)
+        P, I64, I32, U, D = C.c_void_p, C.c_int64, C.c_int32, C.c_uint, C.c_double
+        sig = {
+            "wq_mesh_create": ([P, P], C.c_int),
+            "wq_mesh_destroy": ([P], None),
+            "build_points": ([P, C.c_int, P, P, P, P, P], C.c_int),
+            "build_points_with_s": ([P, P, C.c_int, P, P, P, P, P], C.c_int),
+            "wq_points_destroy": ([P], None),
+            "wq_points_size": ([P, C.c_int], I64),
+            "wq_points_get": ([P, C.c_int, P, P], C.c_int),
+            "solve_weights": ([P, P, U, D, P, P, P], C.c_int),
+            "wq_weights_destroy": ([P], None),
+            "wq_weights_get": ([P, C.c_int, P, P], C.c_int),
+            "wq_rhs_get": ([P, C.c_int, P, P], C.c_int),
+            "assemble_mass": ([P, P, P, P, C.c_int, P], C.c_int),
+            "assemble_stiffness": ([P, P, P, P, C.c_int, P], C.c_int),
+            "assemble_biharmonic": ([P, P, P, P, C.c_int, P], C.c_int),
+            "assemble_mass_stiffness": ([P, P, P, P, P, P, C.c_int, P], C.c_int),
+            "wq_strerror": ([C.c_int], C.c_char_p),
+            "wq_last_error": ([], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        del I32
+        _LIB = lib
+    return _LIB
+
+
+def exported_symbols():
+    """Names the C ABI declares (checked by the CPU tests against the built library)."""
+    return ["wq_mesh_create", "wq_mesh_destroy", "build_points", "build_points_with_s", "wq_points_destroy",
+            "wq_points_size", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
+            "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
+            "wq_strerror", "wq_last_error"]
+
+
+def _check(status, where):
+    if status != 0:
+        raise WQError(status, where)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """wq_mesh_create on a fixture dict (host arrays are copied to the current device)."""
+
+    def __init__(self, fx):
+        self._keep = {
+            "face_vtx": np.ascontiguousarray(fx["face_vtx"], dtype=np.int32),
+            "split": np.ascontiguousarray(fx["split"], dtype=np.uint8),
+            "ext_ptr": np.ascontiguousarray(fx["ext_ptr"], dtype=np.int64),
+            "ext_fn": np.ascontiguousarray(fx["ext_fn"], dtype=np.int32),
+            "coef_ptr": np.ascontiguousarray(fx["coef_ptr"], dtype=np.int64),
+            "coef": np.ascontiguousarray(fx["coef"], dtype=np.float64),
+            "ctrl": np.ascontiguousarray(fx["ctrl"], dtype=np.float64),
+        }
+        k = self._keep
+        d = MeshDesc(int(fx["nv"]), int(len(k["face_vtx"])), int(fx["n_fn"]),
+                     *[C.c_void_p(k[n].ctypes.data) for n in ("face_vtx", "split", "ext_ptr", "ext_fn",
+                                                              "coef_ptr", "coef", "ctrl")])
+        h = C.c_void_p()
+        _check(_lib().wq_mesh_create(C.byref(d), C.byref(h)), "wq_mesh_create")
+        self.h = h
+        self.nf = len(k["face_vtx"])
+        self.n_fn = int(fx["n_fn"])
+
+    def close(self):
+        if self.h:
+            _lib().wq_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Points:
+    """build_points: classification, points, pattern, point sets, basis at points."""
+
+    def __init__(self, mesh, want_laplacian=False, stream=None, s_init=None):
+        h = C.c_void_p()
+        n, nnz, npt = C.c_int64(), C.c_int64(), C.c_int64()
+        if s_init is None:
+            st = _lib().build_points(mesh.h, int(want_laplacian), _stream(stream), C.byref(h), C.byref(n),
+                                     C.byref(nnz), C.byref(npt))
+        else:
+            s_arr = np.ascontiguousarray(s_init, dtype=np.uint8)
+            st = _lib().build_points_with_s(mesh.h, C.c_void_p(s_arr.ctypes.data), int(want_laplacian),
+                                            _stream(stream), C.byref(h), C.byref(n), C.byref(nnz), C.byref(npt))
+        _check(st, "build_points")
+        self.h = h
+        self.mesh = mesh
+        self.n_rows, self.nnz, self.n_points = n.value, nnz.value, npt.value
+
+    def get(self, what, stream=None):
+        size = _lib().wq_points_size(self.h, what)
+        out = torch.empty(size, dtype=_ARR_DTYPE[what], device="cuda")
+        _check(_lib().wq_points_get(self.h, what, _ptr(out), _stream(stream)), "wq_points_get")
+        return out
+
+    def close(self):
+        if self.h:
+            _lib().wq_points_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Weights:
+    """solve_weights: Gauss right-hand sides + truncated-SVD weights per family."""
+
+    def __init__(self, mesh, points, fam_mask, tau=1e-12, stream=None):
+        h = C.c_void_p()
+        rep = SolveReport()
+        _check(_lib().solve_weights(mesh.h, points.h, int(fam_mask), float(tau), _stream(stream), C.byref(h),
+                                    C.byref(rep)), "solve_weights")
+        self.h = h
+        self.points = points
+        self.fam_mask = fam_mask
+        self.report = {k: getattr(rep, k) for k, _ in SolveReport._fields_}
+
+    def weights(self, fam, stream=None):
+        n = _lib().wq_points_size(self.points.h, ARR_QIDX)
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(_lib().wq_weights_get(self.h, fam, _ptr(out), _stream(stream)), "wq_weights_get")
+        return out
+
+    def rhs(self, fam, stream=None):
+        out = torch.empty(self.points.nnz, dtype=torch.float64, device="cuda")
+        _check(_lib().wq_rhs_get(self.h, fam, _ptr(out), _stream(stream)), "wq_rhs_get")
+        return out
+
+    def close(self):
+        if self.h:
+            _lib().wq_weights_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _out(points, out, prec):
+    dt = torch.float64 if prec == WQ_FP64 else torch.float32
+    if out is None:
+        out = torch.empty(points.nnz, dtype=dt, device="cuda")
+    assert out.dtype == dt and out.numel() == points.nnz and out.is_cuda and out.is_contiguous()
+    return out
+
+
+def _coef(points, c):
+    if c is None:
+        return None
+    assert c.dtype == torch.float64 and c.numel() == points.n_points and c.is_cuda and c.is_contiguous()
+    return c
+
+
+def assemble_mass(points, weights, coef=None, out=None, prec=WQ_FP64, stream=None):
+    out = _out(points, out, prec)
+    _check(_lib().assemble_mass(points.h, weights.h, _ptr(_coef(points, coef)), _ptr(out), prec, _stream(stream)),
+           "assemble_mass")
+    return out
+
+
+def assemble_stiffness(points, weights, coef=None, out=None, prec=WQ_FP64, stream=None):
+    out = _out(points, out, prec)
+    _check(_lib().assemble_stiffness(points.h, weights.h, _ptr(_coef(points, coef)), _ptr(out), prec,
+                                     _stream(stream)), "assemble_stiffness")
+    return out
+
+
+def assemble_biharmonic(points, weights, coef=None, out=None, prec=WQ_FP64, stream=None):
+    out = _out(points, out, prec)
+    _check(_lib().assemble_biharmonic(points.h, weights.h, _ptr(_coef(points, coef)), _ptr(out), prec,
+                                      _stream(stream)), "assemble_biharmonic")
+    return out
+
+
+def assemble_mass_stiffness(points, weights, c=None, k=None, mass_out=None, stiff_out=None, prec=WQ_FP64,
+                            stream=None):
+    mass_out = _out(points, mass_out, prec)
+    stiff_out = _out(points, stiff_out, prec)
+    _check(_lib().assemble_mass_stiffness(points.h, weights.h, _ptr(_coef(points, c)), _ptr(_coef(points, k)),
+                                          _ptr(mass_out), _ptr(stiff_out), prec, _stream(stream)),
+           "assemble_mass_stiffness")
+    return mass_out, stiff_out

@@ -1,0 +1,47 @@
+"""The C ABI library loads on any host and exports every entry point include/wq.h declares
+(no compute calls: those need a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2605_29334_amd", "libwq.so")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "wq.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        subprocess.run(["python", os.path.join(ROOT, "paper_2605_29334_amd", "build.py")], check=True)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("build_points", "solve_weights", "assemble_mass", "assemble_stiffness", "assemble_biharmonic",
+              "wq_mesh_create", "wq_strerror"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    import paper_2605_29334_amd.wq as W
+    assert set(W.exported_symbols()) <= set(declared_functions())
+
+
+def test_strerror_is_host_only(lib):
+    lib.wq_strerror.restype = ctypes.c_char_p
+    assert lib.wq_strerror(-3).startswith(b"ill-posed")
