@@ -1,0 +1,217 @@
+"""Benchmark: weighted-quadrature assembly of Poisson mass + stiffness on one MI355X.
+
+Workload (default): 256 x 256 control faces on [0,1]^2, ~1% of interior vertices
+replaced by EPs of valence 3/5/6 (seeded), smooth seeded displacement (amplitude 0.05),
+bicubic EP-enriched splines, TSVD cutoff 1e-12 relative, FP64.
+
+One step = the whole path on the resident mesh: build_points (classification, points,
+pattern, point sets, basis/geometry), solve_weights (Gauss right-hand sides + TSVD
+weights of the mass, x and y families) and the fused mass + stiffness assembly with
+variable coefficients c = 1 + sin(2 pi x) sin(2 pi y) / 2, k = 1 + cos(pi x) cos(pi y) / 2.
+The metric is assembled CSR nonzeros (M and K) per second of step time. The assembly
+alone (the repeated operation when the domain is fixed) is reported beside it.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
+
+
+def tsvd_flops(n, r):
+    """Algorithmic FLOPs of one weight system (n constraints, r points): Golub-Kahan
+    bidiagonalisation 4 r n^2 - 4 n^3 / 3 plus the QR of Z V_t, 2 r n^2 - 2 n^3 / 3
+    (t = n upper bound) -- a lower bound for any SVD-based solve."""
+    n = n.astype(np.float64)
+    r = r.astype(np.float64)
+    return 6.0 * r * n * n - 2.0 * n ** 3
+
+
+def make_fixture(N, density, seed):
+    import fixtures as fx
+    return fx.fixture_eps(N, density, (3, 5, 6), displace=0.05, seed=seed)
+
+
+def cpu_baseline(F, budget_s):
+    """The FP64 oracle on this host: the whole-mesh classification and point allocation
+    once, then the per-row path (points/basis of the row's cells, Gauss right-hand
+    sides, TSVD weights, mass + stiffness row) on seeded sampled rows until the time
+    budget is spent; extrapolated to all rows."""
+    import oracle as O
+    t0 = time.perf_counter()
+    cls = O.classify(F)
+    s = O.points_per_element(F, cls)
+    glob = {"cls": cls, "s": s, "cells": O.cells(F, s)}
+    t_glob = time.perf_counter() - t0
+    rng = np.random.default_rng(7)
+    order = rng.permutation(F["n_fn"])
+    coef = {"mass": lambda x: 1 + 0.5 * np.sin(2 * np.pi * x[:, 0]) * np.sin(2 * np.pi * x[:, 1]),
+            "stiffness": lambda x: 1 + 0.5 * np.cos(np.pi * x[:, 0]) * np.cos(np.pi * x[:, 1])}
+    done, nnz, t_rows = 0, 0, 0.0
+    while t_rows < budget_s and done < len(order):
+        batch = [int(i) for i in order[done:done + 20]]
+        t1 = time.perf_counter()
+        res, glob = O.sample_rows(F, batch, ("mass", "x", "y"), 1e-12, coef, glob)
+        t_rows += time.perf_counter() - t1
+        done += len(batch)
+        nnz += sum(2 * len(r["S"]) for r in res.values())
+    per_row = t_rows / done
+    total_s = t_glob + per_row * F["n_fn"]
+    total_nnz = nnz / done * F["n_fn"]
+    return {"value": total_nnz / total_s, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole-mesh classification + point allocation ({t_glob:.1f} s) and {done} seeded "
+                      f"rows of the per-row path ({t_rows:.1f} s), extrapolated to {F['n_fn']} rows; "
+                      f"one Python/NumPy thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=256)
+    ap.add_argument("--density", type=float, default=0.01)
+    ap.add_argument("--seed", type=int, default=2000)
+    ap.add_argument("--assembly-reps", type=int, default=30)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the assembly shards by rows without communication; see the design notes)", flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2605_29334_amd.wq as W
+
+    torch.cuda.set_device(0)
+    print(f"[bench] generating fixture N={args.N}", file=sys.stderr, flush=True)
+    F = make_fixture(args.N, args.density, args.seed)
+    mesh = W.Mesh(F)
+    stream = torch.cuda.current_stream()
+    mask = W.WQ_FAM_MASS | W.WQ_FAM_DX | W.WQ_FAM_DY
+
+    def step(coefs):
+        pts = W.Points(mesh, stream=stream)
+        wts = W.Weights(mesh, pts, mask, tau=1e-12, stream=stream)
+        c, k = coefs if coefs is not None else (None, None)
+        M, K = W.assemble_mass_stiffness(pts, wts, c, k, stream=stream)
+        return pts, wts, M, K
+
+    # coefficients (PDE data) at the points, resident in HBM before timing
+    pts0 = W.Points(mesh, stream=stream)
+    x = pts0.get(W.ARR_X).reshape(-1, 2)
+    c = (1 + 0.5 * torch.sin(2 * np.pi * x[:, 0]) * torch.sin(2 * np.pi * x[:, 1])).contiguous()
+    k = (1 + 0.5 * torch.cos(np.pi * x[:, 0]) * torch.cos(np.pi * x[:, 1])).contiguous()
+    row_ptr = pts0.get(W.ARR_ROW_PTR).cpu().numpy()
+    qptr = pts0.get(W.ARR_QPTR).cpu().numpy()
+    n_i, r_i = np.diff(row_ptr), np.diff(qptr)
+    nnz = int(row_ptr[-1])
+    n_points = pts0.n_points
+    sum_r = int(qptr[-1])
+    pts0.close()
+    del pts0
+
+    live = None
+    for _ in range(args.warmup):
+        live = step((c, k))
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+    live = None
+    W.timing_enable(True)
+    W.timings()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        live = None  # release the previous step's handles (device memory) inside the step
+        live = step((c, k))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    recs = W.timings()
+    W.timing_enable(False)
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    per_kernel = {}
+    for name, ms, work in recs:
+        e = per_kernel.setdefault(name, {"ms": 0.0, "launches": 0, "work": 0})
+        e["ms"] += ms
+        e["launches"] += 1
+        e["work"] += work
+    for e in per_kernel.values():
+        e["ms_per_step"] = e["ms"] / args.steps
+
+    # dominant kernel: the TSVD size classes (FP64 ALU); algorithmic FLOPs per launch
+    # TSVD size classes, as the library forms them (one launch per class and family)
+    cls0 = (n_i <= 64) & (r_i <= 64)
+    cls1 = (n_i <= 64) & (r_i > 64) & (r_i <= 256)
+    cls2 = ~(cls0 | cls1)
+    fl_cls = {"k_tsvd_r64": float(tsvd_flops(n_i[cls0], r_i[cls0]).sum()),
+              "k_tsvd_r256": float(tsvd_flops(n_i[cls1], r_i[cls1]).sum()),
+              "k_tsvd_n128": float(tsvd_flops(n_i[cls2], r_i[cls2]).sum())}
+    dom = max(per_kernel.items(), key=lambda kv: kv[1]["ms"])
+    dom_name = dom[0]
+    avg_ms = dom[1]["ms"] / dom[1]["launches"]
+    if dom_name.startswith("k_tsvd"):
+        flops_launch = fl_cls[dom_name]
+        achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+        roofline = {"kernel": dom_name, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                    "avg_launch_ms": avg_ms, "algorithmic_per_launch": flops_launch}
+    else:
+        roofline = {"kernel": dom_name, "bound": "unknown", "achieved": None, "peak": None, "unit": None,
+                    "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
+
+    # assembly only (weights and basis resident; caches flushed between repetitions)
+    pts, wts, M, K = live
+    flush = torch.empty(512 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+    times = []
+    for _ in range(args.assembly_reps):
+        flush.fill_(1.0)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        W.assemble_mass_stiffness(pts, wts, c, k, M, K, stream=stream)
+        ev1.record(stream)
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    a_ms = float(np.median(times))
+    asm_bytes = 8.0 * (6 * sum_r + 2 * n_points + 2 * nnz)
+    asm_gbs = asm_bytes / (a_ms * 1e-3) / 1e9
+    assembly = {"nnz_per_s": 2 * nnz / (a_ms * 1e-3), "median_ms": a_ms,
+                "roofline": {"kernel": "k_assemble_mass_stiffness", "bound": "hbm", "achieved": asm_gbs,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": asm_gbs / HBM_PEAK_GBS,
+                             "traffic": None, "algorithmic_bytes": asm_bytes}}
+
+    value = args.steps * 2 * nnz / elapsed
+    out = {
+        "metric": "assembled CSR nonzeros/sec, WQ plain vs mixed-prec at rel err ≤1e-6; p50/p99 latency",
+        "value": value, "unit": "nnz/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"Poisson mass+stiffness, FP64 plain WQ, {args.N}x{args.N} faces, "
+                               f"EP density {args.density} (valence 3/5/6), TSVD cutoff 1e-12",
+                   "n_rows": int(len(n_i)), "nnz_per_matrix": nnz, "n_points": int(n_points),
+                   "sum_r": sum_r, "weight_systems": int(3 * len(n_i)), "seed": args.seed},
+        "roofline": roofline,
+        "assembly_only": assembly,
+        "kernels_ms_per_step": {kname: round(e["ms_per_step"], 4) for kname, e in per_kernel.items()},
+        "tsvd_systems_per_family": {"r64": int(cls0.sum()), "r256": int(cls1.sum()), "n128": int(cls2.sum())},
+        "solve_report": wts.report,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(F, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -164,6 +164,21 @@ wq_status assemble_mass_stiffness(const wq_points* pts, const wq_weights* w, con
                                   const double* k_at_points, void* mass_vals, void* stiff_vals,
                                   wq_precision prec, wq_stream stream);
 
+/* ------------------------------------------------------------------ kernel timing
+ * Measurement aid. While enabled (per process), the library records a pair of HIP
+ * events on the launch stream around each of its main kernels (basis evaluation,
+ * Gauss basis, Gauss rows, TSVD per size class, assembly). wq_timings() waits for the
+ * recorded events, copies up to `cap` records into `out` (host) and clears the list;
+ * it returns the number of records written. `work` is the kernel's unit count (points,
+ * systems, rows). */
+typedef struct {
+  char name[40];
+  double ms;
+  int64_t work;
+} wq_timing;
+void wq_timing_enable(int on);
+int wq_timings(wq_timing* out, int cap);
+
 /* ------------------------------------------------------------------ errors */
 const char* wq_strerror(wq_status s);
 const char* wq_last_error(void);

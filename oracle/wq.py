@@ -480,3 +480,84 @@ def setup(fx, families=("mass", "x", "y"), tau=1e-12, rows=None):
     W, rank, resid = wq_weights(fx, pat, data, gq, families, tau, rows)
     return {"cls": cls, "s": s, "cells": cl, "pat": pat, "data": data, "gq": gq,
             "W": W, "rank": rank, "resid": resid}
+
+
+# ----------------------------------------------------------------------------------
+# Row-by-row evaluation for large meshes: the same steps, restricted to sampled rows
+# (every row's weights and matrix row depend only on the cells of its support).
+# ----------------------------------------------------------------------------------
+
+def row_gauss_rhs(fx, cl, supp_i, S_i, i, fam, cache):
+    """b^f_i[l] = integral of D N_i D N_{S_i[l]} by 4x4 Gauss on each cell of supp N_i."""
+    gp, gw = gauss4()
+    key = _FAM_KEY[fam]
+    pos = {int(j): l for l, j in enumerate(S_i)}
+    b = np.zeros(len(S_i))
+    for c in supp_i:
+        if c not in cache:
+            f, k = int(cl["elem"][c]), int(cl["sub"][c])
+            pts = []
+            for bq in range(4):
+                for aq in range(4):
+                    fn, N, Nx, Ny, Lap, x, dJ = eval_cell(fx, f, k, (gp[aq], gp[bq]), cl["funcs"][c])
+                    pts.append((gw[aq] * gw[bq] * abs(dJ), {"N": N, "Nx": Nx, "Ny": Ny, "Lap": Lap}))
+            cache[c] = (cl["funcs"][c], pts)
+        fn, pts = cache[c]
+        ki = int(np.nonzero(fn == i)[0][0])
+        for wq_, vals in pts:
+            v = vals[key]
+            for k, j in enumerate(fn):
+                b[pos[int(j)]] += wq_ * v[ki] * v[k]
+    return b
+
+
+def sample_rows(fx, rows, families=("mass", "x", "y"), tau=1e-12, coef=None, glob=None):
+    """Everything the method produces for the given rows: S_i, Q_i, weights per family,
+    and mass / stiffness rows (coef: dict kind -> callable of x, or None for 1).
+    glob: optional precomputed {"cls", "s", "cells"} of the whole mesh."""
+    if glob is None:
+        cls = classify(fx)
+        s = points_per_element(fx, cls)
+        glob = {"cls": cls, "s": s, "cells": cells(fx, s)}
+    cl = glob["cells"]
+    if "supp" not in glob:
+        glob["supp"] = supports(fx, cl)
+    supp = glob["supp"]
+    pat = {"S": {}, "supp": {}}
+    for i in rows:
+        cols = set()
+        for c in supp[i]:
+            cols.update(int(j) for j in cl["funcs"][c])
+        pat["S"][i] = np.array(sorted(cols), dtype=np.int64)
+        pat["supp"][i] = supp[i]
+    need = sorted({c for i in rows for c in supp[i]})
+    data = {}
+    for c in need:
+        f, k = int(cl["elem"][c]), int(cl["sub"][c])
+        rr = [eval_cell(fx, f, k, eta, cl["funcs"][c]) for eta in cl["eta"][c]]
+        data[c] = {"fn": cl["funcs"][c], "N": np.array([r[1] for r in rr]), "Nx": np.array([r[2] for r in rr]),
+                   "Ny": np.array([r[3] for r in rr]), "Lap": np.array([r[4] for r in rr]),
+                   "x": np.array([r[5] for r in rr]), "detJ": np.array([r[6] for r in rr])}
+    gcache = {}
+    out = {}
+    for i in rows:
+        S_i = pat["S"][i]
+        z = z_diag(fx, pat, data, i)
+        x = np.concatenate([data[c]["x"] for c in supp[i]])
+        q = np.concatenate([np.arange(cl["pt_off"][c], cl["pt_off"][c + 1]) for c in supp[i]])
+        res = {"S": S_i, "Q": q, "W": {}}
+        for fam in families:
+            A = local_matrix(fx, pat, data, i, _FAM_KEY[fam])
+            b = row_gauss_rhs(fx, cl, supp[i], S_i, i, fam, gcache)
+            w, t, _ = tsvd_solve(A, z, b, tau)
+            res["W"][fam] = w
+            res["b_" + fam] = b
+        cm = np.ones(len(q)) if coef is None or "mass" not in coef else coef["mass"](x)
+        ck = np.ones(len(q)) if coef is None or "stiffness" not in coef else coef["stiffness"](x)
+        if "mass" in families:
+            res["M"] = local_matrix(fx, pat, data, i, "N") @ (cm * res["W"]["mass"])
+        if "x" in families and "y" in families:
+            res["K"] = (local_matrix(fx, pat, data, i, "Nx") @ (ck * res["W"]["x"])
+                        + local_matrix(fx, pat, data, i, "Ny") @ (ck * res["W"]["y"]))
+        out[i] = res
+    return out, glob

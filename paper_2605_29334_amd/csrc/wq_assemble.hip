@@ -91,11 +91,15 @@ wq_status launch(const wq_points* P, const wq_weights* w, const double* c0, cons
     W0 = w->W[3].as<double>();
     D0 = P->DL.as<double>();
   }
+  static const char* names[4] = {"k_assemble_mass", "k_assemble_stiffness", "k_assemble_biharmonic",
+                                  "k_assemble_mass_stiffness"};
+  KTimer tm(names[K], P->n_rows, st);
   k_assemble<K><<<nblocks(P->n_rows, BS / GROUP), BS, lds, st>>>(
       P->n_rows, P->max_row, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(), P->cfn_ptr.as<int64_t>(),
       P->cell_pt_off.as<int64_t>(), P->dptr.as<int64_t>(), P->soff.as<int64_t>(), P->slot.as<uint8_t>(),
       P->row_ptr.as<int64_t>(), P->qptr.as<int64_t>(), W0, W1, W2, D0, P->DX.as<double>(), P->DY.as<double>(), c0,
       c1, o0, o1);
+  tm.stop();
   WQ_HIP(hipGetLastError());
   return WQ_OK;
 }

@@ -111,9 +111,55 @@ wq_status exclusive_scan_i64(int64_t* d, int64_t n, int64_t* total, hipStream_t 
   return WQ_OK;
 }
 
+// ------------------------------------------------------------------ kernel timing
+static bool g_timing = false;
+struct TRec {
+  std::string name;
+  hipEvent_t a, b;
+  int64_t work;
+};
+static std::vector<TRec> g_trecs;
+
+KTimer::KTimer(const char* n, int64_t w, hipStream_t s) : st(s), name(n), work(w) {
+  if (!g_timing) return;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    a = b = nullptr;
+    return;
+  }
+  (void)hipEventRecord(a, st);
+}
+
+void KTimer::stop() {
+  if (!a) return;
+  (void)hipEventRecord(b, st);
+  g_trecs.push_back({name, a, b, work});
+  a = b = nullptr;
+}
+
 }  // namespace wq
 
 using namespace wq;
+
+extern "C" void wq_timing_enable(int on) { g_timing = on != 0; }
+
+extern "C" int wq_timings(wq_timing* out, int cap) {
+  int n = 0;
+  for (auto& r : g_trecs) {
+    float ms = -1.0f;
+    if (hipEventSynchronize(r.b) == hipSuccess) (void)hipEventElapsedTime(&ms, r.a, r.b);
+    if (out && n < cap) {
+      std::memset(out[n].name, 0, sizeof(out[n].name));
+      std::strncpy(out[n].name, r.name.c_str(), sizeof(out[n].name) - 1);
+      out[n].ms = ms;
+      out[n].work = r.work;
+      ++n;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_trecs.clear();
+  return n;
+}
 
 // ------------------------------------------------------------------ errors (C ABI)
 extern "C" const char* wq_strerror(wq_status s) {

@@ -125,6 +125,16 @@ __device__ inline void bern3(double t, double b[4], double d[4], double s[4]) {
 // index n-1, i.e. the sum of the first n-1 inputs (callers scan count+1 entries).
 wq_status exclusive_scan_i64(int64_t* d, int64_t n, int64_t* total, hipStream_t st);
 
+// kernel timing (wq_timing_enable): records events around a launch when enabled
+struct KTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t st = nullptr;
+  const char* name = nullptr;
+  int64_t work = 0;
+  KTimer(const char* n, int64_t w, hipStream_t s);
+  void stop();
+};
+
 // 64-bit index launch helper
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 

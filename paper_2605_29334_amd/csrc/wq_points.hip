@@ -749,6 +749,7 @@ wq_status build_points_impl(wq_mesh* M, int want_lap, const uint8_t* s_host, hip
     if (s == WQ_OK && want_lap) s = dalloc_n<double>(P->DL, P->n_basis);
     if (s == WQ_OK && hipMemsetAsync(flags.p, 0, 8 * sizeof(int), st) != hipSuccess) s = WQ_EDEVICE;
     if (s == WQ_OK) {
+      KTimer tm("k_basis", P->n_points, st);
       k_basis<<<nblocks(P->n_points, BS), BS, 0, st>>>(
           P->n_points, P->ncell, P->cell_pt_off.as<int64_t>(), P->cell_face.as<int32_t>(), P->cell_sub.as<uint8_t>(),
           P->s.as<uint8_t>(), M->split.as<uint8_t>(), M->ext_ptr.as<int64_t>(), M->coef_ptr.as<int64_t>(),
@@ -756,6 +757,7 @@ wq_status build_points_impl(wq_mesh* M, int want_lap, const uint8_t* s_host, hip
           P->cfn_loc.as<uint8_t>(), P->dptr.as<int64_t>(), P->x.as<double>(), P->detJ.as<double>(),
           P->DN.as<double>(), P->DX.as<double>(), P->DY.as<double>(), want_lap ? P->DL.as<double>() : nullptr,
           flags.as<int>());
+      tm.stop();
       if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
     }
     if (s == WQ_OK) s = sync_flags(flags, hf, 1, st);

@@ -151,27 +151,41 @@ struct SysClass {
   int max_n, max_r;
 };
 
-__global__ void k_sys_class(int64_t n, const int64_t* row_ptr, const int64_t* qptr, int64_t* small, int* mx) {
+// Size buckets of the weight systems: LDS is sized per bucket, so typical systems are
+// not charged for the largest one. n bounds x r bounds.
+__constant__ int c_nb[5] = {32, 48, 64, 96, 128};
+__constant__ int c_rb[7] = {64, 80, 96, 128, 160, 192, 256};
+constexpr int NB_N = 5, NB_R = 7, NBKT = NB_N * NB_R;
+static const int h_nb[5] = {32, 48, 64, 96, 128};
+static const int h_rb[7] = {64, 80, 96, 128, 160, 192, 256};
+
+__global__ void k_sys_bucket(int64_t n, const int64_t* row_ptr, const int64_t* qptr, uint8_t* bkt, int* hist,
+                             int* bad) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int ni = (int)(row_ptr[i + 1] - row_ptr[i]);
   const int ri = (int)(qptr[i + 1] - qptr[i]);
-  const bool sm = (ni <= 64 && ri <= 64);
-  small[i] = sm ? 1 : 0;
-  if (sm) {
-    atomicMax(&mx[0], ni);
-    atomicMax(&mx[1], ri);
-  } else {
-    atomicMax(&mx[2], ni);
-    atomicMax(&mx[3], ri);
+  int bn = 0, br = 0;
+  while (bn < NB_N && ni > c_nb[bn]) ++bn;
+  while (br < NB_R && ri > c_rb[br]) ++br;
+  if (bn == NB_N || br == NB_R) {
+    atomicOr(bad, 1);
+    bn = NB_N - 1;
+    br = NB_R - 1;
   }
+  const int b = bn * NB_R + br;
+  bkt[i] = (uint8_t)b;
+  atomicAdd(&hist[b], 1);
+  atomicMax(&hist[2 * (NBKT + 1) + 2 * b], ni);  // per-bucket maxima (LDS sizing)
+  atomicMax(&hist[2 * (NBKT + 1) + 2 * b + 1], ri);
 }
 
-__global__ void k_sys_lists(int64_t n, const int64_t* small, const int64_t* pos, int32_t* list0, int32_t* list1) {
+__global__ void k_sys_scatter(int64_t n, const uint8_t* bkt, const int64_t* start, int* cur, int32_t* lists) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (small[i]) list0[pos[i]] = (int32_t)i;
-  else list1[i - pos[i]] = (int32_t)i;
+  const int b = bkt[i];
+  const int k = atomicAdd(&cur[b], 1);
+  lists[start[b] + k] = (int32_t)i;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -209,30 +223,56 @@ struct TsvdArgs {
   int* fail;
 };
 
-// One wavefront per (row, family) system. LDS: G (n columns of length ld: the r point
-// values of column l = A[l, :]^T, followed by b_l), z (r), and work vectors.
-// Steps: gather A and b; one-sided Jacobi (Hestenes) on A^T, rotating b along, so that
-// the final columns are V S and the rotated b is U^T b; keep sigma_l > tau sigma_max;
-// c = S_t^{-1} U_t^T b; x_l = Z v_l; CGS2 QR of the kept x_l with the forward
-// substitution y = R^{-T} c carried along; w = Z Q y.
-__global__ void __launch_bounds__(64) k_tsvd(TsvdArgs a) {
+// One 256-thread block per (row, family) system. LDS: G (n columns of length ld: the r
+// point values of column l = A[l, :]^T, followed by b_l), z (r), work vectors.
+// Steps: gather A and b; one-sided Jacobi (Hestenes) on A^T with round-robin pairing,
+// rotating b along, so that the final columns are V S and the rotated b is U^T b; keep
+// sigma_l > tau sigma_max; c = S_t^{-1} U_t^T b; x_l = Z v_l; CGS2 QR of the kept x_l
+// with the forward substitution y = R^{-T} c carried along; w = Z Q y.
+// LPP lanes share a column pair; each holds EPL elements of both columns in registers.
+constexpr int TB = 256;
+
+__device__ inline double block_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < TB / 64; ++k) s += red[k];
+  return s;
+}
+
+__device__ inline double block_max(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < TB / 64; ++k) s = fmax(s, red[k]);
+  return s;
+}
+
+template <int LPP, int EPL>
+__global__ void __launch_bounds__(TB) k_tsvd(TsvdArgs a) {
   extern __shared__ double sh[];
   const int64_t sys = blockIdx.x;
-  if (sys >= a.nsys) return;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
   const int64_t i = a.rows[sys];
   const int n = (int)(a.row_ptr[i + 1] - a.row_ptr[i]);
   const int r = (int)(a.qptr[i + 1] - a.qptr[i]);
   const int ld = a.ld;
-  double* Gm = sh;                       // n * ld
-  double* z = Gm + (size_t)n * ld;       // r
-  double* wacc = z + r;                  // r
-  double* sig = wacc + r;                // n
-  double* Rk = sig + n;                  // n (column k of R)
-  double* yv = Rk + n;                   // n
-  int* keep = (int*)(yv + n);            // n
+  double* Gm = sh;                  // n * ld
+  double* z = Gm + (size_t)n * ld;  // r
+  double* wacc = z + r;             // r
+  double* sig = wacc + r;           // n
+  double* Rk = sig + n;             // n
+  double* yv = Rk + n;              // n
+  double* red = yv + n;             // 8
+  int* keep = (int*)(red + 8);      // n + 1
   // 1. gather
-  for (int t = lane; t < n * ld; t += 64) Gm[t] = 0.0;
+  for (int t = tid; t < n * ld; t += TB) Gm[t] = 0.0;
   __syncthreads();
   {
     int moff = 0;
@@ -244,22 +284,29 @@ __global__ void __launch_bounds__(64) k_tsvd(TsvdArgs a) {
       const double* Nc = a.DN + a.dptr[c];
       const uint8_t* sl = a.slot + a.soff[p];
       const int ks = a.kself[p];
-      for (int t = lane; t < np * m; t += 64) {
-        const int q = t / m, k = t % m;
+      for (int t = tid; t < np * m; t += TB) {
+        const int q = t / m, k = t - q * m;
         Gm[(size_t)sl[k] * ld + moff + q] = Dc[t];
       }
-      for (int q = lane; q < np; q += 64) z[moff + q] = Nc[q * m + ks];
+      for (int q = tid; q < np; q += TB) z[moff + q] = Nc[q * m + ks];
       moff += np;
     }
-    for (int l = lane; l < n; l += 64) Gm[(size_t)l * ld + r] = a.rhs[a.row_ptr[i] + l];
+    for (int l = tid; l < n; l += TB) Gm[(size_t)l * ld + r] = a.rhs[a.row_ptr[i] + l];
   }
   __syncthreads();
-  // 2. one-sided Jacobi, round-robin (circle) ordering, LPP lanes per pair
+  // ||A||_F^2: columns below 1e-15 ||A||_F are numerical null space (dropped with a
+  // 1000x margin by the 1e-12 cutoff); pairs involving them need no rotation
+  double fro2 = 0.0;
+  for (int e = tid; e < n * r; e += TB) {
+    const int l = e / r, m = e - l * r;
+    const double g = Gm[(size_t)l * ld + m];
+    fro2 += g * g;
+  }
+  const double negl = 1e-30 * block_sum(fro2, red);
+  // 2. one-sided Jacobi, circle-method ordering
   const int nn = n + (n & 1);
   const int npair = nn / 2;
-  int lpp = 1;
-  while (lpp * 2 * npair <= 64 && lpp < 8) lpp *= 2;
-  const int pk = lane / lpp, sub = lane % lpp;
+  const int pk = tid / LPP, sub = tid % LPP;
   int sweeps = 0;
   bool converged = false;
   for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
@@ -272,27 +319,44 @@ __global__ void __launch_bounds__(64) k_tsvd(TsvdArgs a) {
         if (P < n && Q < n) {
           double* gp = Gm + (size_t)P * ld;
           double* gq = Gm + (size_t)Q * ld;
-          double al = 0, be = 0, ga = 0;
-          for (int m = sub; m < r; m += lpp) {
-            const double u = gp[m], v = gq[m];
-            al += u * u;
-            be += v * v;
-            ga += u * v;
+          double u[EPL], v[EPL];
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            const int m = sub + e * LPP;
+            u[e] = (m < r) ? gp[m] : 0.0;
+            v[e] = (m < r) ? gq[m] : 0.0;
           }
-          for (int off = 1; off < lpp; off <<= 1) {
+          double al = 0, be = 0, ga = 0;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            al += u[e] * u[e];
+            be += v[e] * v[e];
+            ga += u[e] * v[e];
+          }
+#pragma unroll
+          for (int off = 1; off < LPP; off <<= 1) {
             al += __shfl_xor(al, off, 64);
             be += __shfl_xor(be, off, 64);
             ga += __shfl_xor(ga, off, 64);
           }
-          if (fabs(ga) > 1e-15 * sqrt(al * be) && al * be > 0.0) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double cs = 1.0 / sqrt(1.0 + t * t);
+          if (ga * ga > 1e-30 * al * be && fmin(al, be) > negl) {
+            // tan of the rotation angle: t = 2 g sgn(b - a) / (|b - a| + sqrt((b - a)^2 + 4 g^2))
+            const double dba = be - al;
+            const double t = (dba >= 0 ? 2.0 * ga : -2.0 * ga) / (fabs(dba) + sqrt(dba * dba + 4.0 * ga * ga));
+            const double cs = rsqrt(1.0 + t * t);
             const double sn = cs * t;
-            for (int m = sub; m <= r; m += lpp) {
-              const double u = gp[m], v = gq[m];
-              gp[m] = cs * u - sn * v;
-              gq[m] = sn * u + cs * v;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) {
+              const int m = sub + e * LPP;
+              if (m < r) {
+                gp[m] = cs * u[e] - sn * v[e];
+                gq[m] = sn * u[e] + cs * v[e];
+              }
+            }
+            if (sub == 0) {  // the right-hand side row rotates along
+              const double bu = gp[r], bv = gq[r];
+              gp[r] = cs * bu - sn * bv;
+              gq[r] = sn * bu + cs * bv;
             }
             rotated = 1;
           }
@@ -300,22 +364,21 @@ __global__ void __launch_bounds__(64) k_tsvd(TsvdArgs a) {
       }
       __syncthreads();
     }
-    converged = !__any(rotated);
+    converged = !__syncthreads_or(rotated);
   }
-  if (!converged) atomicOr(a.fail, 1);
-  if (lane == 0) atomicMax(a.max_sweeps, sweeps);
+  if (!converged && tid == 0) atomicOr(a.fail, 1);
+  if (tid == 0) atomicMax(a.max_sweeps, sweeps);
   // 3. singular values and truncation
   double smax = 0.0;
-  for (int l = lane; l < n; l += 64) {
+  for (int l = tid; l < n; l += TB) {
     const double* g = Gm + (size_t)l * ld;
     double s2 = 0.0;
     for (int m = 0; m < r; ++m) s2 += g[m] * g[m];
     sig[l] = sqrt(s2);
     smax = fmax(smax, sig[l]);
   }
-  for (int off = 32; off > 0; off >>= 1) smax = fmax(smax, __shfl_xor(smax, off, 64));
-  __syncthreads();
-  if (lane == 0) {
+  smax = block_max(smax, red);
+  if (tid == 0) {
     int t = 0;
     double kmin = INFINITY, dmax = 0.0;
     for (int l = 0; l < n; ++l) {
@@ -326,71 +389,72 @@ __global__ void __launch_bounds__(64) k_tsvd(TsvdArgs a) {
         dmax = fmax(dmax, sig[l] / smax);
       }
     }
-    yv[0] = (double)t;          // stash t
+    keep[n] = t;
     atomicMin(a.min_kept, dbits(kmin));
     atomicMax(a.max_dropped, dbits(dmax));
     if (t < n) atomicAdd(a.truncated, 1ULL);
   }
   __syncthreads();
-  const int t = (int)yv[0];
-  __syncthreads();
-  // 4. c_l = (U^T b)_l / sigma_l stored in sig[]; x_l = Z v_l = z * g_l / sigma_l
-  for (int k = 0; k < t; ++k) {
+  const int t = keep[n];
+  // 4. c_k = (U^T b)_l / sigma_l (into yv), x_l = Z v_l = z * g_l / sigma_l
+  for (int k = tid; k < t; k += TB) {
     const int l = keep[k];
-    double* g = Gm + (size_t)l * ld;
-    const double inv = 1.0 / sig[l];
-    for (int m = lane; m < r; m += 64) g[m] = z[m] * g[m] * inv;
+    yv[k] = Gm[(size_t)l * ld + r] / sig[l];
   }
-  __syncthreads();
-  if (lane == 0) {
-    for (int k = 0; k < t; ++k) {
-      const int l = keep[k];
-      Rk[k] = Gm[(size_t)l * ld + r] / sig[l];  // c_k (temporarily in Rk)
-    }
-    for (int k = 0; k < t; ++k) yv[k] = Rk[k];
+  for (int e = tid; e < t * r; e += TB) {
+    const int k = e / r, m = e - k * r;
+    const int l = keep[k];
+    Gm[(size_t)l * ld + m] = z[m] * Gm[(size_t)l * ld + m] / sig[l];
   }
-  for (int m = lane; m < r; m += 64) wacc[m] = 0.0;
+  for (int m = tid; m < r; m += TB) wacc[m] = 0.0;
   __syncthreads();
   // 5. CGS2 on the kept columns; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk; w += y_k q_k
+  constexpr int DL = 4;  // lanes per dot product
   for (int k = 0; k < t; ++k) {
     double* x = Gm + (size_t)keep[k] * ld;
-    for (int j = lane; j < k; j += 64) Rk[j] = 0.0;
+    for (int j = tid; j < k; j += TB) Rk[j] = 0.0;
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
-      for (int j = lane; j < k; j += 64) {
-        const double* qj = Gm + (size_t)keep[j] * ld;
+      for (int jb = 0; jb < k; jb += TB / DL) {
+        const int j = jb + tid / DL, s4 = tid % DL;
         double d = 0.0;
-        for (int m = 0; m < r; ++m) d += qj[m] * x[m];
-        Rk[j] += d;
-        sig[j] = d;  // this pass's coefficients (sig[] no longer needed for j < k)
+        if (j < k) {
+          const double* qj = Gm + (size_t)keep[j] * ld;
+          for (int m = s4; m < r; m += DL) d += qj[m] * x[m];
+        }
+        for (int off = 1; off < DL; off <<= 1) d += __shfl_xor(d, off, 64);
+        if (j < k && s4 == 0) {
+          Rk[j] += d;
+          sig[j] = d;  // this pass's coefficients (sig is free for j < k)
+        }
       }
       __syncthreads();
-      for (int m = lane; m < r; m += 64) {
+      for (int m = tid; m < r; m += TB) {
         double v = x[m];
         for (int j = 0; j < k; ++j) v -= Gm[(size_t)keep[j] * ld + m] * sig[j];
         x[m] = v;
       }
       __syncthreads();
     }
-    double nrm = 0.0;
-    for (int m = lane; m < r; m += 64) nrm += x[m] * x[m];
-    nrm = sqrt(wave_sum(nrm));
+    double nn2 = 0.0;
+    for (int m = tid; m < r; m += TB) nn2 += x[m] * x[m];
+    const double nrm = sqrt(block_sum(nn2, red));
     double acc = 0.0;
-    for (int j = lane; j < k; j += 64) acc += Rk[j] * yv[j];
-    acc = wave_sum(acc);
+    for (int j = tid; j < k; j += TB) acc += Rk[j] * yv[j];
+    acc = block_sum(acc, red);
     const double yk = (yv[k] - acc) / nrm;  // yv[k] still holds c_k
     __syncthreads();
     const double inv = 1.0 / nrm;
-    for (int m = lane; m < r; m += 64) {
+    for (int m = tid; m < r; m += TB) {
       const double qm = x[m] * inv;
       x[m] = qm;
       wacc[m] += qm * yk;
     }
-    if (lane == 0) yv[k] = yk;
+    if (tid == 0) yv[k] = yk;
     __syncthreads();
   }
   double* W = a.W + a.qptr[i];
-  for (int m = lane; m < r; m += 64) W[m] = z[m] * wacc[m];
+  for (int m = tid; m < r; m += TB) W[m] = z[m] * wacc[m];
 }
 
 void release_weights(wq_weights* w) {
@@ -422,11 +486,13 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     if (f < 3 || (fam_mask & WQ_FAM_LAP)) s = dalloc_n<double>(G[f], ng);
   if (s == WQ_OK) s = dalloc_n<double>(gw, 16 * (size_t)P->ncell);
   if (s == WQ_OK) {
+    KTimer tm("k_gauss_basis", 16LL * P->ncell, st);
     k_gauss_basis<<<nblocks(16LL * P->ncell, BS), BS, 0, st>>>(
         P->ncell, P->cell_face.as<int32_t>(), P->cell_sub.as<uint8_t>(), M->ext_ptr.as<int64_t>(),
         M->coef_ptr.as<int64_t>(), M->coef.as<double>(), M->ctrl.as<double>(), P->cfn_ptr.as<int64_t>(),
         P->cfn.as<int32_t>(), P->cfn_loc.as<uint8_t>(), G[0].as<double>(), G[1].as<double>(), G[2].as<double>(),
         (fam_mask & WQ_FAM_LAP) ? G[3].as<double>() : nullptr, gw.as<double>());
+    tm.stop();
     if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
   }
   for (int f = 0; f < 4 && s == WQ_OK; ++f)
@@ -438,38 +504,48 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
         hipFuncSetAttribute((const void*)k_gauss_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
             hipSuccess)
       s = WQ_EDEVICE;
+    KTimer tm("k_gauss_rows", n, st);
     if (s == WQ_OK) k_gauss_rows<<<nblocks(n, rows_per_block), BS, lds, st>>>(
         n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(), P->cfn_ptr.as<int64_t>(), P->soff.as<int64_t>(),
         P->slot.as<uint8_t>(), P->kself.as<uint8_t>(), P->row_ptr.as<int64_t>(), G[0].as<double>(),
         G[1].as<double>(), G[2].as<double>(), G[3].as<double>(), gw.as<double>(), fam_mask, P->max_row,
         w->rhs[0].as<double>(), w->rhs[1].as<double>(), w->rhs[2].as<double>(), w->rhs[3].as<double>());
+    tm.stop();
     if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
   }
-  // systems by size class
-  DBuf small, lists, stats;
-  int64_t n_small = 0;
-  int mx[4] = {0, 0, 0, 0};
-  if (s == WQ_OK) s = dalloc_n<int64_t>(small, n + 1);
-  if (s == WQ_OK) s = dalloc(stats, 64);
-  if (s == WQ_OK && hipMemsetAsync(stats.p, 0, 64, st) != hipSuccess) s = WQ_EDEVICE;
-  if (s == WQ_OK && hipMemsetAsync(small.p, 0, (n + 1) * 8, st) != hipSuccess) s = WQ_EDEVICE;
+  // systems by size bucket (order inside a bucket is irrelevant: systems are independent)
+  DBuf bkt, lists, stats, dstart;
+  int hist[4 * (NBKT + 1)];
+  int64_t start[NBKT + 1];
+  if (s == WQ_OK) s = dalloc_n<uint8_t>(bkt, n);
+  if (s == WQ_OK) s = dalloc(stats, 4 * (NBKT + 1) * sizeof(int));
+  if (s == WQ_OK) s = dalloc_n<int64_t>(dstart, NBKT + 1);
+  if (s == WQ_OK && hipMemsetAsync(stats.p, 0, 4 * (NBKT + 1) * sizeof(int), st) != hipSuccess) s = WQ_EDEVICE;
   if (s == WQ_OK) {
-    k_sys_class<<<nblocks(n, BS), BS, 0, st>>>(n, P->row_ptr.as<int64_t>(), P->qptr.as<int64_t>(),
-                                                small.as<int64_t>(), stats.as<int>());
-    if (hipMemcpyAsync(mx, stats.p, 4 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess) s = WQ_EDEVICE;
+    k_sys_bucket<<<nblocks(n, BS), BS, 0, st>>>(n, P->row_ptr.as<int64_t>(), P->qptr.as<int64_t>(),
+                                                 bkt.as<uint8_t>(), stats.as<int>(), stats.as<int>() + NBKT);
+    if (hipMemcpyAsync(hist, stats.p, 4 * (NBKT + 1) * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      s = WQ_EDEVICE;
   }
-  DBuf pos;
-  if (s == WQ_OK) s = dalloc_n<int64_t>(pos, n + 1);
-  if (s == WQ_OK && hipMemcpyAsync(pos.p, small.p, (n + 1) * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+  if (s == WQ_OK && hist[NBKT]) {
+    set_error("solve_weights: a weight system exceeds n = 128 constraints or r = 256 points");
+    s = WQ_EINVAL;
+  }
+  if (s == WQ_OK) {
+    start[0] = 0;
+    for (int b = 0; b < NBKT; ++b) start[b + 1] = start[b] + hist[b];
+    s = dalloc_n<int32_t>(lists, n);
+  }
+  if (s == WQ_OK && hipMemcpyAsync(dstart.p, start, (NBKT + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st) !=
+                        hipSuccess)
     s = WQ_EDEVICE;
-  if (s == WQ_OK) s = exclusive_scan_i64(pos.as<int64_t>(), n + 1, &n_small, st);
-  if (s == WQ_OK) s = dalloc_n<int32_t>(lists, n);
   if (s == WQ_OK) {
-    k_sys_lists<<<nblocks(n, BS), BS, 0, st>>>(n, small.as<int64_t>(), pos.as<int64_t>(), lists.as<int32_t>(),
-                                                lists.as<int32_t>() + n_small);
+    k_sys_scatter<<<nblocks(n, BS), BS, 0, st>>>(n, bkt.as<uint8_t>(), dstart.as<int64_t>(),
+                                                  stats.as<int>() + NBKT + 1, lists.as<int32_t>());
     if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
   }
-  // report accumulators: [0] fail, [1] max sweeps, [2..3] min kept bits, [4..5] max dropped, [6..7] truncated
+  // report accumulators
   struct Rep {
     int fail, max_sweeps;
     unsigned long long min_kept, max_dropped, truncated;
@@ -485,14 +561,19 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     s = dalloc_n<double>(w->W[f], (size_t)(P->qidx.bytes / sizeof(int32_t)));
     const double* D = f == 0 ? P->DN.as<double>() : f == 1 ? P->DX.as<double>() : f == 2 ? P->DY.as<double>()
                                                                                         : P->DL.as<double>();
-    for (int cls = 0; cls < 2 && s == WQ_OK; ++cls) {
-      const int64_t ns = cls == 0 ? n_small : n - n_small;
+    for (int b = 0; b < NBKT && s == WQ_OK; ++b) {
+      const int64_t ns = hist[b];
       if (ns == 0) continue;
-      const int mn = cls == 0 ? mx[0] : mx[2];
-      const int mr = cls == 0 ? mx[1] : mx[3];
-      int ld = mr + 1;
-      if (!(ld & 1)) ++ld;
-      const size_t lds = ((size_t)mn * ld + 2 * (size_t)mr + 3 * (size_t)mn) * sizeof(double) + mn * sizeof(int);
+      const int mn = hist[2 * (NBKT + 1) + 2 * b];      // largest n in the bucket
+      const int mr = hist[2 * (NBKT + 1) + 2 * b + 1];  // largest r in the bucket
+      // column stride = 8 (mod 32) doubles: consecutive columns start 16 banks apart
+      int ld = ((mr + 1 + 23) / 32) * 32 + 8;
+      if (ld < mr + 1) ld += 32;
+      auto lds_of = [&](int l) {
+        return ((size_t)mn * l + 2 * (size_t)mr + 3 * (size_t)mn + 8) * sizeof(double) + (mn + 1) * sizeof(int);
+      };
+      if (lds_of(ld) > 160 * 1024) ld = (mr + 1) | 1;  // largest systems: minimal odd stride
+      const size_t lds = lds_of(ld);
       if (lds > 160 * 1024) {
         set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
                   ") does not fit in LDS");
@@ -501,7 +582,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       }
       Rep* R = drep.as<Rep>();
       TsvdArgs ta;
-      ta.rows = lists.as<int32_t>() + (cls == 0 ? 0 : n_small);
+      ta.rows = lists.as<int32_t>() + start[b];
       ta.nsys = ns;
       ta.ld = ld;
       ta.fam = f;
@@ -525,18 +606,31 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       ta.max_dropped = &R->max_dropped;
       ta.truncated = &R->truncated;
       ta.fail = &R->fail;
-      if (lds > 64 * 1024) {
-        if (hipFuncSetAttribute((const void*)k_tsvd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-            hipSuccess) {
-          s = WQ_EDEVICE;
-          break;
-        }
+      // lanes per column pair and register elements per lane
+      const bool wide = mn > 64;
+      const int lpp = wide ? 4 : 8;
+      const int epl = (mr + lpp - 1) / lpp;
+      const void* fn = nullptr;
+      if (!wide && epl <= 8) fn = (const void*)k_tsvd<8, 8>;
+      else if (!wide && epl <= 16) fn = (const void*)k_tsvd<8, 16>;
+      else if (!wide) fn = (const void*)k_tsvd<8, 32>;
+      else if (epl <= 16) fn = (const void*)k_tsvd<4, 16>;
+      else if (epl <= 32) fn = (const void*)k_tsvd<4, 32>;
+      else fn = (const void*)k_tsvd<4, 64>;
+      if (lds > 64 * 1024 &&
+          hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+        s = WQ_EDEVICE;
+        break;
       }
-      k_tsvd<<<(unsigned)ns, 64, lds, st>>>(ta);
-      if (hipGetLastError() != hipSuccess) {
+      const char* kname = h_nb[b / NB_R] <= 64 ? (h_rb[b % NB_R] <= 64 ? "k_tsvd_r64" : "k_tsvd_r256")
+                                                 : "k_tsvd_n128";
+      KTimer tm(kname, ns, st);
+      void* args[] = {&ta};
+      if (hipLaunchKernel(fn, dim3((unsigned)ns), dim3(TB), args, lds, st) != hipSuccess) {
         set_error("solve_weights: TSVD launch failed");
         s = WQ_EDEVICE;
       }
+      tm.stop();
     }
   }
   Rep hrep{};
@@ -545,10 +639,10 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   if (s == WQ_OK && hipStreamSynchronize(st) != hipSuccess) s = WQ_EDEVICE;
   for (int f = 0; f < 4; ++f) dfree(G[f]);
   dfree(gw);
-  dfree(small);
+  dfree(bkt);
   dfree(lists);
   dfree(stats);
-  dfree(pos);
+  dfree(dstart);
   dfree(drep);
   if (s == WQ_OK && hrep.fail) {
     set_error("solve_weights: a Jacobi SVD did not converge in 40 sweeps");

@@ -35,6 +35,10 @@ class MeshDesc(C.Structure):
                 ("ext_fn", C.c_void_p), ("coef_ptr", C.c_void_p), ("coef", C.c_void_p), ("ctrl", C.c_void_p)]
 
 
+class Timing(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("ms", C.c_double), ("work", C.c_int64)]
+
+
 class SolveReport(C.Structure):
     _fields_ = [("systems", C.c_int64), ("truncated", C.c_int64), ("max_sweeps", C.c_int32),
                 ("min_kept_ratio", C.c_double), ("max_dropped_ratio", C.c_double)]
@@ -66,6 +70,8 @@ def _lib():
             "assemble_stiffness": ([P, P, P, P, C.c_int, P], C.c_int),
             "assemble_biharmonic": ([P, P, P, P, C.c_int, P], C.c_int),
             "assemble_mass_stiffness": ([P, P, P, P, P, P, C.c_int, P], C.c_int),
+            "wq_timing_enable": ([C.c_int], None),
+            "wq_timings": ([P, C.c_int], C.c_int),
             "wq_strerror": ([C.c_int], C.c_char_p),
             "wq_last_error": ([], C.c_char_p),
         }
@@ -83,7 +89,7 @@ def exported_symbols():
     return ["wq_mesh_create", "wq_mesh_destroy", "build_points", "build_points_with_s", "wq_points_destroy",
             "wq_points_size", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
             "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
-            "wq_strerror", "wq_last_error"]
+            "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
 
 
 def _check(status, where):
@@ -252,3 +258,15 @@ def assemble_mass_stiffness(points, weights, c=None, k=None, mass_out=None, stif
                                           _ptr(mass_out), _ptr(stiff_out), prec, _stream(stream)),
            "assemble_mass_stiffness")
     return mass_out, stiff_out
+
+
+def timing_enable(on=True):
+    """Record HIP events around the library's main kernels (measurement aid)."""
+    _lib().wq_timing_enable(1 if on else 0)
+
+
+def timings(cap=4096):
+    """[(kernel name, ms, work units)] recorded since the last call (synchronises)."""
+    buf = (Timing * cap)()
+    n = _lib().wq_timings(buf, cap)
+    return [(buf[i].name.decode(), buf[i].ms, buf[i].work) for i in range(n)]
