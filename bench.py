@@ -206,6 +206,7 @@ def main():
         "kernels_ms_per_step": {kname: round(e["ms_per_step"], 4) for kname, e in per_kernel.items()},
         "tsvd_systems_per_family": {"r64": int(cls0.sum()), "r256": int(cls1.sum()), "n128": int(cls2.sum())},
         "solve_report": wts.report,
+        "structure": pts.info(),
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)

@@ -5,100 +5,295 @@ using namespace wq;
 
 namespace {
 
-constexpr int GROUP = 16;  // lanes per row
-constexpr int BS = 256;    // 16 rows per block
+constexpr int WAVE = 64;
+constexpr int NXCD = 8;    // MI355X: workgroups are dispatched round-robin over 8 XCDs
+constexpr int CHUNK = 64;  // consecutive tiles per XCD turn
 
-// K = 0 mass, 1 stiffness, 2 biharmonic, 3 mass + stiffness.
-// Row i is owned by one 16-lane group. For every cell c of supp N_i (ascending) and every
-// cell function k (one lane each): v_k = sum_{points q of c} w_iq coef_q D_k(x_q), then
-// acc[slot_k] += v_k. Lanes of a group own distinct slots at every step, so there are no
-// atomics and the summation order is fixed.
+// Families per kernel: K = 0 mass, 1 stiffness, 2 biharmonic, 3 mass + stiffness.
+// ND basis arrays (N or Delta N; dN/dx, dN/dy) and as many weight families; each weight
+// family a is scaled by the coefficient array cof(a).
+template <int K> struct Fam {
+  static constexpr int N = (K == 3) ? 3 : (K == 1 ? 2 : 1);
+  static constexpr int NACC = (K == 3) ? 2 : 1;
+  static constexpr int NC = (K == 3) ? 2 : 1;
+  __device__ static constexpr int cof(int a) { return (K == 3 && a > 0) ? 1 : 0; }
+};
+
+struct Src {
+  const double* D[3];  // basis blocks, point-major per cell: D[d0 + q * m + k]
+  const double* W[3];  // weights aligned with Q_i
+  const double* C[2];  // coefficients at the points (nullptr: 1)
+};
+
+constexpr int PFD = 4;  // register slots (x 64 lanes) prefetched for a cell's basis block
+constexpr int PFW = 1;  // ... for the member rows' weights on the cell
+constexpr int PFS = 4;  // ... for the members' column slots
+
+// Entry e of a tile: cell block at d0, points pt0.., np points, m functions; member rows
+// are the set bits of the 16-bit mask, their records at smem[mb ..] in row order.
+struct Ent {
+  int64_t d0, pt0;
+  int np, m, R, mb;
+  float rnp, rm;  // 1/np, 1/m for exact small-integer division (see qdiv)
+};
+
+__device__ inline Ent decode(const int4 E, int64_t m0) {
+  Ent e;
+  e.d0 = (uint32_t)E.x;
+  e.pt0 = (uint32_t)E.y;
+  e.np = (E.z >> 16) & 0xff;
+  e.m = (int)((unsigned)E.z >> 24);
+  e.R = __popc((unsigned)E.z & 0xffffu);
+  e.mb = (int)((int64_t)(uint32_t)E.w - m0);
+  e.rnp = 1.0f / (float)e.np;
+  e.rm = 1.0f / (float)e.m;
+  return e;
+}
+
+// floor(t / d) for 0 <= t < 4096, 1 <= d <= 255, with r = 1/d rounded to fp32: the
+// quotient (t + 1/2) / d is at least 1/(2d) >= 1/510 away from an integer and the fp32
+// product errs by < 4096 * 2^-23 < 5e-4, so truncation is exact.
+__device__ inline int qdiv(int t, float r) { return (int)(((float)t + 0.5f) * r); }
+
+template <int K> struct Pre {
+  double d[Fam<K>::N][PFD];
+  double w[Fam<K>::N][PFW];
+  double c[Fam<K>::NC][PFW];
+  int s[PFS];
+  int rl[PFS];
+};
+
+// Issue the global loads of one entry into registers (consumed by stage()).
 template <int K>
-__global__ void __launch_bounds__(BS) k_assemble(int64_t n, int max_row, const int64_t* __restrict__ sptr,
-                                                 const int32_t* __restrict__ scell, const int64_t* __restrict__ cfn_ptr,
-                                                 const int64_t* __restrict__ cell_pt_off, const int64_t* __restrict__ dptr,
-                                                 const int64_t* __restrict__ soff, const uint8_t* __restrict__ slot,
-                                                 const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ qptr,
-                                                 const double* __restrict__ W0, const double* __restrict__ W1,
-                                                 const double* __restrict__ W2, const double* __restrict__ D0,
-                                                 const double* __restrict__ D1, const double* __restrict__ D2,
-                                                 const double* __restrict__ c0, const double* __restrict__ c1,
-                                                 double* __restrict__ out0, double* __restrict__ out1) {
-  extern __shared__ double sh[];
-  constexpr int NACC = (K == 3) ? 2 : 1;
-  const int grp = threadIdx.x / GROUP;
-  const int lane = threadIdx.x % GROUP;
-  const int64_t i = (int64_t)blockIdx.x * (BS / GROUP) + grp;
-  double* acc = sh + (size_t)grp * NACC * max_row;
-  const bool active = i < n;
-  for (int t = lane; t < NACC * max_row; t += GROUP) acc[t] = 0.0;
-  __syncthreads();
-  if (active) {
-    int64_t qo = qptr[i];
-    for (int64_t p = sptr[i]; p < sptr[i + 1]; ++p) {
-      const int32_t c = scell[p];
-      const int64_t f0 = cfn_ptr[c];
-      const int m = (int)(cfn_ptr[c + 1] - f0);
-      const int64_t pt0 = cell_pt_off[c];
-      const int np = (int)(cell_pt_off[c + 1] - pt0);
-      const int64_t d0 = dptr[c];
-      const uint8_t* sl = slot + soff[p];
-      for (int k = lane; k < m; k += GROUP) {
-        double va = 0.0, vb = 0.0;
-        for (int q = 0; q < np; ++q) {
-          const int64_t dq = d0 + (int64_t)q * m + k;
-          if (K == 0 || K == 2) {
-            const double cq = c0 ? c0[pt0 + q] : 1.0;
-            va += (W0[qo + q] * cq) * D0[dq];
-          } else if (K == 1) {
-            const double kq = c0 ? c0[pt0 + q] : 1.0;
-            va += kq * (W1[qo + q] * D1[dq] + W2[qo + q] * D2[dq]);
-          } else {
-            const double cq = c0 ? c0[pt0 + q] : 1.0;
-            const double kq = c1 ? c1[pt0 + q] : 1.0;
-            va += (W0[qo + q] * cq) * D0[dq];
-            vb += kq * (W1[qo + q] * D1[dq] + W2[qo + q] * D2[dq]);
-          }
-        }
-        const int sk = sl[k];
-        acc[sk] += va;
-        if (K == 3) acc[max_row + sk] += vb;
-      }
-      qo += np;
+__device__ inline void prefetch(const Ent& e, int lane, const Src& S, const int2* smem,
+                                const uint8_t* __restrict__ slot, Pre<K>& p) {
+  constexpr int N = Fam<K>::N;
+  const int nd = e.np * e.m, nw = e.R * e.np, ns = e.R * e.m;
+#pragma unroll
+  for (int u = 0; u < PFD; ++u) {
+    const int t = lane + WAVE * u;
+    if (t < nd) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) p.d[a][u] = S.D[a][e.d0 + t];
     }
   }
-  __syncthreads();
-  if (active) {
-    const int64_t r0 = row_ptr[i];
-    const int ni = (int)(row_ptr[i + 1] - r0);
-    for (int t = lane; t < ni; t += GROUP) {
-      out0[r0 + t] = acc[t];
-      if (K == 3) out1[r0 + t] = acc[max_row + t];
+#pragma unroll
+  for (int u = 0; u < PFW; ++u) {
+    const int t = lane + WAVE * u;
+    if (t < nw) {
+      const int j = qdiv(t, e.rnp), q = t - j * e.np;
+      const int64_t qo = smem[e.mb + j].x & ((1 << 28) - 1);
+#pragma unroll
+      for (int a = 0; a < N; ++a) p.w[a][u] = S.W[a][qo + q];
+#pragma unroll
+      for (int a = 0; a < Fam<K>::NC; ++a) p.c[a][u] = S.C[a] ? S.C[a][e.pt0 + q] : 1.0;
     }
+  }
+#pragma unroll
+  for (int u = 0; u < PFS; ++u) {
+    const int t = lane + WAVE * u;
+    if (t < ns) {
+      const int j = qdiv(t, e.rm), k = t - j * e.m;
+      const int2 mm = smem[e.mb + j];
+      p.s[u] = slot[(uint32_t)mm.y + k];
+      p.rl[u] = (int)((unsigned)mm.x >> 28);
+    }
+  }
+}
+
+// Write one prefetched entry into the LDS stage: basis blocks sd[a][q * m + k] and
+// coefficient-scaled weights sw[a][j * np + q]; parts beyond the register slots are
+// loaded here directly.
+template <int K>
+__device__ inline void stage(const Ent& e, int lane, const Src& S, const int2* smem, const Pre<K>& p,
+                             double* sd, int nd_cap, double* sw, int nw_cap) {
+  constexpr int N = Fam<K>::N;
+  const int nd = e.np * e.m, nw = e.R * e.np;
+#pragma unroll
+  for (int u = 0; u < PFD; ++u) {
+    const int t = lane + WAVE * u;
+    if (t < nd) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) sd[a * nd_cap + t] = p.d[a][u];
+    }
+  }
+  for (int t = lane + WAVE * PFD; t < nd; t += WAVE)
+    for (int a = 0; a < N; ++a) sd[a * nd_cap + t] = S.D[a][e.d0 + t];
+#pragma unroll
+  for (int u = 0; u < PFW; ++u) {
+    const int t = lane + WAVE * u;
+    if (t < nw) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) sw[a * nw_cap + t] = p.w[a][u] * p.c[Fam<K>::cof(a)][u];
+    }
+  }
+  for (int t = lane + WAVE * PFW; t < nw; t += WAVE) {
+    const int j = qdiv(t, e.rnp), q = t - j * e.np;
+    const int64_t qo = smem[e.mb + j].x & ((1 << 28) - 1);
+    for (int a = 0; a < N; ++a) {
+      const double* C = S.C[Fam<K>::cof(a)];
+      sw[a * nw_cap + t] = S.W[a][qo + q] * (C ? C[e.pt0 + q] : 1.0);
+    }
+  }
+}
+
+// lane (j, k): v = sum_q sw[j][q] sd[q][k] (per family), added to acc[row j][slot k].
+template <int K>
+__device__ inline void accumulate(const Ent& e, int t, int sk, int rl, const double* sd, int nd_cap,
+                                  const double* sw, int nw_cap, const int* ro, double* acc, int acc_stride) {
+  const int j = qdiv(t, e.rm), k = t - j * e.m;
+  const double* w = sw + j * e.np;
+  double va = 0.0, vb = 0.0;
+  for (int q = 0; q < e.np; ++q) {
+    const int dq = q * e.m + k;
+    if (K == 0 || K == 2) {
+      va += w[q] * sd[dq];
+    } else if (K == 1) {
+      va += w[q] * sd[dq] + w[nw_cap + q] * sd[nd_cap + dq];
+    } else {
+      va += w[q] * sd[dq];
+      vb += w[nw_cap + q] * sd[nd_cap + dq] + w[2 * nw_cap + q] * sd[2 * nd_cap + dq];
+    }
+  }
+  const int at = ro[rl] + sk;
+  acc[at] += va;
+  if (K == 3) acc[acc_stride + at] += vb;
+}
+
+// One wavefront owns a tile of TILE_ROWS consecutive rows and their accumulators in LDS.
+// It visits the tile's cells once each, in ascending order (one precomputed entry per
+// cell: basis block, points, member rows). Per entry, the whole wave loads the cell's
+// basis block and the members' weights with coalesced loads into an LDS stage, then
+// lane (j, k) forms v = sum_{points q of the cell} w_{i_j q} coef_q D_k(x_q) for member
+// row i_j and cell function k and adds it to acc[i_j][slot]. The next entry's loads are
+// issued into registers before the current one is computed. Within an entry the (j, k)
+// are distinct and entries are applied in order: no atomics, fixed summation order.
+// Workgroups of one XCD take chunks of consecutive tiles (L2 reuse between neighbours).
+template <int K>
+__global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, int64_t per_xcd, int acc_stride,
+                                                   int mem_cap, int nd_cap, int nw_cap,
+                                                   const int64_t* __restrict__ eptr, const int4* __restrict__ ent,
+                                                   const int2* __restrict__ mem, const int64_t* __restrict__ sptr,
+                                                   const uint8_t* __restrict__ slot,
+                                                   const int64_t* __restrict__ row_ptr, Src S,
+                                                   double* __restrict__ out0, double* __restrict__ out1) {
+  constexpr int N = Fam<K>::N;
+  constexpr int NACC = Fam<K>::NACC;
+  extern __shared__ double acc[];
+  __shared__ int ro[TILE_ROWS + 1];
+  double* sd = acc + NACC * acc_stride;
+  double* sw = sd + N * nd_cap;
+  int2* smem = (int2*)(sw + N * nw_cap);
+  const int64_t b = blockIdx.x;
+  const int64_t turn = b / NXCD;
+  const int64_t tile = (turn / CHUNK) * (NXCD * CHUNK) + (b % NXCD) * CHUNK + turn % CHUNK;
+  if (tile >= n_tiles) return;
+  const int lane = threadIdx.x;
+  const int64_t i0 = tile * TILE_ROWS;
+  const int nr = (int)min((int64_t)TILE_ROWS, n - i0);
+  const int64_t a0 = row_ptr[i0];
+  const int nz = (int)(row_ptr[i0 + nr] - a0);
+  const int64_t e0 = eptr[tile];
+  const int ne = (int)(eptr[tile + 1] - e0);
+  const int64_t m0 = sptr[i0];
+  const int nm = (int)(sptr[i0 + nr] - m0);
+  if (lane <= nr) ro[lane] = (int)(row_ptr[i0 + lane] - a0);
+  for (int t = lane; t < NACC * acc_stride; t += WAVE) acc[t] = 0.0;
+  for (int t = lane; t < nm; t += WAVE) smem[t] = mem[m0 + t];
+  __syncthreads();
+  if (ne > 0) {
+    Pre<K> p;
+    Ent cur = decode(ent[e0], m0);
+    prefetch<K>(cur, lane, S, smem, slot, p);
+    stage<K>(cur, lane, S, smem, p, sd, nd_cap, sw, nw_cap);
+    int cs[PFS], cr[PFS];
+#pragma unroll
+    for (int u = 0; u < PFS; ++u) {
+      cs[u] = p.s[u];
+      cr[u] = p.rl[u];
+    }
+    __syncthreads();
+    for (int e = 0; e < ne; ++e) {
+      Ent nxt;
+      const bool more = e + 1 < ne;
+      if (more) {
+        nxt = decode(ent[e0 + e + 1], m0);
+        prefetch<K>(nxt, lane, S, smem, slot, p);
+      }
+      const int ns = cur.R * cur.m;
+#pragma unroll
+      for (int u = 0; u < PFS; ++u) {
+        const int t = lane + WAVE * u;
+        if (t < ns) accumulate<K>(cur, t, cs[u], cr[u], sd, nd_cap, sw, nw_cap, ro, acc, acc_stride);
+      }
+      for (int t = lane + WAVE * PFS; t < ns; t += WAVE) {
+        const int j = qdiv(t, cur.rm), k = t - j * cur.m;
+        const int2 mm = smem[cur.mb + j];
+        accumulate<K>(cur, t, slot[(uint32_t)mm.y + k], (int)((unsigned)mm.x >> 28), sd, nd_cap, sw, nw_cap, ro,
+                      acc, acc_stride);
+      }
+      __syncthreads();
+      if (more) {
+        stage<K>(nxt, lane, S, smem, p, sd, nd_cap, sw, nw_cap);
+#pragma unroll
+        for (int u = 0; u < PFS; ++u) {
+          cs[u] = p.s[u];
+          cr[u] = p.rl[u];
+        }
+        cur = nxt;
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = lane; t < nz; t += WAVE) {
+    out0[a0 + t] = acc[t];
+    if (K == 3) out1[a0 + t] = acc[acc_stride + t];
   }
 }
 
 template <int K>
 wq_status launch(const wq_points* P, const wq_weights* w, const double* c0, const double* c1, double* o0, double* o1,
                  hipStream_t st) {
-  constexpr int NACC = (K == 3) ? 2 : 1;
-  const size_t lds = (size_t)(BS / GROUP) * NACC * P->max_row * sizeof(double);
-  const double* W0 = w->W[0].as<double>();
-  const double* W1 = w->W[1].as<double>();
-  const double* W2 = w->W[2].as<double>();
-  const double* D0 = P->DN.as<double>();
-  if (K == 2) {
-    W0 = w->W[3].as<double>();
-    D0 = P->DL.as<double>();
+  constexpr int N = Fam<K>::N;
+  constexpr int NACC = Fam<K>::NACC;
+  const int nd_cap = P->max_tile_nd, nw_cap = P->max_tile_nw;
+  const size_t lds = (size_t)NACC * P->max_tile_nnz * sizeof(double) + (size_t)N * (nd_cap + nw_cap) * sizeof(double) +
+                     (size_t)P->max_tile_mem * sizeof(int2);
+  WQ_CHECK(lds <= 150 * 1024, WQ_EINVAL, "assemble: tile accumulators and stage exceed LDS");
+  WQ_CHECK(nw_cap < 4096 && (int64_t)TILE_ROWS * 255 < 4096, WQ_EINVAL, "assemble: entry too large");
+  Src S{};
+  if (K == 0) {
+    S.D[0] = P->DN.as<double>();
+    S.W[0] = w->W[0].as<double>();
+  } else if (K == 1) {
+    S.D[0] = P->DX.as<double>();
+    S.D[1] = P->DY.as<double>();
+    S.W[0] = w->W[1].as<double>();
+    S.W[1] = w->W[2].as<double>();
+  } else if (K == 2) {
+    S.D[0] = P->DL.as<double>();
+    S.W[0] = w->W[3].as<double>();
+  } else {
+    S.D[0] = P->DN.as<double>();
+    S.D[1] = P->DX.as<double>();
+    S.D[2] = P->DY.as<double>();
+    S.W[0] = w->W[0].as<double>();
+    S.W[1] = w->W[1].as<double>();
+    S.W[2] = w->W[2].as<double>();
   }
+  S.C[0] = c0;
+  S.C[1] = c1;
+  // grid covers whole rounds of NXCD * CHUNK tiles; blocks past the end exit
+  const int64_t per_xcd = ((P->n_tiles + NXCD * CHUNK - 1) / (NXCD * CHUNK)) * CHUNK;
   static const char* names[4] = {"k_assemble_mass", "k_assemble_stiffness", "k_assemble_biharmonic",
                                   "k_assemble_mass_stiffness"};
+  if (lds > 64 * 1024)
+    WQ_HIP(hipFuncSetAttribute((const void*)k_assemble<K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   KTimer tm(names[K], P->n_rows, st);
-  k_assemble<K><<<nblocks(P->n_rows, BS / GROUP), BS, lds, st>>>(
-      P->n_rows, P->max_row, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(), P->cfn_ptr.as<int64_t>(),
-      P->cell_pt_off.as<int64_t>(), P->dptr.as<int64_t>(), P->soff.as<int64_t>(), P->slot.as<uint8_t>(),
-      P->row_ptr.as<int64_t>(), P->qptr.as<int64_t>(), W0, W1, W2, D0, P->DX.as<double>(), P->DY.as<double>(), c0,
-      c1, o0, o1);
+  k_assemble<K><<<(unsigned)(per_xcd * NXCD), WAVE, lds, st>>>(
+      P->n_rows, P->n_tiles, per_xcd, P->max_tile_nnz, P->max_tile_mem, nd_cap, nw_cap, P->tile_eptr.as<int64_t>(),
+      P->tile_ent.as<int4>(), P->tile_mem.as<int2>(), P->supp_ptr.as<int64_t>(), P->slot.as<uint8_t>(),
+      P->row_ptr.as<int64_t>(), S, o0, o1);
   tm.stop();
   WQ_HIP(hipGetLastError());
   return WQ_OK;

@@ -84,6 +84,12 @@ struct wq_points {
       qptr /*int64*/, qidx /*int32*/;
   // per (row, cell) pair = supp entry
   wq::DBuf soff /*int64 [pairs+1]*/, slot /*uint8*/, kself /*uint8*/;
+  // assembly tiles: 16 consecutive rows; one entry per (tile, cell) in ascending cell order
+  int64_t n_tiles = 0, n_entries = 0;
+  int32_t max_tile_nnz = 0, max_tile_ent = 0, max_tile_mem = 0;
+  int32_t max_tile_nd = 0 /*max np*m of an entry*/, max_tile_nw = 0 /*max members*np*/;
+  wq::DBuf tile_eptr /*int64 [tiles+1]*/, tile_ent /*int4 [entries]: dptr, pt0, mask|np<<16|m<<24, mbase*/,
+      tile_mem /*int2 [pairs]: qoff | rowloc<<28, soff*/;
   // per point
   wq::DBuf x /*double [2 np]*/, detJ /*double [np]*/;
   // per (cell, point, cell function)
@@ -134,6 +140,8 @@ struct KTimer {
   KTimer(const char* n, int64_t w, hipStream_t s);
   void stop();
 };
+
+constexpr int TILE_ROWS = 16;
 
 // 64-bit index launch helper
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }

@@ -457,6 +457,87 @@ __global__ void k_basis(int64_t npts_total, int32_t ncell, const int64_t* cell_p
   }
 }
 
+// ------------------------------------------------------------------ assembly tiles
+// Weight offset of every (row, cell) pair: qptr[i] + points of the earlier cells of row i.
+__global__ void k_pair_qoff(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cell_pt_off,
+                            const int64_t* qptr, int64_t* qoff) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t o = qptr[i];
+  for (int64_t p = sptr[i]; p < sptr[i + 1]; ++p) {
+    qoff[p] = o;
+    const int32_t c = scell[p];
+    o += cell_pt_off[c + 1] - cell_pt_off[c];
+  }
+}
+
+// Merge of the (ascending) cell lists of the rows of one tile. fill == false: count the
+// distinct cells; fill == true: write one entry per cell and its member records.
+template <bool FILL>
+__global__ void k_tile_entries(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cfn_ptr,
+                               const int64_t* cell_pt_off, const int64_t* dptr, const int64_t* qoff,
+                               const int64_t* soff, const int64_t* row_ptr, int64_t* eptr, int4* ent, int2* mem,
+                               int* maxnnz, int* overflow) {
+  const int64_t tile = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i0 = tile * TILE_ROWS;
+  if (i0 >= n) return;
+  const int nr = (int)min((int64_t)TILE_ROWS, n - i0);
+  int64_t pos[TILE_ROWS], end[TILE_ROWS];
+  for (int r = 0; r < nr; ++r) {
+    pos[r] = sptr[i0 + r];
+    end[r] = sptr[i0 + r + 1];
+  }
+  if (!FILL) {
+    atomicMax(maxnnz, (int)(row_ptr[i0 + nr] - row_ptr[i0]));
+    atomicMax(maxnnz + 2, (int)(sptr[i0 + nr] - sptr[i0]));  // members of the tile
+  }
+  int64_t e = FILL ? eptr[tile] : 0;
+  int64_t mb = FILL ? sptr[i0] : 0;  // members are stored in (entry, row) order
+  int count = 0;
+  while (true) {
+    int32_t best = INT_MAX;
+    for (int r = 0; r < nr; ++r)
+      if (pos[r] < end[r]) best = min(best, scell[pos[r]]);
+    if (best == INT_MAX) break;
+    unsigned mask = 0;
+    int nm = 0;
+    for (int r = 0; r < nr; ++r) {
+      if (pos[r] < end[r] && scell[pos[r]] == best) {
+        mask |= 1u << r;
+        if (FILL) {
+          const int64_t p = pos[r];
+          const int64_t q = qoff[p], so = soff[p];
+          if (q >= (1LL << 28) || so >= (1LL << 31)) atomicOr(overflow, 1);
+          mem[mb + nm] = make_int2((int)(q | ((int64_t)r << 28)), (int)so);
+        }
+        ++nm;
+        ++pos[r];
+      }
+    }
+    if (FILL) {
+      const int np = (int)(cell_pt_off[best + 1] - cell_pt_off[best]);
+      const int m = (int)(cfn_ptr[best + 1] - cfn_ptr[best]);
+      const int64_t d0 = dptr[best];
+      if (d0 >= (1LL << 31) || cell_pt_off[best] >= (1LL << 31) || np > 255 || m > 255) atomicOr(overflow, 1);
+      ent[e] = make_int4((int)d0, (int)cell_pt_off[best], (int)(mask | (np << 16) | (m << 24)), (int)mb);
+      ++e;
+      mb += nm;
+    }
+    if (!FILL) {
+      // per-entry staging sizes of the assembly: the cell's basis block and the member weights
+      const int np = (int)(cell_pt_off[best + 1] - cell_pt_off[best]);
+      const int m = (int)(cfn_ptr[best + 1] - cfn_ptr[best]);
+      atomicMax(maxnnz + 4, np * m);
+      atomicMax(maxnnz + 5, nm * np);
+    }
+    ++count;
+  }
+  if (!FILL) {
+    eptr[tile] = count;
+    atomicMax(maxnnz + 3, count);
+  }
+}
+
 struct Tmp {
   DBuf vptr, vcur, vidx, bnd, val, ep, passive, enriched, pvtx, tpoint, flags;
   void release() {
@@ -471,6 +552,7 @@ void release_points(wq_points* P) {
   dfree(P->supp_cell); dfree(P->row_ptr); dfree(P->col); dfree(P->qptr); dfree(P->qidx);
   dfree(P->soff); dfree(P->slot); dfree(P->kself); dfree(P->x); dfree(P->detJ);
   dfree(P->DN); dfree(P->DX); dfree(P->DY); dfree(P->DL);
+  dfree(P->tile_eptr); dfree(P->tile_ent); dfree(P->tile_mem);
 }
 
 wq_status sync_flags(DBuf& flags, int* h, int n, hipStream_t st) {
@@ -678,6 +760,41 @@ wq_status minmax_update(wq_mesh* M, wq_points* P, std::vector<uint8_t>& hs, bool
   return WQ_OK;
 }
 
+wq_status build_tiles(wq_mesh* M, wq_points* P, DBuf& flags, hipStream_t st) {
+  const int64_t n = P->n_rows;
+  P->n_tiles = (n + TILE_ROWS - 1) / TILE_ROWS;
+  DBuf qoff;
+  int hf[6];
+  WQ_TRY(dalloc_n<int64_t>(qoff, P->n_pairs));
+  WQ_TRY(dalloc_n<int64_t>(P->tile_eptr, P->n_tiles + 1));
+  WQ_HIP(hipMemsetAsync(P->tile_eptr.p, 0, (P->n_tiles + 1) * sizeof(int64_t), st));
+  WQ_HIP(hipMemsetAsync(flags.p, 0, 8 * sizeof(int), st));
+  k_pair_qoff<<<nblocks(n, BS), BS, 0, st>>>(n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
+                                              P->cell_pt_off.as<int64_t>(), P->qptr.as<int64_t>(), qoff.as<int64_t>());
+  k_tile_entries<false><<<nblocks(P->n_tiles, 64), 64, 0, st>>>(
+      n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(), P->cfn_ptr.as<int64_t>(), P->cell_pt_off.as<int64_t>(),
+      P->dptr.as<int64_t>(), qoff.as<int64_t>(), P->soff.as<int64_t>(), P->row_ptr.as<int64_t>(),
+      P->tile_eptr.as<int64_t>(), nullptr, nullptr, flags.as<int>(), flags.as<int>() + 1);
+  WQ_TRY(exclusive_scan_i64(P->tile_eptr.as<int64_t>(), P->n_tiles + 1, &P->n_entries, st));
+  WQ_TRY(dalloc(P->tile_ent, (size_t)P->n_entries * sizeof(int4)));
+  WQ_TRY(dalloc(P->tile_mem, (size_t)P->n_pairs * sizeof(int2)));
+  k_tile_entries<true><<<nblocks(P->n_tiles, 64), 64, 0, st>>>(
+      n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(), P->cfn_ptr.as<int64_t>(), P->cell_pt_off.as<int64_t>(),
+      P->dptr.as<int64_t>(), qoff.as<int64_t>(), P->soff.as<int64_t>(), P->row_ptr.as<int64_t>(),
+      P->tile_eptr.as<int64_t>(), P->tile_ent.as<int4>(), P->tile_mem.as<int2>(), flags.as<int>(),
+      flags.as<int>() + 1);
+  WQ_TRY(sync_flags(flags, hf, 6, st));
+  dfree(qoff);
+  P->max_tile_nd = hf[4];
+  P->max_tile_nw = hf[5];
+  P->max_tile_nnz = hf[0];
+  P->max_tile_mem = hf[2];
+  P->max_tile_ent = hf[3];
+  WQ_CHECK(!hf[1], WQ_EINVAL, "build_points: mesh too large for 32-bit tile offsets; split it");
+  WQ_HIP(hipGetLastError());
+  return WQ_OK;
+}
+
 wq_status build_points_impl(wq_mesh* M, int want_lap, const uint8_t* s_host, hipStream_t st, wq_points** out,
                             int64_t* n_rows, int64_t* nnz, int64_t* n_points) {
   WQ_CHECK(M && out, WQ_EINVAL, "build_points: null argument");
@@ -767,6 +884,8 @@ wq_status build_points_impl(wq_mesh* M, int want_lap, const uint8_t* s_host, hip
     }
     dfree(npm);
   }
+  // assembly tiles (need dptr)
+  if (s == WQ_OK) s = build_tiles(M, P, flags, st);
   dfree(flags);
   if (s != WQ_OK) {
     release_points(P);
@@ -815,6 +934,24 @@ extern "C" int64_t wq_points_size(const wq_points* P, wq_array what) {
     case WQ_ARR_ETYPE: case WQ_ARR_S: return P->mesh->nf;
     case WQ_ARR_X: return 2 * P->n_points;
     case WQ_ARR_DETJ: return P->n_points;
+  }
+  return -1;
+}
+
+extern "C" int64_t wq_points_info(const wq_points* P, int what) {
+  if (!P) return -1;
+  switch (what) {
+    case 0: return P->max_row;
+    case 1: return P->max_r;
+    case 2: return P->ncell;
+    case 3: return P->n_tiles;
+    case 4: return P->n_entries;
+    case 5: return P->max_tile_nnz;
+    case 6: return P->max_tile_ent;
+    case 7: return P->max_tile_mem;
+    case 8: return P->n_pairs;
+    case 9: return P->max_tile_nd;
+    case 10: return P->max_tile_nw;
   }
   return -1;
 }

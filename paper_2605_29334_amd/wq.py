@@ -62,6 +62,7 @@ def _lib():
             "wq_points_destroy": ([P], None),
             "wq_points_size": ([P, C.c_int], I64),
             "wq_points_get": ([P, C.c_int, P, P], C.c_int),
+            "wq_points_info": ([P, C.c_int], I64),
             "solve_weights": ([P, P, U, D, P, P, P], C.c_int),
             "wq_weights_destroy": ([P], None),
             "wq_weights_get": ([P, C.c_int, P, P], C.c_int),
@@ -87,7 +88,7 @@ def _lib():
 def exported_symbols():
     """Names the C ABI declares (checked by the CPU tests against the built library)."""
     return ["wq_mesh_create", "wq_mesh_destroy", "build_points", "build_points_with_s", "wq_points_destroy",
-            "wq_points_size", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
+            "wq_points_size", "wq_points_info", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
             "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
             "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
 
@@ -159,6 +160,11 @@ class Points:
         self.h = h
         self.mesh = mesh
         self.n_rows, self.nnz, self.n_points = n.value, nnz.value, npt.value
+
+    def info(self):
+        keys = ["max_row", "max_r", "cells", "tiles", "tile_entries", "max_tile_nnz", "max_tile_entries",
+                "max_tile_members", "pairs", "max_entry_basis", "max_entry_weights"]
+        return {k: int(_lib().wq_points_info(self.h, i)) for i, k in enumerate(keys)}
 
     def get(self, what, stream=None):
         size = _lib().wq_points_size(self.h, what)
