@@ -28,13 +28,56 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector
 
 
-def tsvd_flops(n, r):
-    """Algorithmic FLOPs of one weight system (n constraints, r points): Golub-Kahan
-    bidiagonalisation 4 r n^2 - 4 n^3 / 3 plus the QR of Z V_t, 2 r n^2 - 2 n^3 / 3
-    (t = n upper bound) -- a lower bound for any SVD-based solve."""
-    n = n.astype(np.float64)
-    r = r.astype(np.float64)
-    return 6.0 * r * n * n - 2.0 * n ** 3
+def aggregate(recs, steps):
+    """Per kernel: total ms, launches, summed algorithmic work (library timing records)."""
+    out = {}
+    for name, ms, work in recs:
+        e = out.setdefault(name, {"ms": 0.0, "launches": 0, "work": 0})
+        e["ms"] += ms
+        e["launches"] += 1
+        e["work"] += work
+    for e in out.values():
+        e["ms_per_step"] = e["ms"] / steps
+    return out
+
+
+def traffic_of(kernel):
+    """HBM bytes per launch from the committed counter summary of `kernel`, if it was
+    taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 4 and parts[0] == kernel:
+            rec = {"src": parts[1], "sha": parts[2], "bytes": float(parts[3])}
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2605_29334_amd", "csrc", rec["src"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["sha"]:
+        return None
+    return rec["bytes"]
+
+
+def roofline_of(name, e):
+    """Roofline entry of one kernel from its timing aggregate: algorithmic work per launch
+    over the average launch duration."""
+    avg_ms = e["ms"] / e["launches"]
+    per_launch = e["work"] / e["launches"]
+    if name.startswith("k_tsvd"):
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_of(name), "avg_launch_ms": avg_ms,
+                "launches": e["launches"], "algorithmic_per_launch": per_launch}
+    if name.startswith("k_assemble"):
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_of(name), "avg_launch_ms": avg_ms,
+                "launches": e["launches"], "algorithmic_per_launch": per_launch}
+    return {"kernel": name, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None, "avg_launch_ms": avg_ms, "launches": e["launches"]}
 
 
 def make_fixture(N, density, seed):
@@ -141,55 +184,26 @@ def main():
     W.timing_enable(False)
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
-    per_kernel = {}
-    for name, ms, work in recs:
-        e = per_kernel.setdefault(name, {"ms": 0.0, "launches": 0, "work": 0})
-        e["ms"] += ms
-        e["launches"] += 1
-        e["work"] += work
-    for e in per_kernel.values():
-        e["ms_per_step"] = e["ms"] / args.steps
+    per_kernel = aggregate(recs, args.steps)
+    dom_name, dom = max(per_kernel.items(), key=lambda kv: kv[1]["ms"])
+    roofline = roofline_of(dom_name, dom)
 
-    # dominant kernel: the TSVD size classes (FP64 ALU); algorithmic FLOPs per launch
-    # TSVD size classes, as the library forms them (one launch per class and family)
-    cls0 = (n_i <= 64) & (r_i <= 64)
-    cls1 = (n_i <= 64) & (r_i > 64) & (r_i <= 256)
-    cls2 = ~(cls0 | cls1)
-    fl_cls = {"k_tsvd_r64": float(tsvd_flops(n_i[cls0], r_i[cls0]).sum()),
-              "k_tsvd_r256": float(tsvd_flops(n_i[cls1], r_i[cls1]).sum()),
-              "k_tsvd_n128": float(tsvd_flops(n_i[cls2], r_i[cls2]).sum())}
-    dom = max(per_kernel.items(), key=lambda kv: kv[1]["ms"])
-    dom_name = dom[0]
-    avg_ms = dom[1]["ms"] / dom[1]["launches"]
-    if dom_name.startswith("k_tsvd"):
-        flops_launch = fl_cls[dom_name]
-        achieved = flops_launch / (avg_ms * 1e-3) / 1e12
-        roofline = {"kernel": dom_name, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                    "avg_launch_ms": avg_ms, "algorithmic_per_launch": flops_launch}
-    else:
-        roofline = {"kernel": dom_name, "bound": "unknown", "achieved": None, "peak": None, "unit": None,
-                    "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
-
-    # assembly only (weights and basis resident; caches flushed between repetitions)
+    # assembly only (weights and basis resident; caches flushed between repetitions),
+    # timed by the library's HIP events on the launch stream
     pts, wts, M, K = live
     flush = torch.empty(512 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
-    times = []
+    W.timing_enable(True)
+    W.timings()
     for _ in range(args.assembly_reps):
         flush.fill_(1.0)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
         W.assemble_mass_stiffness(pts, wts, c, k, M, K, stream=stream)
-        ev1.record(stream)
-        ev1.synchronize()
-        times.append(ev0.elapsed_time(ev1))
-    a_ms = float(np.median(times))
-    asm_bytes = 8.0 * (6 * sum_r + 2 * n_points + 2 * nnz)
-    asm_gbs = asm_bytes / (a_ms * 1e-3) / 1e9
-    assembly = {"nnz_per_s": 2 * nnz / (a_ms * 1e-3), "median_ms": a_ms,
-                "roofline": {"kernel": "k_assemble_mass_stiffness", "bound": "hbm", "achieved": asm_gbs,
-                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": asm_gbs / HBM_PEAK_GBS,
-                             "traffic": None, "algorithmic_bytes": asm_bytes}}
+    torch.cuda.synchronize()
+    arecs = [r for r in W.timings() if r[0] == "k_assemble_mass_stiffness"]
+    W.timing_enable(False)
+    a_ms = float(np.median([r[1] for r in arecs]))
+    asm_bytes = float(arecs[0][2])
+    asm = {"kernel": "k_assemble_mass_stiffness", "ms": a_ms, "launches": 1, "work": asm_bytes}
+    assembly = {"nnz_per_s": 2 * nnz / (a_ms * 1e-3), "median_ms": a_ms, "roofline": roofline_of(asm["kernel"], asm)}
 
     value = args.steps * 2 * nnz / elapsed
     out = {
@@ -204,7 +218,6 @@ def main():
         "roofline": roofline,
         "assembly_only": assembly,
         "kernels_ms_per_step": {kname: round(e["ms_per_step"], 4) for kname, e in per_kernel.items()},
-        "tsvd_systems_per_family": {"r64": int(cls0.sum()), "r256": int(cls1.sum()), "n128": int(cls2.sum())},
         "solve_report": wts.report,
         "structure": pts.info(),
     }

@@ -174,10 +174,13 @@ wq_status assemble_mass_stiffness(const wq_points* pts, const wq_weights* w, con
 /* ------------------------------------------------------------------ kernel timing
  * Measurement aid. While enabled (per process), the library records a pair of HIP
  * events on the launch stream around each of its main kernels (basis evaluation,
- * Gauss basis, Gauss rows, TSVD per size class, assembly). wq_timings() waits for the
+ * Gauss basis, Gauss rows, TSVD per size bucket, assembly). wq_timings() waits for the
  * recorded events, copies up to `cap` records into `out` (host) and clears the list;
- * it returns the number of records written. `work` is the kernel's unit count (points,
- * systems, rows). */
+ * it returns the number of records written. `name` is the kernel (TSVD: its template
+ * instance). `work` is the launch's algorithmic work: for TSVD the FLOPs
+ * sum(6 r n^2 - 2 n^3) over its systems, for assembly the bytes 8 * (every basis value
+ * and weight read once + coefficients + outputs), otherwise the unit count (points,
+ * rows). */
 typedef struct {
   char name[40];
   double ms;

@@ -289,7 +289,10 @@ wq_status launch(const wq_points* P, const wq_weights* w, const double* c0, cons
                                   "k_assemble_mass_stiffness"};
   if (lds > 64 * 1024)
     WQ_HIP(hipFuncSetAttribute((const void*)k_assemble<K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  KTimer tm(names[K], P->n_rows, st);
+  // algorithmic bytes: every basis value and weight once, the coefficients, the output
+  const int64_t sum_r = (int64_t)(P->qidx.bytes / sizeof(int32_t));
+  const int64_t nc = (c0 ? 1 : 0) + (K == 3 && c1 ? 1 : 0);
+  KTimer tm(names[K], 8 * (2 * N * sum_r + nc * P->n_points + NACC * P->nnz), st);
   k_assemble<K><<<(unsigned)(per_xcd * NXCD), WAVE, lds, st>>>(
       P->n_rows, P->n_tiles, per_xcd, P->max_tile_nnz, P->max_tile_mem, nd_cap, nw_cap, P->tile_eptr.as<int64_t>(),
       P->tile_ent.as<int4>(), P->tile_mem.as<int2>(), P->supp_ptr.as<int64_t>(), P->slot.as<uint8_t>(),

@@ -156,11 +156,12 @@ struct SysClass {
 __constant__ int c_nb[5] = {32, 48, 64, 96, 128};
 __constant__ int c_rb[7] = {64, 80, 96, 128, 160, 192, 256};
 constexpr int NB_N = 5, NB_R = 7, NBKT = NB_N * NB_R;
-static const int h_nb[5] = {32, 48, 64, 96, 128};
-static const int h_rb[7] = {64, 80, 96, 128, 160, 192, 256};
 
+// Also sums, per bucket, the algorithmic FLOPs of its systems, 6 r n^2 - 2 n^3: one
+// bidiagonalisation of the r x n matrix (4 r n^2 - 4 n^3 / 3) plus the QR of Z V_t at
+// full rank (2 r n^2 - 2 n^3 / 3); the measure of useful work for the roofline.
 __global__ void k_sys_bucket(int64_t n, const int64_t* row_ptr, const int64_t* qptr, uint8_t* bkt, int* hist,
-                             int* bad) {
+                             int* bad, unsigned long long* flops) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int ni = (int)(row_ptr[i + 1] - row_ptr[i]);
@@ -178,6 +179,8 @@ __global__ void k_sys_bucket(int64_t n, const int64_t* row_ptr, const int64_t* q
   atomicAdd(&hist[b], 1);
   atomicMax(&hist[2 * (NBKT + 1) + 2 * b], ni);  // per-bucket maxima (LDS sizing)
   atomicMax(&hist[2 * (NBKT + 1) + 2 * b + 1], ri);
+  const long long nn = ni, rr = ri;
+  atomicAdd(&flops[b], (unsigned long long)(6 * rr * nn * nn - 2 * nn * nn * nn));
 }
 
 __global__ void k_sys_scatter(int64_t n, const uint8_t* bkt, const int64_t* start, int* cur, int32_t* lists) {
@@ -514,17 +517,24 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
   }
   // systems by size bucket (order inside a bucket is irrelevant: systems are independent)
-  DBuf bkt, lists, stats, dstart;
+  DBuf bkt, lists, stats, dstart, dflops;
   int hist[4 * (NBKT + 1)];
+  unsigned long long bflops[NBKT];
   int64_t start[NBKT + 1];
   if (s == WQ_OK) s = dalloc_n<uint8_t>(bkt, n);
   if (s == WQ_OK) s = dalloc(stats, 4 * (NBKT + 1) * sizeof(int));
   if (s == WQ_OK) s = dalloc_n<int64_t>(dstart, NBKT + 1);
+  if (s == WQ_OK) s = dalloc(dflops, NBKT * sizeof(unsigned long long));
   if (s == WQ_OK && hipMemsetAsync(stats.p, 0, 4 * (NBKT + 1) * sizeof(int), st) != hipSuccess) s = WQ_EDEVICE;
+  if (s == WQ_OK && hipMemsetAsync(dflops.p, 0, NBKT * sizeof(unsigned long long), st) != hipSuccess)
+    s = WQ_EDEVICE;
   if (s == WQ_OK) {
     k_sys_bucket<<<nblocks(n, BS), BS, 0, st>>>(n, P->row_ptr.as<int64_t>(), P->qptr.as<int64_t>(),
-                                                 bkt.as<uint8_t>(), stats.as<int>(), stats.as<int>() + NBKT);
+                                                 bkt.as<uint8_t>(), stats.as<int>(), stats.as<int>() + NBKT,
+                                                 dflops.as<unsigned long long>());
     if (hipMemcpyAsync(hist, stats.p, 4 * (NBKT + 1) * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(bflops, dflops.p, NBKT * sizeof(unsigned long long), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       s = WQ_EDEVICE;
   }
@@ -611,20 +621,19 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       const int lpp = wide ? 4 : 8;
       const int epl = (mr + lpp - 1) / lpp;
       const void* fn = nullptr;
-      if (!wide && epl <= 8) fn = (const void*)k_tsvd<8, 8>;
-      else if (!wide && epl <= 16) fn = (const void*)k_tsvd<8, 16>;
-      else if (!wide) fn = (const void*)k_tsvd<8, 32>;
-      else if (epl <= 16) fn = (const void*)k_tsvd<4, 16>;
-      else if (epl <= 32) fn = (const void*)k_tsvd<4, 32>;
-      else fn = (const void*)k_tsvd<4, 64>;
+      const char* kname = nullptr;  // timing record: the kernel instance
+      if (!wide && epl <= 8) fn = (const void*)k_tsvd<8, 8>, kname = "k_tsvd<8,8>";
+      else if (!wide && epl <= 16) fn = (const void*)k_tsvd<8, 16>, kname = "k_tsvd<8,16>";
+      else if (!wide) fn = (const void*)k_tsvd<8, 32>, kname = "k_tsvd<8,32>";
+      else if (epl <= 16) fn = (const void*)k_tsvd<4, 16>, kname = "k_tsvd<4,16>";
+      else if (epl <= 32) fn = (const void*)k_tsvd<4, 32>, kname = "k_tsvd<4,32>";
+      else fn = (const void*)k_tsvd<4, 64>, kname = "k_tsvd<4,64>";
       if (lds > 64 * 1024 &&
           hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
         s = WQ_EDEVICE;
         break;
       }
-      const char* kname = h_nb[b / NB_R] <= 64 ? (h_rb[b % NB_R] <= 64 ? "k_tsvd_r64" : "k_tsvd_r256")
-                                                 : "k_tsvd_n128";
-      KTimer tm(kname, ns, st);
+      KTimer tm(kname, (int64_t)bflops[b], st);
       void* args[] = {&ta};
       if (hipLaunchKernel(fn, dim3((unsigned)ns), dim3(TB), args, lds, st) != hipSuccess) {
         set_error("solve_weights: TSVD launch failed");
@@ -643,6 +652,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   dfree(lists);
   dfree(stats);
   dfree(dstart);
+  dfree(dflops);
   dfree(drep);
   if (s == WQ_OK && hrep.fail) {
     set_error("solve_weights: a Jacobi SVD did not converge in 40 sweeps");
