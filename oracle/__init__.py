@@ -6,3 +6,4 @@ shares no code with the GPU library. It is slow and written to be read against t
 paper (Sections 2-5), step by step.
 """
 from .wq import *  # noqa: F401,F403
+from . import heat  # noqa: F401,E402
