@@ -171,6 +171,62 @@ wq_status assemble_mass_stiffness(const wq_points* pts, const wq_weights* w, con
                                   const double* k_at_points, void* mass_vals, void* stiff_vals,
                                   wq_precision prec, wq_stream stream);
 
+/* ------------------------------------------------------------------ nonlinear heat
+ * Section 5: Tdot N_A + k(T) grad T . grad N_A - f N_A = 0 (weak residual), time by the
+ * generalised trapezoidal rule, Newton with the symmetric tangent of Eq. (35).
+ * Thermal conductivity k(u): kind 0 a + b u, 1 a + b u^2, 2 a exp(b u), 3 a sin(b u)
+ * (Section 6.3 uses k = 1, e^{-T}, sin(pi T) and 200 - 0.05 T). */
+typedef enum { WQ_K_LINEAR = 0, WQ_K_QUADRATIC = 1, WQ_K_EXP = 2, WQ_K_SIN = 3 } wq_k_kind;
+typedef struct {
+  int32_t kind; /* wq_k_kind */
+  double a, b;
+} wq_conductivity;
+
+/* assemble_tangent: for the spline fields T, Tdot (device double[n_rows], coefficients
+ * of N_j), with T_q = T(x_q), grad T(x_q), Tdot(x_q) at every WQ point and k_q = k(T_q):
+ *   S_ij = sum_{q in Q_i} [inv_theta_dt w^0_iq N_j(x_q)
+ *                          + k_q (w^x_iq dN_j/dx(x_q) + w^y_iq dN_j/dy(x_q))]   (Eq. 36)
+ *   R_i  = sum_{q in Q_i} [w^0_iq (Tdot(x_q) - f_q) + k_q (w^x_iq dT/dx + w^y_iq dT/dy)]
+ * i.e. R = M Tdot + K[k_q] T - F with F_i = sum_q w^0_iq f_q (the WQ load vector).
+ * Needs the MASS, DX and DY weights. f_at_pts: device double[n_points] or NULL (f = 0).
+ * S_vals: device double[nnz] aligned with COL; R: device double[n_rows]. Only WQ_FP64.
+ * Asynchronous on `stream`; uses scratch owned by `pts` (allocated on the first call),
+ * so calls on the same handle must not overlap. */
+wq_status assemble_tangent(const wq_points* pts, const wq_weights* w, const double* T, const double* Tdot,
+                           double inv_theta_dt, wq_conductivity k, const double* f_at_pts, void* S_vals,
+                           double* R, wq_precision prec, wq_stream stream);
+
+/* wq_heat_step: one time step t_n -> t_{n+1} (Section 5.2). Predictor
+ * T = T_n + (1 - theta) dt Tdot_n with T = g on prescribed DOFs; corrector iterations:
+ * Tdot = (T - T_n - (1 - theta) dt Tdot_n) / (theta dt), S and R by assemble_tangent,
+ * stop when ||R over free DOFs||_2 <= tol, else solve -S_ff dT_f = R_f (Eq. 33) by
+ * Jacobi-preconditioned conjugate gradients on the device and T_f += dT_f.
+ * Prescribed DOFs keep g (their rows and columns are eliminated).
+ *   dirichlet: device uint8[n_rows], 1 = prescribed; g_next: device double[n_rows] or
+ *   NULL (prescribed values 0); f_at_pts: device double[n_points] (f at t_{n+1}) or NULL;
+ *   T, Tdot: device double[n_rows], in: T_n, Tdot_n; out: T_{n+1}, Tdot_{n+1};
+ *   S_vals: device double[nnz], receives the last tangent.
+ * Synchronises `stream` (convergence tests read norms on the host). Returns
+ * WQ_ENOCONV if Newton or PCG hit their caps (T, Tdot then hold the last iterate).
+ * Uses scratch owned by `pts`: calls on the same handle must not overlap. */
+typedef struct {
+  double dt, theta;     /* time step, trapezoidal parameter in (0, 1]                 */
+  wq_conductivity k;
+  double tol;           /* Newton stop: ||R_free||_2 <= tol (absolute)                */
+  int32_t max_newton;   /* Newton iteration cap                                       */
+  double cg_rtol;       /* PCG stop: ||r||_2 <= max(cg_rtol ||R_free||_2, tol / 10)  */
+  int32_t max_cg;       /* PCG iteration cap per solve                                */
+} wq_heat_params;
+typedef struct {
+  int32_t newton_iters; /* corrector solves taken                                     */
+  int32_t cg_iters;     /* PCG iterations, all solves                                 */
+  double residual0;     /* ||R_free||_2 after the predictor                           */
+  double residual;      /* final ||R_free||_2                                         */
+} wq_heat_report;
+wq_status wq_heat_step(const wq_points* pts, const wq_weights* w, const wq_heat_params* hp,
+                       const uint8_t* dirichlet, const double* g_next, const double* f_at_pts, double* T,
+                       double* Tdot, double* S_vals, wq_heat_report* rep, wq_stream stream);
+
 /* ------------------------------------------------------------------ kernel timing
  * Measurement aid. While enabled (per process), the library records a pair of HIP
  * events on the launch stream around each of its main kernels (basis evaluation,

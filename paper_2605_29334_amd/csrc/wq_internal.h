@@ -94,6 +94,9 @@ struct wq_points {
   wq::DBuf x /*double [2 np]*/, detJ /*double [np]*/;
   // per (cell, point, cell function)
   wq::DBuf DN, DX, DY, DL;
+  // scratch owned by the handle, allocated on first use: tangent point fields
+  // (4 x n_points doubles) and the Newton / PCG vectors of wq_heat_step
+  wq::DBuf tangent_ws, newton_ws;
 };
 
 struct wq_weights {

@@ -553,6 +553,7 @@ void release_points(wq_points* P) {
   dfree(P->soff); dfree(P->slot); dfree(P->kself); dfree(P->x); dfree(P->detJ);
   dfree(P->DN); dfree(P->DX); dfree(P->DY); dfree(P->DL);
   dfree(P->tile_eptr); dfree(P->tile_ent); dfree(P->tile_mem);
+  dfree(P->tangent_ws); dfree(P->newton_ws);
 }
 
 wq_status sync_flags(DBuf& flags, int* h, int n, hipStream_t st) {

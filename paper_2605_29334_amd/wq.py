@@ -44,6 +44,22 @@ class SolveReport(C.Structure):
                 ("min_kept_ratio", C.c_double), ("max_dropped_ratio", C.c_double)]
 
 
+class Conductivity(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("a", C.c_double), ("b", C.c_double)]
+
+
+class HeatParams(C.Structure):
+    _fields_ = [("dt", C.c_double), ("theta", C.c_double), ("k", Conductivity), ("tol", C.c_double),
+                ("max_newton", C.c_int32), ("cg_rtol", C.c_double), ("max_cg", C.c_int32)]
+
+
+class HeatReport(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("cg_iters", C.c_int32), ("residual0", C.c_double),
+                ("residual", C.c_double)]
+
+
+K_LINEAR, K_QUADRATIC, K_EXP, K_SIN = 0, 1, 2, 3
+
 _LIB = None
 
 
@@ -71,6 +87,8 @@ def _lib():
             "assemble_stiffness": ([P, P, P, P, C.c_int, P], C.c_int),
             "assemble_biharmonic": ([P, P, P, P, C.c_int, P], C.c_int),
             "assemble_mass_stiffness": ([P, P, P, P, P, P, C.c_int, P], C.c_int),
+            "assemble_tangent": ([P, P, P, P, D, Conductivity, P, P, P, C.c_int, P], C.c_int),
+            "wq_heat_step": ([P, P, C.POINTER(HeatParams), P, P, P, P, P, P, C.POINTER(HeatReport), P], C.c_int),
             "wq_timing_enable": ([C.c_int], None),
             "wq_timings": ([P, C.c_int], C.c_int),
             "wq_strerror": ([C.c_int], C.c_char_p),
@@ -90,7 +108,7 @@ def exported_symbols():
     return ["wq_mesh_create", "wq_mesh_destroy", "build_points", "build_points_with_s", "wq_points_destroy",
             "wq_points_size", "wq_points_info", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
             "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
-            "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
+            "assemble_tangent", "wq_heat_step", "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
 
 
 def _check(status, where):
@@ -264,6 +282,46 @@ def assemble_mass_stiffness(points, weights, c=None, k=None, mass_out=None, stif
                                           _ptr(mass_out), _ptr(stiff_out), prec, _stream(stream)),
            "assemble_mass_stiffness")
     return mass_out, stiff_out
+
+
+def _vec(t, n, dtype=torch.float64):
+    assert t.dtype == dtype and t.numel() == n and t.is_cuda and t.is_contiguous()
+    return t
+
+
+def assemble_tangent(points, weights, T, Tdot, inv_theta_dt, k=(K_QUADRATIC, 1.0, 1.0), f=None, S_out=None,
+                     R_out=None, stream=None):
+    """Eq. (36) tangent S (CSR values) and residual R at the fields T, Tdot."""
+    n = points.n_rows
+    S_out = _out(points, S_out, WQ_FP64)
+    if R_out is None:
+        R_out = torch.empty(n, dtype=torch.float64, device="cuda")
+    _vec(T, n), _vec(Tdot, n), _vec(R_out, n)
+    if f is not None:
+        _vec(f, points.n_points)
+    _check(_lib().assemble_tangent(points.h, weights.h, _ptr(T), _ptr(Tdot), float(inv_theta_dt),
+                                   Conductivity(*k), _ptr(f), _ptr(S_out), _ptr(R_out), WQ_FP64, _stream(stream)),
+           "assemble_tangent")
+    return S_out, R_out
+
+
+def heat_step(points, weights, dirichlet, T, Tdot, dt, theta=1.0, k=(K_QUADRATIC, 1.0, 1.0), f=None, g=None,
+              tol=1e-10, max_newton=50, cg_rtol=1e-6, max_cg=20000, S_out=None, stream=None):
+    """One time step of the nonlinear heat problem (Section 5.2); T and Tdot are
+    updated in place. Returns the Newton/PCG report as a dict."""
+    n = points.n_rows
+    _vec(dirichlet, n, torch.uint8), _vec(T, n), _vec(Tdot, n)
+    if f is not None:
+        _vec(f, points.n_points)
+    if g is not None:
+        _vec(g, n)
+    S_out = _out(points, S_out, WQ_FP64)
+    hp = HeatParams(float(dt), float(theta), Conductivity(*k), float(tol), int(max_newton), float(cg_rtol),
+                    int(max_cg))
+    rep = HeatReport()
+    _check(_lib().wq_heat_step(points.h, weights.h, C.byref(hp), _ptr(dirichlet), _ptr(g), _ptr(f), _ptr(T),
+                               _ptr(Tdot), _ptr(S_out), C.byref(rep), _stream(stream)), "wq_heat_step")
+    return {k_: getattr(rep, k_) for k_, _ in HeatReport._fields_}
 
 
 def timing_enable(on=True):
