@@ -49,7 +49,7 @@ typedef enum {
 typedef enum { WQ_FAM_MASS = 1, WQ_FAM_DX = 2, WQ_FAM_DY = 4, WQ_FAM_LAP = 8 } wq_family;
 
 /* Arithmetic of the row contraction. FP64 everywhere else, always. */
-typedef enum { WQ_FP64 = 0, WQ_SPLIT_FP16 = 1, WQ_SPLIT_BF16 = 2 } wq_precision;
+typedef enum { WQ_FP64 = 0, WQ_SPLIT_FP16 = 1, WQ_SPLIT_BF16 = 2, WQ_SLICED_FP16 = 3 } wq_precision;
 
 /* ------------------------------------------------------------------ input mesh
  * Control mesh and Bezier extraction of the spline space (Section 3). All arrays are
@@ -159,8 +159,19 @@ wq_status wq_rhs_get(const wq_weights* w, wq_family fam, double* dst_device, wq_
  *   assemble_mass_stiffness: both M and K in one pass over the weights.
  * coef_at_points: device double[n_points] or NULL (coefficient 1).
  * vals: device output aligned with COL, double[nnz] for WQ_FP64, float[nnz] for the
- * split precisions (operands split into two FP16 / three BF16 terms, products on MFMA
- * with FP32 accumulation). Asynchronous on `stream`. */
+ * low-precision contractions, which run the per-cell product (member rows x points) x
+ * (points x functions) on MFMA with FP32 accumulation; cells are summed in FP64:
+ *   WQ_SPLIT_FP16: each operand as two FP16 terms (22 bits; weights x coefficient scaled
+ *     per row and cell by a power of two, basis data per family), three MFMA products;
+ *   WQ_SPLIT_BF16: three BF16 terms (24 bits, no scaling), six MFMA products;
+ *   WQ_SLICED_FP16: four 10-bit slices per operand on a grid shared along the summed
+ *     index (row exponent for the weights, column exponent for the basis), so every
+ *     MFMA sum is exact; ten MFMA products, about 40 bits.
+ * The two split forms carry FP32 rounding relative to the sum of |terms|: where a
+ * contraction cancels (stiffness rows: oscillating derivative-family weights) their
+ * normwise error grows by that cancellation factor; the sliced form does not.
+ * Asynchronous on `stream`. The first low-precision call on a handle converts the basis
+ * data (allocates and synchronises). */
 wq_status assemble_mass(const wq_points* pts, const wq_weights* w, const double* coef_at_points,
                         void* vals, wq_precision prec, wq_stream stream);
 wq_status assemble_stiffness(const wq_points* pts, const wq_weights* w, const double* coef_at_points,

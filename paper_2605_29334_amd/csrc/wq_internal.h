@@ -97,6 +97,12 @@ struct wq_points {
   // scratch owned by the handle, allocated on first use: tangent point fields
   // (4 x n_points doubles) and the Newton / PCG vectors of wq_heat_step
   wq::DBuf tangent_ws, newton_ws;
+  // basis data split for the low-precision contraction (built on first use):
+  // FP16 x 2: uint32 per value (hi | lo << 16) of D * 2^-ds_exp[f];
+  // BF16 x 3: uint2 per value (hi | mid << 16, lo)
+  wq::DBuf DS[4];
+  int ds_prec = 0;
+  int ds_exp[4] = {0, 0, 0, 0};
 };
 
 struct wq_weights {

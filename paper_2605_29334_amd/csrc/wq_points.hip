@@ -554,6 +554,8 @@ void release_points(wq_points* P) {
   dfree(P->DN); dfree(P->DX); dfree(P->DY); dfree(P->DL);
   dfree(P->tile_eptr); dfree(P->tile_ent); dfree(P->tile_mem);
   dfree(P->tangent_ws); dfree(P->newton_ws);
+  for (int f = 0; f < 4; ++f) dfree(P->DS[f]);
+  P->ds_prec = 0;
 }
 
 wq_status sync_flags(DBuf& flags, int* h, int n, hipStream_t st) {

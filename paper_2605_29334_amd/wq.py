@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwq.so")
 
 WQ_FAM_MASS, WQ_FAM_DX, WQ_FAM_DY, WQ_FAM_LAP = 1, 2, 4, 8
-WQ_FP64, WQ_SPLIT_FP16, WQ_SPLIT_BF16 = 0, 1, 2
+WQ_FP64, WQ_SPLIT_FP16, WQ_SPLIT_BF16, WQ_SLICED_FP16 = 0, 1, 2, 3
 ARR_ROW_PTR, ARR_COL, ARR_QPTR, ARR_QIDX, ARR_ETYPE, ARR_S, ARR_X, ARR_DETJ = range(8)
 _ARR_DTYPE = {ARR_ROW_PTR: torch.int64, ARR_COL: torch.int32, ARR_QPTR: torch.int64, ARR_QIDX: torch.int32,
               ARR_ETYPE: torch.uint8, ARR_S: torch.uint8, ARR_X: torch.float64, ARR_DETJ: torch.float64}

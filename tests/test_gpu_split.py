@@ -1,0 +1,139 @@
+"""Low-precision assembly on MFMA against the FP64 oracle evaluated with the GPU's weights.
+
+Target: normwise relative error <= 1e-6 per matrix (max |A - A*| / max |A*|).
+* FP16 x 2 (22-bit operands, power-of-two scaling) and BF16 x 3 (24-bit operands) sum the
+  products of a cell in FP32, so their error is about 2^-24 times the sum of |terms|;
+  it meets 1e-6 where the contraction does not cancel (mass, biharmonic here) and is
+  bounded by 8 * 2^-24 * (cancellation factor) otherwise (stiffness: the derivative-
+  family weights oscillate; the factor max_ij sum_q |terms| / max |K| is computed here).
+* Sliced FP16 (four 10-bit slices per operand on a shared grid, exact MFMA sums,
+  about 40 bits) meets 1e-6 on every matrix.
+"""
+import numpy as np
+import pytest
+
+import fixtures as fx
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FAM = {"mass": 1, "x": 2, "y": 4, "lap": 8}
+
+
+def _wq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_29334_amd.wq as W
+    return W
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _case(F, families, lap):
+    W = _wq()
+    R = O.setup(F, families=families)
+    mesh = W.Mesh(F)
+    pts = W.Points(mesh, want_laplacian=lap)
+    wts = W.Weights(mesh, pts, sum(FAM[f] for f in families), tau=1e-12)
+    Wg = {f: _np(wts.weights(FAM[f])) for f in families}
+    x = O.point_values(R["data"], "x")
+    c = 1.0 + 0.5 * np.sin(2 * np.pi * x[:, 0]) * np.sin(2 * np.pi * x[:, 1])
+    k = 1.0 + 0.5 * np.cos(np.pi * x[:, 0]) * np.cos(np.pi * x[:, 1])
+    return {"F": F, "R": R, "W": W, "mesh": mesh, "pts": pts, "wts": wts, "Wg": Wg, "c": c, "k": k, "lap": lap}
+
+
+@pytest.fixture(scope="module")
+def grid12():
+    print("[gpu] split case grid12", flush=True)
+    return _case(fx.fixture_grid(12, displace=0.05, seed=3), ("mass", "x", "y", "lap"), True)
+
+
+@pytest.fixture(scope="module")
+def eps32():
+    print("[gpu] split case eps32", flush=True)
+    return _case(fx.fixture_eps(32, 0.02, (3, 5, 6), seed=5), ("mass", "x", "y"), False)
+
+
+@pytest.fixture(scope="module")
+def hs():
+    print("[gpu] split case half_strip", flush=True)
+    return _case(fx.fixture_half_strip(), ("mass", "x", "y", "lap"), True)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _cancellation(F, R, Wg, kind, coef):
+    """max over entries of sum_q |terms| divided by the largest |entry| of the matrix."""
+    pat, data = R["pat"], R["data"]
+    terms = {"mass": [("mass", "N")], "stiffness": [("x", "Nx"), ("y", "Ny")], "biharmonic": [("lap", "Lap")]}[kind]
+    tmax, vmax = 0.0, 0.0
+    for i in range(F["n_fn"]):
+        q0, q1 = pat["qptr"][i], pat["qptr"][i + 1]
+        cq = coef[pat["qidx"][q0:q1]]
+        v = 0.0
+        t = 0.0
+        for fam, key in terms:
+            A = O.local_matrix(F, pat, data, i, key)
+            v = v + A @ (cq * Wg[fam][q0:q1])
+            t = t + np.abs(A) @ np.abs(cq * Wg[fam][q0:q1])
+        tmax, vmax = max(tmax, np.max(t)), max(vmax, np.max(np.abs(v)))
+    return tmax / vmax
+
+
+@pytest.mark.parametrize("case", ["grid12", "eps32", "hs"])
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_split_precision_within_1e6(case, prec, request):
+    cs = request.getfixturevalue(case)
+    F, R, W, pts, wts, Wg = cs["F"], cs["R"], cs["W"], cs["pts"], cs["wts"], cs["Wg"]
+    pat, data = R["pat"], R["data"]
+    c, k = cs["c"], cs["k"]
+    tc, tk = torch.tensor(c, device="cuda"), torch.tensor(k, device="cuda")
+    ref = {"M": O.wq_assemble(F, pat, data, Wg, "mass", c), "K": O.wq_assemble(F, pat, data, Wg, "stiffness", k)}
+    got = {"M": _np(W.assemble_mass(pts, wts, tc, prec=prec)), "K": _np(W.assemble_stiffness(pts, wts, tk, prec=prec))}
+    m2, k2 = W.assemble_mass_stiffness(pts, wts, tc, tk, prec=prec)
+    got["M_fused"], got["K_fused"] = _np(m2), _np(k2)
+    ref["M_fused"], ref["K_fused"] = ref["M"], ref["K"]
+    if cs["lap"]:
+        ref["B"] = O.wq_assemble(F, pat, data, Wg, "biharmonic", k)
+        got["B"] = _np(W.assemble_biharmonic(pts, wts, tk, prec=prec))
+    errs = {key: _rel(got[key], ref[key]) for key in ref}
+    name = {1: "fp16x2", 2: "bf16x3", 3: "sliced"}[prec]
+    canc = {"M": _cancellation(F, R, Wg, "mass", c), "K": _cancellation(F, R, Wg, "stiffness", k)}
+    if cs["lap"]:
+        canc["B"] = _cancellation(F, R, Wg, "biharmonic", k)
+    print(f"[gpu] {case} {name} rel err per matrix: " + ", ".join(f"{k_}={v:.2e}" for k_, v in errs.items())
+          + "; cancellation factors " + ", ".join(f"{k_}={v:.1f}" for k_, v in canc.items()))
+    for key, v in errs.items():
+        bound = 1e-6 if prec == 3 else max(1e-6, 8 * 2.0 ** -24 * canc[key[0]])
+        assert v <= bound, (key, v, bound)
+    # fused and single-matrix kernels compute the same products in the same order
+    assert np.array_equal(got["M"], got["M_fused"]) and np.array_equal(got["K"], got["K_fused"])
+
+
+def test_split_precision_deterministic(eps32):
+    W, pts, wts = eps32["W"], eps32["pts"], eps32["wts"]
+    tk = torch.tensor(eps32["k"], device="cuda")
+    for prec in (1, 2, 3):
+        a = _np(W.assemble_stiffness(pts, wts, tk, prec=prec))
+        b = _np(W.assemble_stiffness(pts, wts, tk, prec=prec))
+        assert np.array_equal(a, b)
+
+
+def test_tangent_rejects_split_precision(eps32):
+    W, pts, wts = eps32["W"], eps32["pts"], eps32["wts"]
+    n = pts.n_rows
+    T = torch.zeros(n, dtype=torch.float64, device="cuda")
+    S = torch.empty(pts.nnz, dtype=torch.float64, device="cuda")
+    R = torch.empty(n, dtype=torch.float64, device="cuda")
+    lib = W._lib()
+    import ctypes as C
+    st = lib.assemble_tangent(pts.h, wts.h, W._ptr(T), W._ptr(T), 1.0, W.Conductivity(1, 1.0, 1.0), None,
+                              W._ptr(S), W._ptr(R), 1, W._stream(None))
+    assert st == -1
+    del C
