@@ -211,32 +211,78 @@ wq_status assemble_tangent(const wq_points* pts, const wq_weights* w, const doub
  * T = T_n + (1 - theta) dt Tdot_n with T = g on prescribed DOFs; corrector iterations:
  * Tdot = (T - T_n - (1 - theta) dt Tdot_n) / (theta dt), S and R by assemble_tangent,
  * stop when ||R over free DOFs||_2 <= tol, else solve -S_ff dT_f = R_f (Eq. 33) by
- * Jacobi-preconditioned conjugate gradients on the device and T_f += dT_f.
+ * Jacobi-preconditioned BiCGStab on the device (with a variable conductivity the WQ
+ * tangent is not symmetric: each row is integrated with its own weights) and T_f += dT_f.
  * Prescribed DOFs keep g (their rows and columns are eliminated).
  *   dirichlet: device uint8[n_rows], 1 = prescribed; g_next: device double[n_rows] or
  *   NULL (prescribed values 0); f_at_pts: device double[n_points] (f at t_{n+1}) or NULL;
  *   T, Tdot: device double[n_rows], in: T_n, Tdot_n; out: T_{n+1}, Tdot_{n+1};
  *   S_vals: device double[nnz], receives the last tangent.
  * Synchronises `stream` (convergence tests read norms on the host). Returns
- * WQ_ENOCONV if Newton or PCG hit their caps (T, Tdot then hold the last iterate).
+ * WQ_ENOCONV if Newton or BiCGStab hit their caps (T, Tdot then hold the last iterate).
  * Uses scratch owned by `pts`: calls on the same handle must not overlap. */
 typedef struct {
   double dt, theta;     /* time step, trapezoidal parameter in (0, 1]                 */
   wq_conductivity k;
   double tol;           /* Newton stop: ||R_free||_2 <= tol (absolute)                */
   int32_t max_newton;   /* Newton iteration cap                                       */
-  double cg_rtol;       /* PCG stop: ||r||_2 <= max(cg_rtol ||R_free||_2, tol / 10)  */
-  int32_t max_cg;       /* PCG iteration cap per solve                                */
+  double cg_rtol;       /* Krylov stop: ||r||_2 <= max(cg_rtol ||R_free||_2, tol/10) */
+  int32_t max_cg;       /* Krylov iteration cap per solve                             */
 } wq_heat_params;
 typedef struct {
   int32_t newton_iters; /* corrector solves taken                                     */
-  int32_t cg_iters;     /* PCG iterations, all solves                                 */
+  int32_t cg_iters;     /* BiCGStab iterations, all solves                            */
   double residual0;     /* ||R_free||_2 after the predictor                           */
   double residual;      /* final ||R_free||_2                                         */
 } wq_heat_report;
 wq_status wq_heat_step(const wq_points* pts, const wq_weights* w, const wq_heat_params* hp,
                        const uint8_t* dirichlet, const double* g_next, const double* f_at_pts, double* T,
                        double* Tdot, double* S_vals, wq_heat_report* rep, wq_stream stream);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop for the nonlinear heat problem of Section 5 on meshes that arrive over
+ * time (the paper's setting of repeated assembly on fixed domains, many domains).
+ * A request carries a mesh, its prescribed DOFs (value 0), heat parameters and a number
+ * of time steps from T = Tdot = 0; the server builds the points and the MASS/DX/DY
+ * weights, runs the steps with wq_heat_step (source: none, or the manufactured
+ * f = d(T*)/dt - div(k(T*) grad T*) for T* = (1 - e^{-lambda t}) sin(pi x) sin(pi y)) and
+ * copies the final T to the caller's host buffer.
+ * Admission: requests start in arrival order as soon as a slot is free and their HBM
+ * estimate (from the mesh sizes) fits in the budget next to the running ones; each slot
+ * is a host thread with its own non-blocking stream of default priority, so admitted
+ * requests overlap on the device. Results do not depend on what else runs (the kernels
+ * use fixed summation orders).
+ *   wq_server_start: budget in bytes, 1..16 slots; the current device is used.
+ *   wq_server_submit: copies the request's host arrays; T_out (host double[n_fn]) must
+ *     stay valid until the request completes. WQ_ENOMEM if the estimate alone exceeds
+ *     the budget. Returns a ticket.
+ *   wq_server_poll: 1 = done (result copied to *out, ticket released), 0 = pending
+ *     (wait = 0), negative = bad ticket. wait != 0 blocks until done.
+ *   wq_server_stop: finishes queued and running requests, then frees the server.
+ * Times are seconds since wq_server_start. */
+typedef struct wq_server wq_server;
+typedef enum { WQ_SOURCE_NONE = 0, WQ_SOURCE_MANUFACTURED = 1 } wq_source;
+typedef struct {
+  wq_mesh_desc mesh;          /* host arrays, copied at submit                           */
+  const uint8_t* dirichlet;   /* host uint8[n_fn], 1 = prescribed (value 0)              */
+  wq_heat_params heat;
+  int32_t n_steps;
+  int32_t source;             /* wq_source                                               */
+  double lambda;              /* manufactured source rate                                */
+} wq_request;
+typedef struct {
+  int32_t status;             /* wq_status of the whole request                          */
+  int32_t newton_iters;       /* corrector solves, all steps                             */
+  int32_t cg_iters;           /* BiCGStab iterations, all steps                          */
+  int64_t n_rows, nnz;
+  double residual;            /* final ||R_free||_2 of the last step                     */
+  double submitted, started, finished;
+  size_t hbm_estimate;        /* bytes charged against the budget while running          */
+} wq_result;
+wq_status wq_server_start(size_t hbm_budget_bytes, int32_t slots, wq_server** out);
+wq_status wq_server_submit(wq_server* server, const wq_request* req, double* T_out, int64_t* ticket);
+int wq_server_poll(wq_server* server, int64_t ticket, int wait, wq_result* out);
+void wq_server_stop(wq_server* server);
 
 /* ------------------------------------------------------------------ kernel timing
  * Measurement aid. While enabled (per process), the library records a pair of HIP

@@ -1,6 +1,6 @@
 // Nonlinear heat transfer time step (Section 5.2): predictor, corrector Newton iterations
 // with the WQ tangent of Eq. (36), and the linear solves of Eq. (33) by Jacobi-
-// preconditioned conjugate gradients on the device.
+// preconditioned BiCGStab on the device.
 #include "wq_internal.h"
 
 #include <cmath>
@@ -12,17 +12,18 @@ namespace {
 
 constexpr int RB = 256;        // threads per block of the vector kernels
 constexpr int ROW_LANES = 8;   // lanes per CSR row in the matrix-vector product
-constexpr int CHECK_EVERY = 8; // PCG iterations between host convergence checks
+constexpr int CHECK_EVERY = 4; // Krylov iterations between host convergence checks
 
 // scalar slots in the workspace
-enum { S_RZ = 0, S_RR, S_ALPHA, S_BETA, S_PQ, S_NORM, S_COUNT };
+enum { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_RR, S_NORM, S_SS, S_COUNT };
 
 struct Ws {
-  double *Tn, *Tdn, *R, *x, *r, *z, *p, *q, *d;
+  double *Tn, *Tdn, *R, *x, *r, *rh, *p, *v, *y, *s, *z, *t, *d;
   double* part;      // per-block partial sums (two lanes per block)
   double* sc;        // scalars
   unsigned* ticket;  // last-block counter (returns to 0 after each reduction)
 };
+constexpr int NVEC = 13;
 
 __device__ inline double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -64,6 +65,20 @@ __device__ inline void grid_reduce(double a, double b, Ws ws, double* sh, Fin fi
   }
 }
 
+__device__ inline double safe_div(double a, double b) { return b != 0.0 ? a / b : 0.0; }
+
+// y = S u on free rows (0 on prescribed rows; u is 0 on prescribed DOFs), 8 lanes per row;
+// returns the row value on lane 0 of the row group
+__device__ inline double row_product(int64_t i, int sub, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                                     const double* S, const uint8_t* dir, const double* u) {
+  double v = 0.0;
+  if (i < n) {
+    for (int64_t e = row_ptr[i] + sub; e < row_ptr[i + 1]; e += ROW_LANES) v += S[e] * u[col[e]];
+  }
+  for (int off = ROW_LANES / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return (i < n && !dir[i]) ? v : 0.0;
+}
+
 __global__ void k_predict(int64_t n, double* T, double* Td, Ws ws, double c1, const uint8_t* dir, const double* g) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -86,13 +101,15 @@ __global__ void k_norm_free(int64_t n, const double* R, const uint8_t* dir, Ws w
   grid_reduce(v * v, 0.0, ws, sh, [&](double a, double) { ws.sc[S_NORM] = a; });
 }
 
-// PCG start for S_ff x = -R_f: x = 0, r = -R (0 on prescribed DOFs), d = diag(S)
-// (1 on prescribed DOFs), z = r / d, p = z; rz = r.z, rr = r.r.
-__global__ void k_cg_init(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* S,
+// Jacobi-preconditioned BiCGStab for S_ff x = -R_f (the WQ tangent with a variable
+// conductivity is not symmetric: rows are integrated by their own weights).
+// Start: x = 0, r = r^ = -R (0 on prescribed DOFs), p = v = 0, d = diag(S) (1 on
+// prescribed DOFs); rho = r^.r, rr = r.r, alpha = omega = 1.
+__global__ void k_bi_init(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* S,
                           const uint8_t* dir, Ws ws) {
   __shared__ double sh[16];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  double rz = 0.0, rr = 0.0;
+  double rr = 0.0;
   if (i < n) {
     double di = 1.0, ri = 0.0;
     if (!dir[i]) {
@@ -108,66 +125,89 @@ __global__ void k_cg_init(int64_t n, const int64_t* row_ptr, const int32_t* col,
     ws.d[i] = di;
     ws.x[i] = 0.0;
     ws.r[i] = ri;
-    const double zi = ri / di;
-    ws.z[i] = zi;
-    ws.p[i] = zi;
-    rz = ri * zi;
+    ws.rh[i] = ri;
+    ws.p[i] = 0.0;
+    ws.v[i] = 0.0;
     rr = ri * ri;
   }
-  grid_reduce(rz, rr, ws, sh, [&](double a, double b) {
-    ws.sc[S_RZ] = a;
+  grid_reduce(rr, rr, ws, sh, [&](double a, double b) {
+    ws.sc[S_RHO] = a;
     ws.sc[S_RR] = b;
+    ws.sc[S_ALPHA] = 1.0;
+    ws.sc[S_OMEGA] = 1.0;
+    ws.sc[S_BETA] = 0.0;
   });
 }
 
-// q = S p on free rows (0 on prescribed rows; p is 0 on prescribed DOFs); alpha = rz / p.q
-__global__ void k_cg_spmv(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* S,
-                          const uint8_t* dir, Ws ws) {
+// p = r + beta (p - omega v); y = p / d
+__global__ void k_bi_dir(int64_t n, Ws ws) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double pi = ws.r[i] + ws.sc[S_BETA] * (ws.p[i] - ws.sc[S_OMEGA] * ws.v[i]);
+  ws.p[i] = pi;
+  ws.y[i] = pi / ws.d[i];
+}
+
+// v = S y; alpha = rho / (r^.v)
+__global__ void k_bi_sv(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* S, const uint8_t* dir,
+                        Ws ws) {
   __shared__ double sh[16];
   const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / ROW_LANES;
   const int sub = threadIdx.x % ROW_LANES;
-  double v = 0.0;
-  if (i < n) {
-    for (int64_t e = row_ptr[i] + sub; e < row_ptr[i + 1]; e += ROW_LANES) v += S[e] * ws.p[col[e]];
-  }
-  for (int off = ROW_LANES / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  double pq = 0.0;
+  const double vi = row_product(i, sub, n, row_ptr, col, S, dir, ws.y);
+  double a = 0.0;
   if (i < n && sub == 0) {
-    const double qi = dir[i] ? 0.0 : v;
-    ws.q[i] = qi;
-    pq = ws.p[i] * qi;
+    ws.v[i] = vi;
+    a = ws.rh[i] * vi;
   }
-  grid_reduce(pq, 0.0, ws, sh, [&](double a, double) {
-    ws.sc[S_PQ] = a;
-    ws.sc[S_ALPHA] = a != 0.0 ? ws.sc[S_RZ] / a : 0.0;
-  });
+  grid_reduce(a, 0.0, ws, sh, [&](double t, double) { ws.sc[S_ALPHA] = safe_div(ws.sc[S_RHO], t); });
 }
 
-// x += alpha p, r -= alpha q, z = r / d; beta = rz_new / rz
-__global__ void k_cg_update(int64_t n, Ws ws) {
+// x += alpha y; s = r - alpha v; z = s / d
+__global__ void k_bi_s(int64_t n, Ws ws) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double al = ws.sc[S_ALPHA];
+  ws.x[i] += al * ws.y[i];
+  const double si = ws.r[i] - al * ws.v[i];
+  ws.s[i] = si;
+  ws.z[i] = si / ws.d[i];
+}
+
+// t = S z; omega = (t.s) / (t.t)
+__global__ void k_bi_tz(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* S, const uint8_t* dir,
+                        Ws ws) {
+  __shared__ double sh[16];
+  const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / ROW_LANES;
+  const int sub = threadIdx.x % ROW_LANES;
+  const double ti = row_product(i, sub, n, row_ptr, col, S, dir, ws.z);
+  double ts = 0.0, tt = 0.0;
+  if (i < n && sub == 0) {
+    ws.t[i] = ti;
+    ts = ti * ws.s[i];
+    tt = ti * ti;
+  }
+  grid_reduce(ts, tt, ws, sh, [&](double a, double b) { ws.sc[S_OMEGA] = safe_div(a, b); });
+}
+
+// x += omega z; r = s - omega t; rho' = r^.r, rr = r.r; beta = (rho' / rho) (alpha / omega)
+__global__ void k_bi_r(int64_t n, Ws ws) {
   __shared__ double sh[16];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const double alpha = ws.sc[S_ALPHA];
-  double rz = 0.0, rr = 0.0;
+  const double om = ws.sc[S_OMEGA];
+  double a = 0.0, b = 0.0;
   if (i < n) {
-    ws.x[i] += alpha * ws.p[i];
-    const double ri = ws.r[i] - alpha * ws.q[i];
+    ws.x[i] += om * ws.z[i];
+    const double ri = ws.s[i] - om * ws.t[i];
     ws.r[i] = ri;
-    const double zi = ri / ws.d[i];
-    ws.z[i] = zi;
-    rz = ri * zi;
-    rr = ri * ri;
+    a = ws.rh[i] * ri;
+    b = ri * ri;
   }
-  grid_reduce(rz, rr, ws, sh, [&](double a, double b) {
-    ws.sc[S_BETA] = ws.sc[S_RZ] != 0.0 ? a / ws.sc[S_RZ] : 0.0;
-    ws.sc[S_RZ] = a;
-    ws.sc[S_RR] = b;
+  grid_reduce(a, b, ws, sh, [&](double rho1, double rr) {
+    ws.sc[S_BETA] = safe_div(rho1, ws.sc[S_RHO]) * safe_div(ws.sc[S_ALPHA], om);
+    ws.sc[S_RHO] = rho1;
+    ws.sc[S_RR] = rr;
   });
-}
-
-__global__ void k_cg_dir(int64_t n, Ws ws) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) ws.p[i] = ws.z[i] + ws.sc[S_BETA] * ws.p[i];
 }
 
 __global__ void k_add(int64_t n, double* T, const double* dT) {
@@ -193,7 +233,7 @@ extern "C" wq_status wq_heat_step(const wq_points* P, const wq_weights* w, const
   const int64_t n = P->n_rows;
   const unsigned nb = nblocks(n, RB);
   const unsigned nbs = nblocks(n * ROW_LANES, RB);
-  const size_t need = (9 * (size_t)n + 2 * (size_t)std::max(nb, nbs) + 8) * sizeof(double) + 64;
+  const size_t need = (NVEC * (size_t)n + 2 * (size_t)std::max(nb, nbs) + 8) * sizeof(double) + 64;
   wq_points* Pm = const_cast<wq_points*>(P);
   if (Pm->newton_ws.bytes < need) {
     WQ_TRY(dalloc(Pm->newton_ws, need));
@@ -201,16 +241,9 @@ extern "C" wq_status wq_heat_step(const wq_points* P, const wq_weights* w, const
   }
   Ws ws;
   double* base = Pm->newton_ws.as<double>();
-  ws.Tn = base;
-  ws.Tdn = base + n;
-  ws.R = base + 2 * n;
-  ws.x = base + 3 * n;
-  ws.r = base + 4 * n;
-  ws.z = base + 5 * n;
-  ws.p = base + 6 * n;
-  ws.q = base + 7 * n;
-  ws.d = base + 8 * n;
-  ws.part = base + 9 * n;
+  double** vec[NVEC] = {&ws.Tn, &ws.Tdn, &ws.R, &ws.x, &ws.r, &ws.rh, &ws.p, &ws.v, &ws.y, &ws.s, &ws.z, &ws.t, &ws.d};
+  for (int k = 0; k < NVEC; ++k) *vec[k] = base + k * n;
+  ws.part = base + NVEC * n;
   ws.sc = ws.part + 2 * std::max(nb, nbs);
   ws.ticket = (unsigned*)(ws.sc + 8);
   const double c1 = (1.0 - hp->theta) * hp->dt;
@@ -238,26 +271,29 @@ extern "C" wq_status wq_heat_step(const wq_points* P, const wq_weights* w, const
       status = WQ_ENOCONV;
       break;
     }
-    // PCG on S_ff dT_f = -R_f
+    // BiCGStab on S_ff dT_f = -R_f
     const double target = std::max(hp->cg_rtol * nr, 0.1 * hp->tol);
-    k_cg_init<<<nb, RB, 0, st>>>(n, row_ptr, col, (const double*)S_vals, dirichlet, ws);
+    k_bi_init<<<nb, RB, 0, st>>>(n, row_ptr, col, (const double*)S_vals, dirichlet, ws);
     WQ_HIP(hipGetLastError());
     double rr = 0.0;
     WQ_TRY(read_scalar(ws, S_RR, &rr, st));
     int k = 0;
     while (std::sqrt(rr) > target) {
       if (k >= hp->max_cg) {
-        set_error("wq_heat_step: PCG iteration cap reached, ||r|| = " + std::to_string(std::sqrt(rr)));
+        set_error("wq_heat_step: BiCGStab iteration cap reached, ||r|| = " + std::to_string(std::sqrt(rr)));
         status = WQ_ENOCONV;
         break;
       }
       for (int s = 0; s < CHECK_EVERY; ++s, ++k) {
-        k_cg_spmv<<<nbs, RB, 0, st>>>(n, row_ptr, col, (const double*)S_vals, dirichlet, ws);
-        k_cg_update<<<nb, RB, 0, st>>>(n, ws);
-        k_cg_dir<<<nb, RB, 0, st>>>(n, ws);
+        k_bi_dir<<<nb, RB, 0, st>>>(n, ws);
+        k_bi_sv<<<nbs, RB, 0, st>>>(n, row_ptr, col, (const double*)S_vals, dirichlet, ws);
+        k_bi_s<<<nb, RB, 0, st>>>(n, ws);
+        k_bi_tz<<<nbs, RB, 0, st>>>(n, row_ptr, col, (const double*)S_vals, dirichlet, ws);
+        k_bi_r<<<nb, RB, 0, st>>>(n, ws);
       }
       WQ_HIP(hipGetLastError());
       WQ_TRY(read_scalar(ws, S_RR, &rr, st));
+      WQ_CHECK(std::isfinite(rr), WQ_ENOCONV, "wq_heat_step: BiCGStab residual is not finite");
     }
     rp.cg_iters += k;
     if (status != WQ_OK) break;

@@ -1,0 +1,266 @@
+// Served nonlinear heat transfer: a request loop that runs whole WQ solves (points,
+// weights, Newton time steps of Section 5.2) for meshes as they arrive. Requests are
+// admitted in arrival order when a slot is free and their HBM estimate fits the budget;
+// each slot is a host thread with its own non-blocking stream, so admitted requests
+// overlap on the device. All state of a request stays on the device until its final
+// temperature is copied out.
+#include "wq_internal.h"
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+using namespace wq;
+
+namespace {
+
+// f = dT*/dt - div(k(T*) grad T*) for T* = (1 - e^{-lam t}) sin(pi x) sin(pi y), with
+// div(k grad u) = k'(u) |grad u|^2 + k(u) Lap u.
+__global__ void k_manufactured_source(int64_t np, const double* __restrict__ x, double t, double lam,
+                                      wq_conductivity kc, double* __restrict__ f) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= np) return;
+  const double PI = 3.141592653589793;
+  const double e = exp(-lam * t), s = 1.0 - e;
+  const double sx = sin(PI * x[2 * q]), sy = sin(PI * x[2 * q + 1]);
+  const double cx = cos(PI * x[2 * q]), cy = cos(PI * x[2 * q + 1]);
+  const double u = s * sx * sy;
+  const double ux = s * PI * cx * sy, uy = s * PI * sx * cy;
+  const double lap = -2.0 * PI * PI * u;
+  double k, dk;
+  switch (kc.kind) {
+    case WQ_K_LINEAR: k = kc.a + kc.b * u; dk = kc.b; break;
+    case WQ_K_QUADRATIC: k = kc.a + kc.b * u * u; dk = 2.0 * kc.b * u; break;
+    case WQ_K_EXP: k = kc.a * exp(kc.b * u); dk = kc.b * k; break;
+    default: k = kc.a * sin(kc.b * u); dk = kc.a * kc.b * cos(kc.b * u); break;
+  }
+  f[q] = lam * e * sx * sy - (dk * (ux * ux + uy * uy) + k * lap);
+}
+
+struct Request {
+  int64_t id = 0;
+  // deep copies of the host inputs
+  std::vector<int32_t> face_vtx, ext_fn;
+  std::vector<uint8_t> split, dirichlet;
+  std::vector<int64_t> ext_ptr, coef_ptr;
+  std::vector<double> coef, ctrl;
+  wq_mesh_desc desc{};
+  wq_heat_params heat{};
+  int32_t n_steps = 0, source = 0;
+  double lambda = 0;
+  double* T_out = nullptr;
+  size_t est = 0;
+  wq_result res{};
+  bool done = false;
+};
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct wq_server {
+  int device = 0;
+  size_t budget = 0, in_use = 0;
+  bool stopping = false;
+  int64_t next_id = 1;
+  std::deque<Request*> queue;
+  std::map<int64_t, Request*> all;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::vector<std::thread> workers;
+  std::chrono::steady_clock::time_point t0;
+};
+
+namespace {
+
+// HBM estimate of one request from its input sizes: per face of the control mesh about
+// 4 points x (basis values of ~16 functions x 3 arrays + weights x 3) + CSR values and
+// pattern + tile records, bounded generously, plus the Newton/PCG vectors.
+size_t hbm_estimate(const wq_mesh_desc& d) {
+  return (size_t)16384 * (size_t)d.nf + (size_t)256 * (size_t)d.n_fn + ((size_t)8 << 20);
+}
+
+wq_status run_request(Request* r, hipStream_t st) {
+  wq_mesh* mesh = nullptr;
+  wq_points* pts = nullptr;
+  wq_weights* w = nullptr;
+  DBuf T, Td, S, dir, f;
+  wq_status s = wq_mesh_create(&r->desc, &mesh);
+  int64_t n = 0, nnz = 0, np = 0;
+  if (s == WQ_OK) s = build_points(mesh, 0, st, &pts, &n, &nnz, &np);
+  if (s == WQ_OK) s = solve_weights(mesh, pts, WQ_FAM_MASS | WQ_FAM_DX | WQ_FAM_DY, 1e-12, st, &w, nullptr);
+  if (s == WQ_OK) s = dalloc_n<double>(T, n);
+  if (s == WQ_OK) s = dalloc_n<double>(Td, n);
+  if (s == WQ_OK) s = dalloc_n<double>(S, nnz);
+  if (s == WQ_OK) s = dalloc_n<uint8_t>(dir, n);
+  if (s == WQ_OK && r->source) s = dalloc_n<double>(f, np);
+  if (s == WQ_OK) {
+    if (hipMemsetAsync(T.p, 0, n * sizeof(double), st) != hipSuccess ||
+        hipMemsetAsync(Td.p, 0, n * sizeof(double), st) != hipSuccess ||
+        hipMemcpyAsync(dir.p, r->dirichlet.data(), n, hipMemcpyHostToDevice, st) != hipSuccess)
+      s = WQ_EDEVICE;
+  }
+  r->res.n_rows = n;
+  r->res.nnz = nnz;
+  for (int step = 0; s == WQ_OK && step < r->n_steps; ++step) {
+    const double t1 = r->heat.dt * (step + 1);
+    if (r->source) {
+      k_manufactured_source<<<nblocks(np, 256), 256, 0, st>>>(np, pts->x.as<double>(), t1, r->lambda, r->heat.k,
+                                                               f.as<double>());
+      if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
+    }
+    wq_heat_report rep{};
+    if (s == WQ_OK)
+      s = wq_heat_step(pts, w, &r->heat, dir.as<uint8_t>(), nullptr, r->source ? f.as<double>() : nullptr,
+                       T.as<double>(), Td.as<double>(), S.as<double>(), &rep, (wq_stream)st);
+    r->res.newton_iters += rep.newton_iters;
+    r->res.cg_iters += rep.cg_iters;
+    r->res.residual = rep.residual;
+  }
+  if (s == WQ_OK && r->T_out) {
+    if (hipMemcpyAsync(r->T_out, T.p, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      s = WQ_EDEVICE;
+  }
+  (void)hipStreamSynchronize(st);
+  dfree(T);
+  dfree(Td);
+  dfree(S);
+  dfree(dir);
+  dfree(f);
+  wq_weights_destroy(w);
+  wq_points_destroy(pts);
+  wq_mesh_destroy(mesh);
+  return s;
+}
+
+void worker(wq_server* sv) {
+  (void)hipSetDevice(sv->device);
+  hipStream_t st = nullptr;
+  const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  for (;;) {
+    Request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      // FIFO admission: the oldest request starts as soon as its estimate fits
+      sv->cv_work.wait(lk, [&] {
+        return (sv->stopping && sv->queue.empty()) ||
+               (!sv->queue.empty() && sv->in_use + sv->queue.front()->est <= sv->budget);
+      });
+      if (sv->queue.empty()) break;
+      r = sv->queue.front();
+      sv->queue.pop_front();
+      sv->in_use += r->est;
+      r->res.started = now_s(sv->t0);
+    }
+    const wq_status s = have_stream ? run_request(r, st) : WQ_EDEVICE;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->in_use -= r->est;
+      r->res.status = s;
+      r->res.finished = now_s(sv->t0);
+      r->done = true;
+    }
+    sv->cv_done.notify_all();
+    sv->cv_work.notify_all();
+  }
+  if (have_stream) (void)hipStreamDestroy(st);
+}
+
+}  // namespace
+
+extern "C" wq_status wq_server_start(size_t hbm_budget_bytes, int32_t slots, wq_server** out) {
+  WQ_CHECK(out && slots >= 1 && slots <= 16 && hbm_budget_bytes > 0, WQ_EINVAL,
+           "wq_server_start: need 1..16 slots and a positive budget");
+  wq_server* sv = new wq_server();
+  WQ_HIP(hipGetDevice(&sv->device));
+  sv->budget = hbm_budget_bytes;
+  sv->t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker, sv);
+  *out = sv;
+  return WQ_OK;
+}
+
+extern "C" wq_status wq_server_submit(wq_server* sv, const wq_request* q, double* T_out, int64_t* ticket) {
+  WQ_CHECK(sv && q && ticket, WQ_EINVAL, "wq_server_submit: null argument");
+  const wq_mesh_desc& d = q->mesh;
+  WQ_CHECK(d.nf > 0 && d.n_fn > 0 && d.face_vtx && d.split && d.ext_ptr && d.ext_fn && d.coef_ptr && d.coef && d.ctrl &&
+               q->dirichlet,
+           WQ_EINVAL, "wq_server_submit: incomplete request");
+  WQ_CHECK(q->n_steps >= 0 && q->heat.dt > 0 && q->heat.theta > 0 && q->heat.theta <= 1, WQ_EINVAL,
+           "wq_server_submit: bad time stepping");
+  Request* r = new Request();
+  r->face_vtx.assign(d.face_vtx, d.face_vtx + 4 * (size_t)d.nf);
+  r->split.assign(d.split, d.split + d.nf);
+  r->ext_ptr.assign(d.ext_ptr, d.ext_ptr + d.nf + 1);
+  r->ext_fn.assign(d.ext_fn, d.ext_fn + d.ext_ptr[d.nf]);
+  r->coef_ptr.assign(d.coef_ptr, d.coef_ptr + d.nf + 1);
+  r->coef.assign(d.coef, d.coef + d.coef_ptr[d.nf]);
+  r->ctrl.assign(d.ctrl, d.ctrl + 2 * (size_t)d.n_fn);
+  r->dirichlet.assign(q->dirichlet, q->dirichlet + d.n_fn);
+  r->desc = d;
+  r->desc.face_vtx = r->face_vtx.data();
+  r->desc.split = r->split.data();
+  r->desc.ext_ptr = r->ext_ptr.data();
+  r->desc.ext_fn = r->ext_fn.data();
+  r->desc.coef_ptr = r->coef_ptr.data();
+  r->desc.coef = r->coef.data();
+  r->desc.ctrl = r->ctrl.data();
+  r->heat = q->heat;
+  r->n_steps = q->n_steps;
+  r->source = q->source;
+  r->lambda = q->lambda;
+  r->T_out = T_out;
+  r->est = hbm_estimate(d);
+  r->res.hbm_estimate = r->est;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stopping || r->est > sv->budget) {
+      const bool too_big = r->est > sv->budget;
+      delete r;
+      WQ_CHECK(!too_big, WQ_ENOMEM, "wq_server_submit: the request's HBM estimate exceeds the whole budget");
+      WQ_CHECK(false, WQ_EINVAL, "wq_server_submit: server is stopping");
+    }
+    r->id = sv->next_id++;
+    r->res.submitted = now_s(sv->t0);
+    sv->all[r->id] = r;
+    sv->queue.push_back(r);
+    *ticket = r->id;
+  }
+  sv->cv_work.notify_all();
+  return WQ_OK;
+}
+
+extern "C" int wq_server_poll(wq_server* sv, int64_t ticket, int wait, wq_result* out) {
+  if (!sv || !out) return WQ_EINVAL;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return WQ_EINVAL;
+  Request* r = it->second;
+  if (wait) sv->cv_done.wait(lk, [&] { return r->done; });
+  if (!r->done) return 0;
+  *out = r->res;
+  sv->all.erase(it);
+  delete r;
+  return 1;
+}
+
+extern "C" void wq_server_stop(wq_server* sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stopping = true;
+  }
+  sv->cv_work.notify_all();
+  for (auto& t : sv->workers) t.join();
+  for (auto& kv : sv->all) delete kv.second;
+  delete sv;
+}

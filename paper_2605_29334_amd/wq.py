@@ -59,6 +59,18 @@ class HeatReport(C.Structure):
 
 
 K_LINEAR, K_QUADRATIC, K_EXP, K_SIN = 0, 1, 2, 3
+SOURCE_NONE, SOURCE_MANUFACTURED = 0, 1
+
+
+class Request(C.Structure):
+    _fields_ = [("mesh", MeshDesc), ("dirichlet", C.c_void_p), ("heat", HeatParams), ("n_steps", C.c_int32),
+                ("source", C.c_int32), ("lam", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32), ("cg_iters", C.c_int32), ("n_rows", C.c_int64),
+                ("nnz", C.c_int64), ("residual", C.c_double), ("submitted", C.c_double), ("started", C.c_double),
+                ("finished", C.c_double), ("hbm_estimate", C.c_size_t)]
 
 _LIB = None
 
@@ -89,6 +101,10 @@ def _lib():
             "assemble_mass_stiffness": ([P, P, P, P, P, P, C.c_int, P], C.c_int),
             "assemble_tangent": ([P, P, P, P, D, Conductivity, P, P, P, C.c_int, P], C.c_int),
             "wq_heat_step": ([P, P, C.POINTER(HeatParams), P, P, P, P, P, P, C.POINTER(HeatReport), P], C.c_int),
+            "wq_server_start": ([C.c_size_t, C.c_int32, P], C.c_int),
+            "wq_server_submit": ([P, C.POINTER(Request), P, P], C.c_int),
+            "wq_server_poll": ([P, C.c_int64, C.c_int, C.POINTER(Result)], C.c_int),
+            "wq_server_stop": ([P], None),
             "wq_timing_enable": ([C.c_int], None),
             "wq_timings": ([P, C.c_int], C.c_int),
             "wq_strerror": ([C.c_int], C.c_char_p),
@@ -108,7 +124,8 @@ def exported_symbols():
     return ["wq_mesh_create", "wq_mesh_destroy", "build_points", "build_points_with_s", "wq_points_destroy",
             "wq_points_size", "wq_points_info", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
             "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
-            "assemble_tangent", "wq_heat_step", "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
+            "assemble_tangent", "wq_heat_step", "wq_server_start", "wq_server_submit", "wq_server_poll",
+            "wq_server_stop", "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
 
 
 def _check(status, where):
@@ -322,6 +339,68 @@ def heat_step(points, weights, dirichlet, T, Tdot, dt, theta=1.0, k=(K_QUADRATIC
     _check(_lib().wq_heat_step(points.h, weights.h, C.byref(hp), _ptr(dirichlet), _ptr(g), _ptr(f), _ptr(T),
                                _ptr(Tdot), _ptr(S_out), C.byref(rep), _stream(stream)), "wq_heat_step")
     return {k_: getattr(rep, k_) for k_, _ in HeatReport._fields_}
+
+
+def _mesh_desc(fx, keep):
+    keep.update({
+        "face_vtx": np.ascontiguousarray(fx["face_vtx"], dtype=np.int32),
+        "split": np.ascontiguousarray(fx["split"], dtype=np.uint8),
+        "ext_ptr": np.ascontiguousarray(fx["ext_ptr"], dtype=np.int64),
+        "ext_fn": np.ascontiguousarray(fx["ext_fn"], dtype=np.int32),
+        "coef_ptr": np.ascontiguousarray(fx["coef_ptr"], dtype=np.int64),
+        "coef": np.ascontiguousarray(fx["coef"], dtype=np.float64),
+        "ctrl": np.ascontiguousarray(fx["ctrl"], dtype=np.float64),
+    })
+    return MeshDesc(int(fx["nv"]), int(len(keep["face_vtx"])), int(fx["n_fn"]),
+                    *[C.c_void_p(keep[n].ctypes.data) for n in ("face_vtx", "split", "ext_ptr", "ext_fn", "coef_ptr",
+                                                                "coef", "ctrl")])
+
+
+class Server:
+    """wq_server_*: requests of (mesh, prescribed DOFs, heat parameters, steps) served
+    with HBM-budget admission on `slots` concurrent streams."""
+
+    def __init__(self, hbm_budget_bytes, slots):
+        h = C.c_void_p()
+        _check(_lib().wq_server_start(int(hbm_budget_bytes), int(slots), C.byref(h)), "wq_server_start")
+        self.h = h
+        self._out = {}
+
+    def submit(self, fx, dirichlet, dt, n_steps, theta=1.0, k=(K_QUADRATIC, 1.0, 1.0), source=SOURCE_MANUFACTURED,
+               lam=5.0, tol=1e-10, max_newton=50, cg_rtol=1e-6, max_cg=20000):
+        keep = {}
+        desc = _mesh_desc(fx, keep)
+        keep["dirichlet"] = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        hp = HeatParams(float(dt), float(theta), Conductivity(*k), float(tol), int(max_newton), float(cg_rtol),
+                        int(max_cg))
+        req = Request(desc, C.c_void_p(keep["dirichlet"].ctypes.data), hp, int(n_steps), int(source), float(lam))
+        T = np.zeros(int(fx["n_fn"]), dtype=np.float64)
+        ticket = C.c_int64()
+        _check(_lib().wq_server_submit(self.h, C.byref(req), C.c_void_p(T.ctypes.data), C.byref(ticket)),
+               "wq_server_submit")
+        self._out[ticket.value] = T
+        return ticket.value
+
+    def poll(self, ticket, wait=True):
+        """None while pending; else (T, result dict)."""
+        res = Result()
+        st = _lib().wq_server_poll(self.h, int(ticket), 1 if wait else 0, C.byref(res))
+        if st < 0:
+            raise WQError(st, "wq_server_poll")
+        if st == 0:
+            return None
+        return self._out.pop(ticket), {k_: getattr(res, k_) for k_, _ in Result._fields_}
+
+    def close(self):
+        if self.h:
+            _lib().wq_server_stop(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def timing_enable(on=True):

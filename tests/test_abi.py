@@ -45,3 +45,29 @@ def test_binding_names_match_header():
 def test_strerror_is_host_only(lib):
     lib.wq_strerror.restype = ctypes.c_char_p
     assert lib.wq_strerror(-3).startswith(b"ill-posed")
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """Sizes and field offsets of the ABI structs, as a C compiler lays them out from
+    include/wq.h, equal the ctypes mirrors of the binding."""
+    import paper_2605_29334_amd.wq as W
+    structs = {"wq_mesh_desc": W.MeshDesc, "wq_timing": W.Timing, "wq_solve_report": W.SolveReport,
+               "wq_conductivity": W.Conductivity, "wq_heat_params": W.HeatParams, "wq_heat_report": W.HeatReport,
+               "wq_request": W.Request, "wq_result": W.Result}
+    rename = {"lam": "lambda"}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "wq.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {rename.get(f, f)}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
