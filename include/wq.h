@@ -284,6 +284,41 @@ wq_status wq_server_submit(wq_server* server, const wq_request* req, double* T_o
 int wq_server_poll(wq_server* server, int64_t ticket, int wait, wq_result* out);
 void wq_server_stop(wq_server* server);
 
+/* ------------------------------------------------------------------ batching
+ * Many independent meshes through one set of launches: wq_batch_create joins them into
+ * one disjoint union (vertex, face and function ids offset mesh by mesh, in the given
+ * order) on the device; wq_batch_build runs build_points and solve_weights once over the
+ * union, so the weight systems of all meshes are binned together by size and every
+ * mesh's rows, points, weights and matrix values equal those it gets alone (the method
+ * is local to each function's support). Mesh k owns rows [row0, row0 + n_rows), CSR
+ * entries [nnz0, nnz0 + nnz) (columns are union ids, i.e. offset by row0) and points
+ * [pt0, pt0 + n_points) of the union (wq_batch_info). wq_batch_points/weights return
+ * the union handles (owned by the batch) for the assemble_* calls and array queries.
+ * wq_batch_graph_assemble: mass + stiffness of all meshes as a HIP graph; the first call
+ * (or a call with other pointers, precision or stream) runs once eagerly, captures the
+ * launch and instantiates it; later calls replay it. The captured pointers are used as
+ * they are: update the coefficient buffers' contents in place between replays. The
+ * stream must be a created stream (capture is not possible on the null stream).
+ * wq_batch_build and the first graph call synchronise `stream`. */
+typedef struct wq_batch wq_batch;
+wq_status wq_batch_create(const wq_mesh_desc* meshes, int32_t n_meshes, wq_batch** out);
+wq_status wq_batch_build(wq_batch* batch, unsigned fam_mask, double tsvd_rel_cutoff, wq_stream stream,
+                         wq_solve_report* report);
+wq_status wq_batch_info(const wq_batch* batch, int32_t mesh, int64_t* row0, int64_t* n_rows, int64_t* nnz0,
+                        int64_t* nnz, int64_t* pt0, int64_t* n_points);
+wq_points* wq_batch_points(wq_batch* batch);
+wq_weights* wq_batch_weights(wq_batch* batch);
+wq_status wq_batch_graph_assemble(wq_batch* batch, const double* c_at_points, const double* k_at_points,
+                                  void* mass_vals, void* stiff_vals, wq_precision prec, wq_stream stream);
+void wq_batch_destroy(wq_batch* batch);
+
+/* wq_autotune_assembly: times the FP64 mass + stiffness assembly on `pts` for each
+ * candidate length of the runs of consecutive row tiles that one XCD takes in turn
+ * (4 .. 256), keeps the fastest in the handle (later assembly calls on it use it) and
+ * returns it with its median time in ms. Synchronises `stream`. */
+wq_status wq_autotune_assembly(wq_points* pts, const wq_weights* w, wq_stream stream, int32_t* chosen_chunk,
+                               double* best_ms);
+
 /* ------------------------------------------------------------------ kernel timing
  * Measurement aid. While enabled (per process), the library records a pair of HIP
  * events on the launch stream around each of its main kernels (basis evaluation,

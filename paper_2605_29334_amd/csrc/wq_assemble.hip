@@ -12,7 +12,6 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr int NXCD = 8;    // MI355X: workgroups are dispatched round-robin over 8 XCDs
-constexpr int CHUNK = 64;  // consecutive tiles per XCD turn
 
 // Families per kernel: K = 0 mass, 1 stiffness, 2 biharmonic, 3 mass + stiffness,
 // 4 tangent (Eq. (36)) + residual.
@@ -203,7 +202,7 @@ __device__ inline void accumulate(const Ent& e, int t, int sk, int rl, const dou
 // in point order) to racc[i_j]; R is written once per row.
 // Workgroups of one XCD take chunks of consecutive tiles (L2 reuse between neighbours).
 template <int K>
-__global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, int64_t per_xcd, int acc_stride,
+__global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, int64_t chunk, int acc_stride,
                                                    int mem_cap, int nd_cap, int nw_cap,
                                                    const int64_t* __restrict__ eptr, const int4* __restrict__ ent,
                                                    const int2* __restrict__ mem, const int64_t* __restrict__ sptr,
@@ -222,7 +221,7 @@ __global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, i
   int2* smem = (int2*)(rho + (RES ? nw_cap : 0));
   const int64_t b = blockIdx.x;
   const int64_t turn = b / NXCD;
-  const int64_t tile = (turn / CHUNK) * (NXCD * CHUNK) + (b % NXCD) * CHUNK + turn % CHUNK;
+  const int64_t tile = (turn / chunk) * (NXCD * chunk) + (b % NXCD) * chunk + turn % chunk;
   if (tile >= n_tiles) return;
   const int lane = threadIdx.x;
   const int64_t i0 = tile * TILE_ROWS;
@@ -323,8 +322,11 @@ wq_status launch(const wq_points* P, const wq_weights* w, Src S, double* o0, dou
     S.W[1] = w->W[1].as<double>();
     S.W[2] = w->W[2].as<double>();
   }
-  // grid covers whole rounds of NXCD * CHUNK tiles; blocks past the end exit
-  const int64_t per_xcd = ((P->n_tiles + NXCD * CHUNK - 1) / (NXCD * CHUNK)) * CHUNK;
+  // workgroup b runs on XCD b % 8 and takes, in turn, chunks of `chunk` consecutive tiles
+  // (L2 reuse between neighbouring rows on one XCD); the grid covers whole rounds of
+  // 8 * chunk tiles and blocks past the end exit
+  const int64_t chunk = P->asm_chunk;
+  const int64_t per_xcd = ((P->n_tiles + NXCD * chunk - 1) / (NXCD * chunk)) * chunk;
   static const char* names[5] = {"k_assemble_mass", "k_assemble_stiffness", "k_assemble_biharmonic",
                                   "k_assemble_mass_stiffness", "k_assemble_tangent"};
   if (lds > 64 * 1024)
@@ -337,7 +339,7 @@ wq_status launch(const wq_points* P, const wq_weights* w, Src S, double* o0, dou
   const int64_t outb = K == 4 ? P->nnz + P->n_rows : NACC * P->nnz;
   KTimer tm(names[K], 8 * (2 * N * sum_r + nc * P->n_points + outb), st);
   k_assemble<K><<<(unsigned)(per_xcd * NXCD), WAVE, lds, st>>>(
-      P->n_rows, P->n_tiles, per_xcd, P->max_tile_nnz, P->max_tile_mem, nd_cap, nw_cap, P->tile_eptr.as<int64_t>(),
+      P->n_rows, P->n_tiles, chunk, P->max_tile_nnz, P->max_tile_mem, nd_cap, nw_cap, P->tile_eptr.as<int64_t>(),
       P->tile_ent.as<int4>(), P->tile_mem.as<int2>(), P->supp_ptr.as<int64_t>(), P->slot.as<uint8_t>(),
       P->row_ptr.as<int64_t>(), S, o0, o1);
   tm.stop();
@@ -641,7 +643,7 @@ __device__ inline f4 contract_split(const double* sw, int nw_cap, const uint32_t
 // with the per-entry contraction on MFMA. K = 0 mass, 1 stiffness, 2 biharmonic,
 // 3 mass + stiffness. Output FP32.
 template <int K, int PREC>
-__global__ void __launch_bounds__(WAVE) k_assemble_split(int64_t n, int64_t n_tiles, int64_t per_xcd, int acc_stride,
+__global__ void __launch_bounds__(WAVE) k_assemble_split(int64_t n, int64_t n_tiles, int64_t chunk, int acc_stride,
                                                          int nd_cap, int nw_cap, const int64_t* __restrict__ eptr,
                                                          const int4* __restrict__ ent, const int2* __restrict__ mem,
                                                          const int64_t* __restrict__ sptr,
@@ -658,7 +660,7 @@ __global__ void __launch_bounds__(WAVE) k_assemble_split(int64_t n, int64_t n_ti
   int2* smem = (int2*)(sd + ((N * nd_cap * VW + 1) & ~1));
   const int64_t b = blockIdx.x;
   const int64_t turn = b / NXCD;
-  const int64_t tile = (turn / CHUNK) * (NXCD * CHUNK) + (b % NXCD) * CHUNK + turn % CHUNK;
+  const int64_t tile = (turn / chunk) * (NXCD * chunk) + (b % NXCD) * chunk + turn % chunk;
   if (tile >= n_tiles) return;
   const int lane = threadIdx.x;
   const int64_t i0 = tile * TILE_ROWS;
@@ -748,7 +750,8 @@ wq_status launch_split(const wq_points* P, const wq_weights* w, const double* c0
     S.W[a] = w->W[f].as<double>();
     S.eb[a] = PREC == WQ_SLICED_FP16 ? 0 : P->ds_exp[f];
   }
-  const int64_t per_xcd = ((P->n_tiles + NXCD * CHUNK - 1) / (NXCD * CHUNK)) * CHUNK;
+  const int64_t chunk = P->asm_chunk;
+  const int64_t per_xcd = ((P->n_tiles + NXCD * chunk - 1) / (NXCD * chunk)) * chunk;
   static const char* names[3][4] = {{"k_assemble_mass_fp16x2", "k_assemble_stiffness_fp16x2",
                                      "k_assemble_biharmonic_fp16x2", "k_assemble_mass_stiffness_fp16x2"},
                                     {"k_assemble_mass_bf16x3", "k_assemble_stiffness_bf16x3",
@@ -762,7 +765,7 @@ wq_status launch_split(const wq_points* P, const wq_weights* w, const double* c0
   const int64_t nc = (c0 ? 1 : 0) + (K == 3 && c1 ? 1 : 0);
   KTimer tm(names[PREC - 1][K], N * sum_r * (4 * VW + 8) + 8 * nc * P->n_points + 4 * NACC * P->nnz, st);
   k_assemble_split<K, PREC><<<(unsigned)(per_xcd * NXCD), WAVE, lds, st>>>(
-      P->n_rows, P->n_tiles, per_xcd, P->max_tile_nnz, nd_cap, nw_cap, P->tile_eptr.as<int64_t>(),
+      P->n_rows, P->n_tiles, chunk, P->max_tile_nnz, nd_cap, nw_cap, P->tile_eptr.as<int64_t>(),
       P->tile_ent.as<int4>(), P->tile_mem.as<int2>(), P->supp_ptr.as<int64_t>(), P->slot.as<uint8_t>(),
       P->row_ptr.as<int64_t>(), S, o0, o1);
   tm.stop();

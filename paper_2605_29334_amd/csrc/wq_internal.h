@@ -88,6 +88,7 @@ struct wq_points {
   int64_t n_tiles = 0, n_entries = 0;
   int32_t max_tile_nnz = 0, max_tile_ent = 0, max_tile_mem = 0;
   int32_t max_tile_nd = 0 /*max np*m of an entry*/, max_tile_nw = 0 /*max members*np*/;
+  int32_t asm_chunk = 64;  // consecutive tiles per XCD turn in the assembly launch (tunable)
   wq::DBuf tile_eptr /*int64 [tiles+1]*/, tile_ent /*int4 [entries]: dptr, pt0, mask|np<<16|m<<24, mbase*/,
       tile_mem /*int2 [pairs]: qoff | rowloc<<28, soff*/;
   // per point
@@ -139,6 +140,9 @@ __device__ inline void bern3(double t, double b[4], double d[4], double s[4]) {
 // exclusive scan of n int64 values in place on the device. *total receives the result at
 // index n-1, i.e. the sum of the first n-1 inputs (callers scan count+1 entries).
 wq_status exclusive_scan_i64(int64_t* d, int64_t n, int64_t* total, hipStream_t st);
+
+// whether kernel timing records are being taken (wq_timing_enable)
+bool timing_enabled();
 
 // kernel timing (wq_timing_enable): records events around a launch when enabled
 struct KTimer {

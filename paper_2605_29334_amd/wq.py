@@ -105,6 +105,14 @@ def _lib():
             "wq_server_submit": ([P, C.POINTER(Request), P, P], C.c_int),
             "wq_server_poll": ([P, C.c_int64, C.c_int, C.POINTER(Result)], C.c_int),
             "wq_server_stop": ([P], None),
+            "wq_batch_create": ([P, C.c_int32, P], C.c_int),
+            "wq_batch_build": ([P, U, D, P, P], C.c_int),
+            "wq_batch_info": ([P, C.c_int32, P, P, P, P, P, P], C.c_int),
+            "wq_batch_points": ([P], P),
+            "wq_batch_weights": ([P], P),
+            "wq_batch_graph_assemble": ([P, P, P, P, P, C.c_int, P], C.c_int),
+            "wq_batch_destroy": ([P], None),
+            "wq_autotune_assembly": ([P, P, P, P, P], C.c_int),
             "wq_timing_enable": ([C.c_int], None),
             "wq_timings": ([P, C.c_int], C.c_int),
             "wq_strerror": ([C.c_int], C.c_char_p),
@@ -125,7 +133,9 @@ def exported_symbols():
             "wq_points_size", "wq_points_info", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
             "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
             "assemble_tangent", "wq_heat_step", "wq_server_start", "wq_server_submit", "wq_server_poll",
-            "wq_server_stop", "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
+            "wq_server_stop", "wq_batch_create", "wq_batch_build", "wq_batch_info", "wq_batch_points",
+            "wq_batch_weights", "wq_batch_graph_assemble", "wq_batch_destroy", "wq_autotune_assembly",
+            "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
 
 
 def _check(status, where):
@@ -401,6 +411,80 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class _Borrowed:
+    """Points / weights handle owned by a batch (not destroyed by the wrapper)."""
+
+    def __init__(self, h, **kw):
+        self.h = h
+        self.__dict__.update(kw)
+
+    def get(self, what, stream=None):
+        return Points.get(self, what, stream)
+
+    def weights(self, fam, stream=None):
+        return Weights.weights(self, fam, stream)
+
+    def rhs(self, fam, stream=None):
+        return Weights.rhs(self, fam, stream)
+
+    def info(self):
+        return Points.info(self)
+
+
+class Batch:
+    """wq_batch_*: many meshes joined into one union and processed by one set of launches."""
+
+    def __init__(self, fixtures):
+        self._keep = [dict() for _ in fixtures]
+        descs = (MeshDesc * len(fixtures))(*[_mesh_desc(fx, k) for fx, k in zip(fixtures, self._keep)])
+        h = C.c_void_p()
+        _check(_lib().wq_batch_create(descs, len(fixtures), C.byref(h)), "wq_batch_create")
+        self.h = h
+        self.n_meshes = len(fixtures)
+        self.points = self.weights = None
+
+    def build(self, fam_mask, tau=1e-12, stream=None):
+        rep = SolveReport()
+        _check(_lib().wq_batch_build(self.h, int(fam_mask), float(tau), _stream(stream), C.byref(rep)),
+               "wq_batch_build")
+        self.report = {k: getattr(rep, k) for k, _ in SolveReport._fields_}
+        ph = C.c_void_p(_lib().wq_batch_points(self.h))
+        n = _lib().wq_points_size(ph, ARR_ROW_PTR) - 1
+        nnz = _lib().wq_points_size(ph, ARR_COL)
+        npt = _lib().wq_points_size(ph, ARR_X) // 2
+        self.points = _Borrowed(ph, n_rows=n, nnz=nnz, n_points=npt)
+        self.weights = _Borrowed(C.c_void_p(_lib().wq_batch_weights(self.h)), points=self.points)
+        return self
+
+    def info(self, k):
+        v = [C.c_int64() for _ in range(6)]
+        _check(_lib().wq_batch_info(self.h, int(k), *[C.byref(x) for x in v]), "wq_batch_info")
+        return dict(zip(("row0", "n_rows", "nnz0", "nnz", "pt0", "n_points"), [x.value for x in v]))
+
+    def graph_assemble(self, c, k, mass_out, stiff_out, prec=WQ_FP64, stream=None):
+        _check(_lib().wq_batch_graph_assemble(self.h, _ptr(c), _ptr(k), _ptr(mass_out), _ptr(stiff_out), int(prec),
+                                              _stream(stream)), "wq_batch_graph_assemble")
+
+    def close(self):
+        if self.h:
+            _lib().wq_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_assembly(points, weights, stream=None):
+    """Pick the assembly's XCD chunk length on `points` by measurement; returns (chunk, ms)."""
+    ch, ms = C.c_int32(), C.c_double()
+    _check(_lib().wq_autotune_assembly(points.h, weights.h, _stream(stream), C.byref(ch), C.byref(ms)),
+           "wq_autotune_assembly")
+    return ch.value, ms.value
 
 
 def timing_enable(on=True):

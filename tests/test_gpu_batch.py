@@ -1,0 +1,108 @@
+"""Batched meshes (wq_batch_*), the assembly HIP graph and the assembly autotuner.
+
+* Every mesh of a batch gets exactly what it gets alone: the same classification,
+  pattern, point sets (shifted by its offsets), weights and matrix values, bit for bit
+  (the method is local to each function's support and the kernels sum in fixed orders).
+* The captured graph reproduces the eager assembly on every replay, with eager work and
+  coefficient updates between the replays.
+* The autotuner's choice only reorders the schedule of tiles: values are unchanged.
+"""
+import numpy as np
+import pytest
+
+import fixtures as fx
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _wq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_29334_amd.wq as W
+    return W
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def batch():
+    W = _wq()
+    print("[gpu] batch of 5 meshes", flush=True)
+    pool = [fx.fixture_grid(8, displace=0.05, seed=11), fx.fixture_half_strip(),
+            fx.fixture_eps(32, 0.02, (3, 5, 6), seed=5), fx.fixture_grid(12, displace=0.05, seed=3),
+            fx.fixture_grid(10, displace=0.05, seed=7)]
+    B = W.Batch(pool).build(1 | 2 | 4)
+    return W, pool, B
+
+
+def _coef(x, shift):
+    c = 1 + 0.5 * torch.sin(2 * np.pi * x[:, 0] + shift) * torch.sin(2 * np.pi * x[:, 1])
+    k = 1 + 0.5 * torch.cos(np.pi * x[:, 0]) * torch.cos(np.pi * x[:, 1] + shift)
+    return c.contiguous(), k.contiguous()
+
+
+def test_each_mesh_equals_its_own_run(batch):
+    W, pool, B = batch
+    P, Wt = B.points, B.weights
+    x = P.get(W.ARR_X).reshape(-1, 2)
+    c, k = _coef(x, 0.3)
+    Mb, Kb = W.assemble_mass_stiffness(P, Wt, c, k)
+    rp, col = _np(P.get(W.ARR_ROW_PTR)), _np(P.get(W.ARR_COL))
+    qp, qi = _np(P.get(W.ARR_QPTR)), _np(P.get(W.ARR_QIDX))
+    wb = {f: _np(Wt.weights(f)) for f in (1, 2, 4)}
+    for m, F in enumerate(pool):
+        o = B.info(m)
+        mesh = W.Mesh(F)
+        pts = W.Points(mesh)
+        wts = W.Weights(mesh, pts, 1 | 2 | 4)
+        assert pts.n_rows == o["n_rows"] and pts.nnz == o["nnz"] and pts.n_points == o["n_points"]
+        r0, z0, p0 = o["row0"], o["nnz0"], o["pt0"]
+        rows = slice(r0, r0 + o["n_rows"] + 1)
+        np.testing.assert_array_equal(_np(pts.get(W.ARR_ROW_PTR)), rp[rows] - z0)
+        np.testing.assert_array_equal(_np(pts.get(W.ARR_COL)), col[z0:z0 + o["nnz"]] - r0)
+        q0 = qp[r0]
+        np.testing.assert_array_equal(_np(pts.get(W.ARR_QPTR)), qp[rows] - q0)
+        np.testing.assert_array_equal(_np(pts.get(W.ARR_QIDX)), qi[q0:qp[r0 + o["n_rows"]]] - p0)
+        for f in (1, 2, 4):
+            assert np.array_equal(_np(wts.weights(f)), wb[f][q0:qp[r0 + o["n_rows"]]]), (m, f)
+        cs, ks = c[p0:p0 + o["n_points"]].contiguous(), k[p0:p0 + o["n_points"]].contiguous()
+        M, K = W.assemble_mass_stiffness(pts, wts, cs, ks)
+        assert np.array_equal(_np(M), _np(Mb)[z0:z0 + o["nnz"]]), m
+        assert np.array_equal(_np(K), _np(Kb)[z0:z0 + o["nnz"]]), m
+    print(f"[gpu] batch: {B.n_meshes} meshes, {P.n_rows} rows, {P.nnz} nnz, report {B.report}")
+
+
+def test_graph_replays_match_eager(batch):
+    W, pool, B = batch
+    P, Wt = B.points, B.weights
+    x = P.get(W.ARR_X).reshape(-1, 2)
+    c, k = _coef(x, 0.0)
+    Mg = torch.empty(P.nnz, dtype=torch.float64, device="cuda")
+    Kg = torch.empty_like(Mg)
+    s = torch.cuda.Stream()  # capture needs a created stream
+    torch.cuda.synchronize()
+    for rep in range(4):
+        c2, k2 = _coef(x, 0.1 * rep)
+        c.copy_(c2)
+        k.copy_(k2)
+        torch.cuda.synchronize()
+        B.graph_assemble(c, k, Mg, Kg, stream=s)
+        s.synchronize()
+        Me, Ke = W.assemble_mass_stiffness(P, Wt, c, k)
+        torch.cuda.synchronize()
+        assert torch.equal(Mg, Me) and torch.equal(Kg, Ke), rep
+
+
+def test_autotune_changes_schedule_not_values(batch):
+    W, pool, B = batch
+    P, Wt = B.points, B.weights
+    M0, K0 = W.assemble_mass_stiffness(P, Wt)
+    chunk, ms = W.autotune_assembly(P, Wt)
+    print(f"[gpu] autotune: chunk {chunk}, {ms:.4f} ms")
+    assert chunk in (4, 8, 16, 32, 64, 128, 256) and ms > 0
+    M1, K1 = W.assemble_mass_stiffness(P, Wt)
+    assert torch.equal(M0, M1) and torch.equal(K0, K1)
