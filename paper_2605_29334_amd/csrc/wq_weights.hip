@@ -191,6 +191,26 @@ __global__ void k_sys_scatter(int64_t n, const uint8_t* bkt, const int64_t* star
   lists[start[b] + k] = (int32_t)i;
 }
 
+// Cross-lane moves inside a row of 16 lanes by DPP (VALU, no LDS round trip).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of G = 4, 8 or 16 lanes; every lane of a group gets the same
+// bits (quad_perm [1,0,3,2], then [2,3,0,1], then the mirrored quad, then the mirrored 8).
+template <int G>
+__device__ inline double group_sum(double v) {
+  static_assert(G == 4 || G == 8 || G == 16, "group of 4, 8 or 16 lanes");
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  if (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror: the other quad of the 8
+  if (G >= 16) v += dpp_f64<0x140>(v); // row_mirror: the other 8 of the row
+  return v;
+}
+
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -233,7 +253,6 @@ struct TsvdArgs {
 // sigma_l > tau sigma_max; c = S_t^{-1} U_t^T b; x_l = Z v_l; CGS2 QR of the kept x_l
 // with the forward substitution y = R^{-T} c carried along; w = Z Q y.
 // LPP lanes share a column pair; each holds EPL elements of both columns in registers.
-constexpr int TB = 256;
 
 __device__ inline double block_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -242,7 +261,7 @@ __device__ inline double block_sum(double v, double* red) {
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
   double s = 0.0;
-  for (int k = 0; k < TB / 64; ++k) s += red[k];
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
   return s;
 }
 
@@ -253,12 +272,12 @@ __device__ inline double block_max(double v, double* red) {
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
   double s = 0.0;
-  for (int k = 0; k < TB / 64; ++k) s = fmax(s, red[k]);
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s = fmax(s, red[k]);
   return s;
 }
 
-template <int LPP, int EPL>
-__global__ void __launch_bounds__(TB) k_tsvd(TsvdArgs a) {
+template <int LPP, int EPL, int NT>
+__global__ void __launch_bounds__(NT) k_tsvd(TsvdArgs a) {
   extern __shared__ double sh[];
   const int64_t sys = blockIdx.x;
   const int tid = threadIdx.x;
@@ -275,7 +294,7 @@ __global__ void __launch_bounds__(TB) k_tsvd(TsvdArgs a) {
   double* red = yv + n;             // 8
   int* keep = (int*)(red + 8);      // n + 1
   // 1. gather
-  for (int t = tid; t < n * ld; t += TB) Gm[t] = 0.0;
+  for (int t = tid; t < n * ld; t += NT) Gm[t] = 0.0;
   __syncthreads();
   {
     int moff = 0;
@@ -287,20 +306,20 @@ __global__ void __launch_bounds__(TB) k_tsvd(TsvdArgs a) {
       const double* Nc = a.DN + a.dptr[c];
       const uint8_t* sl = a.slot + a.soff[p];
       const int ks = a.kself[p];
-      for (int t = tid; t < np * m; t += TB) {
+      for (int t = tid; t < np * m; t += NT) {
         const int q = t / m, k = t - q * m;
         Gm[(size_t)sl[k] * ld + moff + q] = Dc[t];
       }
-      for (int q = tid; q < np; q += TB) z[moff + q] = Nc[q * m + ks];
+      for (int q = tid; q < np; q += NT) z[moff + q] = Nc[q * m + ks];
       moff += np;
     }
-    for (int l = tid; l < n; l += TB) Gm[(size_t)l * ld + r] = a.rhs[a.row_ptr[i] + l];
+    for (int l = tid; l < n; l += NT) Gm[(size_t)l * ld + r] = a.rhs[a.row_ptr[i] + l];
   }
   __syncthreads();
   // ||A||_F^2: columns below 1e-15 ||A||_F are numerical null space (dropped with a
   // 1000x margin by the 1e-12 cutoff); pairs involving them need no rotation
   double fro2 = 0.0;
-  for (int e = tid; e < n * r; e += TB) {
+  for (int e = tid; e < n * r; e += NT) {
     const int l = e / r, m = e - l * r;
     const double g = Gm[(size_t)l * ld + m];
     fro2 += g * g;
@@ -336,12 +355,9 @@ __global__ void __launch_bounds__(TB) k_tsvd(TsvdArgs a) {
             be += v[e] * v[e];
             ga += u[e] * v[e];
           }
-#pragma unroll
-          for (int off = 1; off < LPP; off <<= 1) {
-            al += __shfl_xor(al, off, 64);
-            be += __shfl_xor(be, off, 64);
-            ga += __shfl_xor(ga, off, 64);
-          }
+          al = group_sum<LPP>(al);
+          be = group_sum<LPP>(be);
+          ga = group_sum<LPP>(ga);
           if (ga * ga > 1e-30 * al * be && fmin(al, be) > negl) {
             // tan of the rotation angle: t = 2 g sgn(b - a) / (|b - a| + sqrt((b - a)^2 + 4 g^2))
             const double dba = be - al;
@@ -373,7 +389,7 @@ __global__ void __launch_bounds__(TB) k_tsvd(TsvdArgs a) {
   if (tid == 0) atomicMax(a.max_sweeps, sweeps);
   // 3. singular values and truncation
   double smax = 0.0;
-  for (int l = tid; l < n; l += TB) {
+  for (int l = tid; l < n; l += NT) {
     const double* g = Gm + (size_t)l * ld;
     double s2 = 0.0;
     for (int m = 0; m < r; ++m) s2 += g[m] * g[m];
@@ -400,39 +416,39 @@ __global__ void __launch_bounds__(TB) k_tsvd(TsvdArgs a) {
   __syncthreads();
   const int t = keep[n];
   // 4. c_k = (U^T b)_l / sigma_l (into yv), x_l = Z v_l = z * g_l / sigma_l
-  for (int k = tid; k < t; k += TB) {
+  for (int k = tid; k < t; k += NT) {
     const int l = keep[k];
     yv[k] = Gm[(size_t)l * ld + r] / sig[l];
   }
-  for (int e = tid; e < t * r; e += TB) {
+  for (int e = tid; e < t * r; e += NT) {
     const int k = e / r, m = e - k * r;
     const int l = keep[k];
     Gm[(size_t)l * ld + m] = z[m] * Gm[(size_t)l * ld + m] / sig[l];
   }
-  for (int m = tid; m < r; m += TB) wacc[m] = 0.0;
+  for (int m = tid; m < r; m += NT) wacc[m] = 0.0;
   __syncthreads();
   // 5. CGS2 on the kept columns; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk; w += y_k q_k
   constexpr int DL = 4;  // lanes per dot product
   for (int k = 0; k < t; ++k) {
     double* x = Gm + (size_t)keep[k] * ld;
-    for (int j = tid; j < k; j += TB) Rk[j] = 0.0;
+    for (int j = tid; j < k; j += NT) Rk[j] = 0.0;
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
-      for (int jb = 0; jb < k; jb += TB / DL) {
+      for (int jb = 0; jb < k; jb += NT / DL) {
         const int j = jb + tid / DL, s4 = tid % DL;
         double d = 0.0;
         if (j < k) {
           const double* qj = Gm + (size_t)keep[j] * ld;
           for (int m = s4; m < r; m += DL) d += qj[m] * x[m];
         }
-        for (int off = 1; off < DL; off <<= 1) d += __shfl_xor(d, off, 64);
+        d = group_sum<DL>(d);
         if (j < k && s4 == 0) {
           Rk[j] += d;
           sig[j] = d;  // this pass's coefficients (sig is free for j < k)
         }
       }
       __syncthreads();
-      for (int m = tid; m < r; m += TB) {
+      for (int m = tid; m < r; m += NT) {
         double v = x[m];
         for (int j = 0; j < k; ++j) v -= Gm[(size_t)keep[j] * ld + m] * sig[j];
         x[m] = v;
@@ -440,15 +456,15 @@ __global__ void __launch_bounds__(TB) k_tsvd(TsvdArgs a) {
       __syncthreads();
     }
     double nn2 = 0.0;
-    for (int m = tid; m < r; m += TB) nn2 += x[m] * x[m];
+    for (int m = tid; m < r; m += NT) nn2 += x[m] * x[m];
     const double nrm = sqrt(block_sum(nn2, red));
     double acc = 0.0;
-    for (int j = tid; j < k; j += TB) acc += Rk[j] * yv[j];
+    for (int j = tid; j < k; j += NT) acc += Rk[j] * yv[j];
     acc = block_sum(acc, red);
     const double yk = (yv[k] - acc) / nrm;  // yv[k] still holds c_k
     __syncthreads();
     const double inv = 1.0 / nrm;
-    for (int m = tid; m < r; m += TB) {
+    for (int m = tid; m < r; m += NT) {
       const double qm = x[m] * inv;
       x[m] = qm;
       wacc[m] += qm * yk;
@@ -457,7 +473,7 @@ __global__ void __launch_bounds__(TB) k_tsvd(TsvdArgs a) {
     __syncthreads();
   }
   double* W = a.W + a.qptr[i];
-  for (int m = tid; m < r; m += TB) W[m] = z[m] * wacc[m];
+  for (int m = tid; m < r; m += NT) W[m] = z[m] * wacc[m];
 }
 
 void release_weights(wq_weights* w) {
@@ -616,18 +632,21 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       ta.max_dropped = &R->max_dropped;
       ta.truncated = &R->truncated;
       ta.fail = &R->fail;
-      // lanes per column pair and register elements per lane
+      // 8 lanes per column pair; systems with more than 64 constraints (more than 32
+      // pairs) take 512 threads. EPL: register elements of a column per lane.
       const bool wide = mn > 64;
-      const int lpp = wide ? 4 : 8;
-      const int epl = (mr + lpp - 1) / lpp;
       const void* fn = nullptr;
       const char* kname = nullptr;  // timing record: the kernel instance
-      if (!wide && epl <= 8) fn = (const void*)k_tsvd<8, 8>, kname = "k_tsvd<8,8>";
-      else if (!wide && epl <= 16) fn = (const void*)k_tsvd<8, 16>, kname = "k_tsvd<8,16>";
-      else if (!wide) fn = (const void*)k_tsvd<8, 32>, kname = "k_tsvd<8,32>";
-      else if (epl <= 16) fn = (const void*)k_tsvd<4, 16>, kname = "k_tsvd<4,16>";
-      else if (epl <= 32) fn = (const void*)k_tsvd<4, 32>, kname = "k_tsvd<4,32>";
-      else fn = (const void*)k_tsvd<4, 64>, kname = "k_tsvd<4,64>";
+      int nt = 0;
+      {
+        const int epl = (mr + 7) / 8;
+        nt = wide ? 512 : 256;
+        if (!wide && epl <= 8) fn = (const void*)k_tsvd<8, 8, 256>, kname = "k_tsvd<8,8,256>";
+        else if (!wide && epl <= 16) fn = (const void*)k_tsvd<8, 16, 256>, kname = "k_tsvd<8,16,256>";
+        else if (!wide) fn = (const void*)k_tsvd<8, 32, 256>, kname = "k_tsvd<8,32,256>";
+        else if (epl <= 16) fn = (const void*)k_tsvd<8, 16, 512>, kname = "k_tsvd<8,16,512>";
+        else fn = (const void*)k_tsvd<8, 32, 512>, kname = "k_tsvd<8,32,512>";
+      }
       if (lds > 64 * 1024 &&
           hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
         s = WQ_EDEVICE;
@@ -635,7 +654,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       }
       KTimer tm(kname, (int64_t)bflops[b], st);
       void* args[] = {&ta};
-      if (hipLaunchKernel(fn, dim3((unsigned)ns), dim3(TB), args, lds, st) != hipSuccess) {
+      if (hipLaunchKernel(fn, dim3((unsigned)ns), dim3(nt), args, lds, st) != hipSuccess) {
         set_error("solve_weights: TSVD launch failed");
         s = WQ_EDEVICE;
       }
