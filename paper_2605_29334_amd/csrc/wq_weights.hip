@@ -222,7 +222,8 @@ __device__ inline unsigned long long dbits(double v) { return (unsigned long lon
 struct TsvdArgs {
   const int32_t* rows;
   int64_t nsys;
-  int ld;  // leading dimension (doubles) of a column in LDS, odd, >= r_max + 1
+  int ld;   // leading dimension (doubles) of a column of A^T in LDS, >= r_max + 1
+  int ldm;  // leading dimension of a column of R^T in LDS, >= n_max, <= ld
   int fam;
   double tau;
   const int64_t* sptr;
@@ -276,25 +277,47 @@ __device__ inline double block_max(double v, double* red) {
   return s;
 }
 
-template <int LPP, int EPL, int NT>
-__global__ void __launch_bounds__(NT) k_tsvd(TsvdArgs a) {
+// Weight system of one (row i, family): A (n x r, A[l][m] = D N_{S_i[l]}(x_{Q_i[m]})),
+// z (r, z_m = N_i(x_{Q_i[m]})), b (n). Truncated SVD of Eqs. (20)-(22) with the weighted
+// solution of Eqs. (5)-(6):
+//  1. A^T (r x n) is reduced by Householder QR with column pivoting, A^T P = Q1 R1
+//     (P permutes the constraints);
+//  2. one-sided Jacobi on the columns of M = R1^T (n x n): M J = W has orthogonal columns,
+//     sigma_k = |w_k|, and the left singular vectors of A are U = P W Sigma^-1 (Q1 is never
+//     needed). Jacobi on the triangular factor of a pivoted QR converges in fewer sweeps
+//     than on A^T itself, and its columns have length n instead of r;
+//  3. keep sigma_k > tau sigma_1; c_k = u_k^T b / sigma_k; V_t = A^T U_t Sigma_t^-1 (A
+//     re-read from the basis blocks), X = Z V_t;
+//  4. X = Q R (CGS2), y = R^-T c, w = Z Q y.
+// One workgroup per system; everything lives in LDS.
+template <int LPP, int EPR, int EPJ, int NT>
+__global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   extern __shared__ double sh[];
+  constexpr int NG = NT / LPP;  // lane groups
   const int64_t sys = blockIdx.x;
   const int tid = threadIdx.x;
+  const int g = tid / LPP, sub = tid % LPP;
   const int64_t i = a.rows[sys];
   const int n = (int)(a.row_ptr[i + 1] - a.row_ptr[i]);
   const int r = (int)(a.qptr[i + 1] - a.qptr[i]);
-  const int ld = a.ld;
-  double* Gm = sh;                  // n * ld
-  double* z = Gm + (size_t)n * ld;  // r
+  const int ld = a.ld, ldm = a.ldm;
+  double* G = sh;                   // n * ld: columns of A^T, later of X
+  double* z = G + (size_t)n * ld;   // r
   double* wacc = z + r;             // r
   double* sig = wacc + r;           // n
-  double* Rk = sig + n;             // n
+  double* Rk = sig + n;             // n: b (phases 1-3), CGS2 scratch (phase 4)
   double* yv = Rk + n;              // n
-  double* red = yv + n;             // 8
-  int* keep = (int*)(red + 8);      // n + 1
-  // 1. gather
-  for (int t = tid; t < n * ld; t += NT) Gm[t] = 0.0;
+  double* nrm = yv + n;             // n: trailing column norms^2 in the QR
+  double* red = nrm + n;            // 16
+  int* keep = (int*)(red + 16);     // n + 1
+  int* piv = keep + n + 1;          // n
+  int* pinv = piv + n;              // n
+  int* ptc = pinv + n;              // r: support entry of the point's cell
+  int* ptq = ptc + r;               // r: point index inside its cell
+  __shared__ int s_p;
+  __shared__ double s_tau, s_v0;
+  // ---- 1. gather A^T, z, b
+  for (int t = tid; t < n * ld; t += NT) G[t] = 0.0;
   __syncthreads();
   {
     int moff = 0;
@@ -308,49 +331,177 @@ __global__ void __launch_bounds__(NT) k_tsvd(TsvdArgs a) {
       const int ks = a.kself[p];
       for (int t = tid; t < np * m; t += NT) {
         const int q = t / m, k = t - q * m;
-        Gm[(size_t)sl[k] * ld + moff + q] = Dc[t];
+        G[(size_t)sl[k] * ld + moff + q] = Dc[t];
       }
-      for (int q = tid; q < np; q += NT) z[moff + q] = Nc[q * m + ks];
+      for (int q = tid; q < np; q += NT) {
+        z[moff + q] = Nc[q * m + ks];
+        ptc[moff + q] = (int)(p - a.sptr[i]);
+        ptq[moff + q] = q;
+      }
       moff += np;
     }
-    for (int l = tid; l < n; l += NT) Gm[(size_t)l * ld + r] = a.rhs[a.row_ptr[i] + l];
+    for (int l = tid; l < n; l += NT) {
+      Rk[l] = a.rhs[a.row_ptr[i] + l];
+      piv[l] = l;
+    }
   }
   __syncthreads();
-  // ||A||_F^2: columns below 1e-15 ||A||_F are numerical null space (dropped with a
+  // ||A||_F^2: columns of M below 1e-15 ||A||_F are numerical null space (dropped with a
   // 1000x margin by the 1e-12 cutoff); pairs involving them need no rotation
   double fro2 = 0.0;
   for (int e = tid; e < n * r; e += NT) {
     const int l = e / r, m = e - l * r;
-    const double g = Gm[(size_t)l * ld + m];
-    fro2 += g * g;
+    const double v = G[(size_t)l * ld + m];
+    fro2 += v * v;
   }
   const double negl = 1e-30 * block_sum(fro2, red);
-  // 2. one-sided Jacobi, circle-method ordering
+  // ---- 2. Householder QR of A^T with column pivoting (largest trailing norm first)
+  for (int l = g; l < n; l += NG) {
+    double s = 0.0;
+    for (int m = sub; m < r; m += LPP) s += G[(size_t)l * ld + m] * G[(size_t)l * ld + m];
+    s = group_sum<LPP>(s);
+    if (sub == 0) nrm[l] = s;
+  }
+  __syncthreads();
+  const int kmax = min(n, r);
+  for (int j = 0; j < kmax; ++j) {
+    if (tid < 64) {  // pivot: largest trailing norm, ties to the smaller index
+      double best = -1.0;
+      int bi = j;
+      for (int l = j + tid; l < n; l += 64)
+        if (nrm[l] > best) {
+          best = nrm[l];
+          bi = l;
+        }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) s_p = bi;
+    }
+    __syncthreads();
+    const int pv = s_p;
+    if (pv != j) {
+      for (int m = tid; m < r; m += NT) {
+        const double t0 = G[(size_t)j * ld + m];
+        G[(size_t)j * ld + m] = G[(size_t)pv * ld + m];
+        G[(size_t)pv * ld + m] = t0;
+      }
+      if (tid == 0) {
+        const double tn = nrm[j];
+        nrm[j] = nrm[pv];
+        nrm[pv] = tn;
+        const int tp = piv[j];
+        piv[j] = piv[pv];
+        piv[pv] = tp;
+      }
+      __syncthreads();
+    }
+    // reflector H = I - tau v v^T with v_j = 1 zeroing rows j+1.. of column j
+    double* cj = G + (size_t)j * ld;
+    if (tid < 64) {
+      double s = 0.0;
+      for (int m = j + 1 + tid; m < r; m += 64) s += cj[m] * cj[m];
+      s = wave_sum(s);
+      if (tid == 0) {
+        const double x0 = cj[j];
+        if (s == 0.0) {
+          s_tau = 0.0;
+          s_v0 = 1.0;
+        } else {
+          const double beta = -copysign(sqrt(x0 * x0 + s), x0);
+          s_tau = (beta - x0) / beta;
+          s_v0 = x0 - beta;
+          cj[j] = beta;
+        }
+      }
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    if (tau != 0.0) {
+      const double inv = 1.0 / s_v0;
+      for (int m = j + 1 + tid; m < r; m += NT) cj[m] *= inv;
+    }
+    __syncthreads();
+    // apply H to the trailing columns and recompute their trailing norms exactly
+    for (int l = j + 1 + g; l < n; l += NG) {
+      double* cl = G + (size_t)l * ld;
+      double x[EPR], v[EPR];
+      double s = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPR; ++e) {
+        const int m = j + sub + LPP * e;
+        x[e] = (m < r) ? cl[m] : 0.0;
+        v[e] = (m == j) ? 1.0 : ((m < r) ? cj[m] : 0.0);
+        s += v[e] * x[e];
+      }
+      s = tau * group_sum<LPP>(s);
+      double ns = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPR; ++e) {
+        const int m = j + sub + LPP * e;
+        if (m < r) {
+          const double y = x[e] - s * v[e];
+          if (tau != 0.0) cl[m] = y;
+          if (m > j) ns += y * y;
+        }
+      }
+      ns = group_sum<LPP>(ns);
+      if (sub == 0) nrm[l] = ns;
+    }
+    __syncthreads();
+  }
+  // ---- M = R1^T: column k of M is row k of R1, M[k][i] = R1[k][i] = G[i][k] for i >= k.
+  // M sits at the end of the G area (X is later written from the start; see step 3).
+  double* M = G + (size_t)n * ld - (size_t)n * ldm;
+  {
+    constexpr int MS = (EPJ * LPP * EPJ * LPP + NT - 1) / NT;  // n^2 <= (EPJ LPP)^2
+    double val[MS];
+#pragma unroll
+    for (int s2 = 0; s2 < MS; ++s2) {
+      const int e = tid + NT * s2;
+      const int k = e / n, ii = e - k * n;
+      val[s2] = (e < n * n && ii >= k && k < kmax) ? G[(size_t)ii * ld + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < MS; ++s2) {
+      const int e = tid + NT * s2;
+      const int k = e / n, ii = e - k * n;
+      if (e < n * n) M[(size_t)k * ldm + ii] = val[s2];
+    }
+    for (int l = tid; l < n; l += NT) pinv[piv[l]] = l;
+  }
+  __syncthreads();
+  // ---- one-sided Jacobi on the columns of M, circle-method ordering
   const int nn = n + (n & 1);
   const int npair = nn / 2;
-  const int pk = tid / LPP, sub = tid % LPP;
   int sweeps = 0;
   bool converged = false;
   for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
     int rotated = 0;
     for (int rd = 0; rd < nn - 1; ++rd) {
-      if (pk < npair) {
-        const int pa = pk, pb = nn - 1 - pk;
+      if (g < npair) {
+        const int pa = g, pb = nn - 1 - g;
         const int P = (pa == 0) ? 0 : 1 + (pa - 1 + rd) % (nn - 1);
         const int Q = 1 + (pb - 1 + rd) % (nn - 1);
         if (P < n && Q < n) {
-          double* gp = Gm + (size_t)P * ld;
-          double* gq = Gm + (size_t)Q * ld;
-          double u[EPL], v[EPL];
+          double* gp = M + (size_t)P * ldm;
+          double* gq = M + (size_t)Q * ldm;
+          double u[EPJ], v[EPJ];
 #pragma unroll
-          for (int e = 0; e < EPL; ++e) {
+          for (int e = 0; e < EPJ; ++e) {
             const int m = sub + e * LPP;
-            u[e] = (m < r) ? gp[m] : 0.0;
-            v[e] = (m < r) ? gq[m] : 0.0;
+            u[e] = (m < n) ? gp[m] : 0.0;
+            v[e] = (m < n) ? gq[m] : 0.0;
           }
           double al = 0, be = 0, ga = 0;
 #pragma unroll
-          for (int e = 0; e < EPL; ++e) {
+          for (int e = 0; e < EPJ; ++e) {
             al += u[e] * u[e];
             be += v[e] * v[e];
             ga += u[e] * v[e];
@@ -359,23 +510,17 @@ __global__ void __launch_bounds__(NT) k_tsvd(TsvdArgs a) {
           be = group_sum<LPP>(be);
           ga = group_sum<LPP>(ga);
           if (ga * ga > 1e-30 * al * be && fmin(al, be) > negl) {
-            // tan of the rotation angle: t = 2 g sgn(b - a) / (|b - a| + sqrt((b - a)^2 + 4 g^2))
             const double dba = be - al;
             const double t = (dba >= 0 ? 2.0 * ga : -2.0 * ga) / (fabs(dba) + sqrt(dba * dba + 4.0 * ga * ga));
             const double cs = rsqrt(1.0 + t * t);
             const double sn = cs * t;
 #pragma unroll
-            for (int e = 0; e < EPL; ++e) {
+            for (int e = 0; e < EPJ; ++e) {
               const int m = sub + e * LPP;
-              if (m < r) {
+              if (m < n) {
                 gp[m] = cs * u[e] - sn * v[e];
                 gq[m] = sn * u[e] + cs * v[e];
               }
-            }
-            if (sub == 0) {  // the right-hand side row rotates along
-              const double bu = gp[r], bv = gq[r];
-              gp[r] = cs * bu - sn * bv;
-              gq[r] = sn * bu + cs * bv;
             }
             rotated = 1;
           }
@@ -387,14 +532,14 @@ __global__ void __launch_bounds__(NT) k_tsvd(TsvdArgs a) {
   }
   if (!converged && tid == 0) atomicOr(a.fail, 1);
   if (tid == 0) atomicMax(a.max_sweeps, sweeps);
-  // 3. singular values and truncation
+  // ---- 3. singular values, truncation, c
   double smax = 0.0;
-  for (int l = tid; l < n; l += NT) {
-    const double* g = Gm + (size_t)l * ld;
+  for (int l = g; l < n; l += NG) {
     double s2 = 0.0;
-    for (int m = 0; m < r; ++m) s2 += g[m] * g[m];
-    sig[l] = sqrt(s2);
-    smax = fmax(smax, sig[l]);
+    for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+    s2 = group_sum<LPP>(s2);
+    if (sub == 0) sig[l] = sqrt(s2);
+    smax = fmax(smax, sqrt(s2));
   }
   smax = block_max(smax, red);
   if (tid == 0) {
@@ -415,22 +560,56 @@ __global__ void __launch_bounds__(NT) k_tsvd(TsvdArgs a) {
   }
   __syncthreads();
   const int t = keep[n];
-  // 4. c_k = (U^T b)_l / sigma_l (into yv), x_l = Z v_l = z * g_l / sigma_l
-  for (int k = tid; k < t; k += NT) {
-    const int l = keep[k];
-    yv[k] = Gm[(size_t)l * ld + r] / sig[l];
+  // c_k = u_k^T b / sigma_k = (w_k . P^T b) / sigma_k^2
+  for (int k = g; k < t; k += NG) {
+    const double* wk = M + (size_t)keep[k] * ldm;
+    double s2 = 0.0;
+    for (int m = sub; m < n; m += LPP) s2 += wk[m] * Rk[piv[m]];
+    s2 = group_sum<LPP>(s2);
+    if (sub == 0) yv[k] = s2 / (sig[keep[k]] * sig[keep[k]]);
   }
-  for (int e = tid; e < t * r; e += NT) {
-    const int k = e / r, m = e - k * r;
-    const int l = keep[k];
-    Gm[(size_t)l * ld + m] = z[m] * Gm[(size_t)l * ld + m] / sig[l];
+  // X[m][k] = z_m sum_l A[l][m] U[l][k] / sigma_k with U[l][k] = M[pinv[l]][keep[k]] /
+  // sigma_k. Columns k are written from the start of G, M's columns sit at the end: the
+  // writes of a chunk never reach a column of M still to be read (n ld >= k ld + n ldm -
+  // (n - k) ldm for k <= n), and a chunk's own columns are read before the barrier.
+  constexpr int KC = 8;
+  for (int k0 = 0; k0 < t; k0 += KC) {
+    double acc[KC];
+#pragma unroll
+    for (int kq = 0; kq < KC; ++kq) acc[kq] = 0.0;
+    const int m = tid;
+    if (m < r) {
+      const int64_t p = a.sptr[i] + ptc[m];
+      const int q = ptq[m];
+      const int32_t c = a.scell[p];
+      const int mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
+      const double* Dc = a.D + a.dptr[c] + (int64_t)q * mc;
+      const uint8_t* sl = a.slot + a.soff[p];
+      for (int kk = 0; kk < mc; ++kk) {
+        const double av = Dc[kk];
+        const int ii = pinv[sl[kk]];
+#pragma unroll
+        for (int kq = 0; kq < KC; ++kq)
+          if (k0 + kq < t) acc[kq] += av * M[(size_t)keep[k0 + kq] * ldm + ii];
+      }
+    }
+    __syncthreads();
+    if (m < r) {
+#pragma unroll
+      for (int kq = 0; kq < KC; ++kq)
+        if (k0 + kq < t) {
+          const double sk = sig[keep[k0 + kq]];
+          G[(size_t)(k0 + kq) * ld + m] = z[m] * acc[kq] / (sk * sk);
+        }
+    }
+    __syncthreads();
   }
   for (int m = tid; m < r; m += NT) wacc[m] = 0.0;
   __syncthreads();
-  // 5. CGS2 on the kept columns; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk; w += y_k q_k
+  // ---- 4. CGS2 on the columns of X; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk; w += y_k q_k
   constexpr int DL = 4;  // lanes per dot product
   for (int k = 0; k < t; ++k) {
-    double* x = Gm + (size_t)keep[k] * ld;
+    double* x = G + (size_t)k * ld;
     for (int j = tid; j < k; j += NT) Rk[j] = 0.0;
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
@@ -438,32 +617,32 @@ __global__ void __launch_bounds__(NT) k_tsvd(TsvdArgs a) {
         const int j = jb + tid / DL, s4 = tid % DL;
         double d = 0.0;
         if (j < k) {
-          const double* qj = Gm + (size_t)keep[j] * ld;
+          const double* qj = G + (size_t)j * ld;
           for (int m = s4; m < r; m += DL) d += qj[m] * x[m];
         }
         d = group_sum<DL>(d);
         if (j < k && s4 == 0) {
           Rk[j] += d;
-          sig[j] = d;  // this pass's coefficients (sig is free for j < k)
+          sig[j] = d;  // this pass's coefficients (sig is free now)
         }
       }
       __syncthreads();
       for (int m = tid; m < r; m += NT) {
         double v = x[m];
-        for (int j = 0; j < k; ++j) v -= Gm[(size_t)keep[j] * ld + m] * sig[j];
+        for (int j = 0; j < k; ++j) v -= G[(size_t)j * ld + m] * sig[j];
         x[m] = v;
       }
       __syncthreads();
     }
     double nn2 = 0.0;
     for (int m = tid; m < r; m += NT) nn2 += x[m] * x[m];
-    const double nrm = sqrt(block_sum(nn2, red));
+    const double nrmx = sqrt(block_sum(nn2, red));
     double acc = 0.0;
     for (int j = tid; j < k; j += NT) acc += Rk[j] * yv[j];
     acc = block_sum(acc, red);
-    const double yk = (yv[k] - acc) / nrm;  // yv[k] still holds c_k
+    const double yk = (yv[k] - acc) / nrmx;  // yv[k] still holds c_k
     __syncthreads();
-    const double inv = 1.0 / nrm;
+    const double inv = 1.0 / nrmx;
     for (int m = tid; m < r; m += NT) {
       const double qm = x[m] * inv;
       x[m] = qm;
@@ -475,6 +654,7 @@ __global__ void __launch_bounds__(NT) k_tsvd(TsvdArgs a) {
   double* W = a.W + a.qptr[i];
   for (int m = tid; m < r; m += NT) W[m] = z[m] * wacc[m];
 }
+
 
 void release_weights(wq_weights* w) {
   for (int f = 0; f < 4; ++f) {
@@ -596,9 +776,13 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       int ld = ((mr + 1 + 23) / 32) * 32 + 8;
       if (ld < mr + 1) ld += 32;
       auto lds_of = [&](int l) {
-        return ((size_t)mn * l + 2 * (size_t)mr + 3 * (size_t)mn + 8) * sizeof(double) + (mn + 1) * sizeof(int);
+        return ((size_t)mn * l + 2 * (size_t)mr + 4 * (size_t)mn + 16) * sizeof(double) +
+               (3 * (size_t)mn + 1 + 2 * (size_t)mr) * sizeof(int);
       };
       if (lds_of(ld) > 160 * 1024) ld = (mr + 1) | 1;  // largest systems: minimal odd stride
+      // M = R1^T columns: stride = 8 (mod 16) doubles, at most ld
+      int ldm = ((mn + 8) / 16) * 16 + 8;
+      if (ldm > ld) ldm = mn;
       const size_t lds = lds_of(ld);
       if (lds > 160 * 1024) {
         set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
@@ -611,6 +795,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       ta.rows = lists.as<int32_t>() + start[b];
       ta.nsys = ns;
       ta.ld = ld;
+      ta.ldm = ldm;
       ta.fam = f;
       ta.tau = tau;
       ta.sptr = P->supp_ptr.as<int64_t>();
@@ -639,13 +824,14 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       const char* kname = nullptr;  // timing record: the kernel instance
       int nt = 0;
       {
-        const int epl = (mr + 7) / 8;
+        // EPR: register elements per lane of a column of A^T (r), EPJ: of M (n)
+        const int epr = (mr + 7) / 8;
         nt = wide ? 512 : 256;
-        if (!wide && epl <= 8) fn = (const void*)k_tsvd<8, 8, 256>, kname = "k_tsvd<8,8,256>";
-        else if (!wide && epl <= 16) fn = (const void*)k_tsvd<8, 16, 256>, kname = "k_tsvd<8,16,256>";
-        else if (!wide) fn = (const void*)k_tsvd<8, 32, 256>, kname = "k_tsvd<8,32,256>";
-        else if (epl <= 16) fn = (const void*)k_tsvd<8, 16, 512>, kname = "k_tsvd<8,16,512>";
-        else fn = (const void*)k_tsvd<8, 32, 512>, kname = "k_tsvd<8,32,512>";
+        if (!wide && epr <= 8) fn = (const void*)k_tsvd2<8, 8, 8, 256>, kname = "k_tsvd2<8,8,8,256>";
+        else if (!wide && epr <= 16) fn = (const void*)k_tsvd2<8, 16, 8, 256>, kname = "k_tsvd2<8,16,8,256>";
+        else if (!wide) fn = (const void*)k_tsvd2<8, 32, 8, 256>, kname = "k_tsvd2<8,32,8,256>";
+        else if (epr <= 16) fn = (const void*)k_tsvd2<8, 16, 16, 512>, kname = "k_tsvd2<8,16,16,512>";
+        else fn = (const void*)k_tsvd2<8, 32, 16, 512>, kname = "k_tsvd2<8,32,16,512>";
       }
       if (lds > 64 * 1024 &&
           hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
