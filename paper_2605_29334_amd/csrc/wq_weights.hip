@@ -277,6 +277,55 @@ __device__ inline double block_max(double v, double* red) {
   return s;
 }
 
+// Householder reflector for a column whose trailing part (rows j..) has first entry x0
+// and squared norm s2: H = I - tau v v^T maps it to R_jj e_j, with v_j = 1 and
+// v_m = x_m * rv0 below (rv0 = 1 / (x0 - R_jj)). s2 = 0: identity (tau = 0, R_jj = x0).
+__device__ inline void householder(double x0, double s2, double* rjj, double* rv0, double* tau) {
+  if (s2 == 0.0) {
+    *rjj = x0;
+    *rv0 = 0.0;
+    *tau = 0.0;
+    return;
+  }
+  const double b = -copysign(sqrt(s2), x0);
+  *rjj = b;
+  *rv0 = 1.0 / (x0 - b);
+  *tau = (b - x0) / b;
+}
+
+// Apply reflector j (stored unscaled in logical column j) to logical columns l > j, LPP
+// lanes per column, and recompute their trailing squared norms (rows > j) exactly.
+template <int LPP, int EPR, int NG>
+__device__ inline void qr_update(double* G, int ld, int r, int ncol, int j, const int* cmap, double tau, double rv0,
+                                 double* nrm, int g, int sub) {
+  const double* cj = G + (size_t)cmap[j] * ld;
+  for (int l = j + 1 + g; l < ncol; l += NG) {
+    double* cl = G + (size_t)cmap[l] * ld;
+    double x[EPR], v[EPR];
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPR; ++e) {
+      const int m = j + sub + LPP * e;
+      x[e] = (m < r) ? cl[m] : 0.0;
+      v[e] = (m == j) ? 1.0 : ((m < r) ? cj[m] * rv0 : 0.0);
+      s += v[e] * x[e];
+    }
+    s = tau * group_sum<LPP>(s);
+    double ns = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPR; ++e) {
+      const int m = j + sub + LPP * e;
+      if (m < r) {
+        const double y = x[e] - s * v[e];
+        if (tau != 0.0) cl[m] = y;
+        if (m > j) ns += y * y;
+      }
+    }
+    ns = group_sum<LPP>(ns);
+    if (sub == 0) nrm[l] = ns;
+  }
+}
+
 // Weight system of one (row i, family): A (n x r, A[l][m] = D N_{S_i[l]}(x_{Q_i[m]})),
 // z (r, z_m = N_i(x_{Q_i[m]})), b (n). Truncated SVD of Eqs. (20)-(22) with the weighted
 // solution of Eqs. (5)-(6):
@@ -305,17 +354,19 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   double* z = G + (size_t)n * ld;   // r
   double* wacc = z + r;             // r
   double* sig = wacc + r;           // n
-  double* Rk = sig + n;             // n: b (phases 1-3), CGS2 scratch (phase 4)
-  double* yv = Rk + n;              // n
-  double* nrm = yv + n;             // n: trailing column norms^2 in the QR
-  double* red = nrm + n;            // 16
+  double* Rk = sig + n;             // n: b
+  double* yv = Rk + n;              // n: c
+  double* nrm = yv + n;             // n: trailing column norms^2 in a QR
+  double* beta = nrm + n;           // n: R_jj of a QR
+  double* rv0 = beta + n;           // n: 1 / (x_jj - R_jj), scale of reflector j
+  double* tau = rv0 + n;            // n: reflector coefficients
+  double* red = tau + n;            // 16
   int* keep = (int*)(red + 16);     // n + 1
   int* piv = keep + n + 1;          // n
   int* pinv = piv + n;              // n
-  int* ptc = pinv + n;              // r: support entry of the point's cell
+  int* cmap = pinv + n;             // n: physical column of logical column j (pivoting)
+  int* ptc = cmap + n;              // r: support entry of the point's cell
   int* ptq = ptc + r;               // r: point index inside its cell
-  __shared__ int s_p;
-  __shared__ double s_tau, s_v0;
   // ---- 1. gather A^T, z, b
   for (int t = tid; t < n * ld; t += NT) G[t] = 0.0;
   __syncthreads();
@@ -343,6 +394,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     for (int l = tid; l < n; l += NT) {
       Rk[l] = a.rhs[a.row_ptr[i] + l];
       piv[l] = l;
+      cmap[l] = l;
     }
   }
   __syncthreads();
@@ -355,12 +407,14 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     fro2 += v * v;
   }
   const double negl = 1e-30 * block_sum(fro2, red);
-  // ---- 2. Householder QR of A^T with column pivoting (largest trailing norm first)
+  // ---- 2. Householder QR of A^T with column pivoting (largest trailing norm first).
+  // Columns are addressed through cmap (no data swaps); reflector j is kept unscaled in
+  // column j (v_j = 1, v_m = x_m / (x_j - R_jj) below), R_jj in beta[j].
   for (int l = g; l < n; l += NG) {
-    double s = 0.0;
-    for (int m = sub; m < r; m += LPP) s += G[(size_t)l * ld + m] * G[(size_t)l * ld + m];
-    s = group_sum<LPP>(s);
-    if (sub == 0) nrm[l] = s;
+    double s2 = 0.0;
+    for (int m = sub; m < r; m += LPP) s2 += G[(size_t)l * ld + m] * G[(size_t)l * ld + m];
+    s2 = group_sum<LPP>(s2);
+    if (sub == 0) nrm[l] = s2;
   }
   __syncthreads();
   const int kmax = min(n, r);
@@ -381,78 +435,23 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
           bi = oi;
         }
       }
-      if (tid == 0) s_p = bi;
-    }
-    __syncthreads();
-    const int pv = s_p;
-    if (pv != j) {
-      for (int m = tid; m < r; m += NT) {
-        const double t0 = G[(size_t)j * ld + m];
-        G[(size_t)j * ld + m] = G[(size_t)pv * ld + m];
-        G[(size_t)pv * ld + m] = t0;
-      }
       if (tid == 0) {
-        const double tn = nrm[j];
-        nrm[j] = nrm[pv];
-        nrm[pv] = tn;
-        const int tp = piv[j];
-        piv[j] = piv[pv];
-        piv[pv] = tp;
-      }
-      __syncthreads();
-    }
-    // reflector H = I - tau v v^T with v_j = 1 zeroing rows j+1.. of column j
-    double* cj = G + (size_t)j * ld;
-    if (tid < 64) {
-      double s = 0.0;
-      for (int m = j + 1 + tid; m < r; m += 64) s += cj[m] * cj[m];
-      s = wave_sum(s);
-      if (tid == 0) {
-        const double x0 = cj[j];
-        if (s == 0.0) {
-          s_tau = 0.0;
-          s_v0 = 1.0;
-        } else {
-          const double beta = -copysign(sqrt(x0 * x0 + s), x0);
-          s_tau = (beta - x0) / beta;
-          s_v0 = x0 - beta;
-          cj[j] = beta;
+        if (bi != j) {
+          const double tn = nrm[j];
+          nrm[j] = nrm[bi];
+          nrm[bi] = tn;
+          int tp = piv[j];
+          piv[j] = piv[bi];
+          piv[bi] = tp;
+          tp = cmap[j];
+          cmap[j] = cmap[bi];
+          cmap[bi] = tp;
         }
+        householder(G[(size_t)cmap[j] * ld + j], nrm[j], beta + j, rv0 + j, tau + j);
       }
     }
     __syncthreads();
-    const double tau = s_tau;
-    if (tau != 0.0) {
-      const double inv = 1.0 / s_v0;
-      for (int m = j + 1 + tid; m < r; m += NT) cj[m] *= inv;
-    }
-    __syncthreads();
-    // apply H to the trailing columns and recompute their trailing norms exactly
-    for (int l = j + 1 + g; l < n; l += NG) {
-      double* cl = G + (size_t)l * ld;
-      double x[EPR], v[EPR];
-      double s = 0.0;
-#pragma unroll
-      for (int e = 0; e < EPR; ++e) {
-        const int m = j + sub + LPP * e;
-        x[e] = (m < r) ? cl[m] : 0.0;
-        v[e] = (m == j) ? 1.0 : ((m < r) ? cj[m] : 0.0);
-        s += v[e] * x[e];
-      }
-      s = tau * group_sum<LPP>(s);
-      double ns = 0.0;
-#pragma unroll
-      for (int e = 0; e < EPR; ++e) {
-        const int m = j + sub + LPP * e;
-        if (m < r) {
-          const double y = x[e] - s * v[e];
-          if (tau != 0.0) cl[m] = y;
-          if (m > j) ns += y * y;
-        }
-      }
-      ns = group_sum<LPP>(ns);
-      if (sub == 0) nrm[l] = ns;
-    }
+    qr_update<LPP, EPR, NG>(G, ld, r, n, j, cmap, tau[j], rv0[j], nrm, g, sub);
     __syncthreads();
   }
   // ---- M = R1^T: column k of M is row k of R1, M[k][i] = R1[k][i] = G[i][k] for i >= k.
@@ -465,7 +464,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     for (int s2 = 0; s2 < MS; ++s2) {
       const int e = tid + NT * s2;
       const int k = e / n, ii = e - k * n;
-      val[s2] = (e < n * n && ii >= k && k < kmax) ? G[(size_t)ii * ld + k] : 0.0;
+      val[s2] = (e < n * n && ii >= k && k < kmax) ? (ii == k ? beta[k] : G[(size_t)cmap[ii] * ld + k]) : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -776,8 +775,8 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       int ld = ((mr + 1 + 23) / 32) * 32 + 8;
       if (ld < mr + 1) ld += 32;
       auto lds_of = [&](int l) {
-        return ((size_t)mn * l + 2 * (size_t)mr + 4 * (size_t)mn + 16) * sizeof(double) +
-               (3 * (size_t)mn + 1 + 2 * (size_t)mr) * sizeof(int);
+        return ((size_t)mn * l + 2 * (size_t)mr + 7 * (size_t)mn + 16) * sizeof(double) +
+               (4 * (size_t)mn + 1 + 2 * (size_t)mr) * sizeof(int);
       };
       if (lds_of(ld) > 160 * 1024) ld = (mr + 1) | 1;  // largest systems: minimal odd stride
       // M = R1^T columns: stride = 8 (mod 16) doubles, at most ld
