@@ -609,9 +609,9 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   constexpr int DL = 4;  // lanes per dot product
   for (int k = 0; k < t; ++k) {
     double* x = G + (size_t)k * ld;
-    for (int j = tid; j < k; j += NT) Rk[j] = 0.0;
-    __syncthreads();
+    double part_n = 0.0, part_a = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
+      // h_j = q_j . x for j < k (DL lanes per j); R_jk accumulates both passes
       for (int jb = 0; jb < k; jb += NT / DL) {
         const int j = jb + tid / DL, s4 = tid % DL;
         double d = 0.0;
@@ -621,26 +621,39 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
         }
         d = group_sum<DL>(d);
         if (j < k && s4 == 0) {
-          Rk[j] += d;
+          Rk[j] = pass == 0 ? d : Rk[j] + d;
           sig[j] = d;  // this pass's coefficients (sig is free now)
         }
       }
       __syncthreads();
+      // x -= sum_j h_j q_j (thread per row); the second pass also forms the partial sums
+      // of |x|^2 and of sum_j R_jk y_j
       for (int m = tid; m < r; m += NT) {
         double v = x[m];
         for (int j = 0; j < k; ++j) v -= G[(size_t)j * ld + m] * sig[j];
         x[m] = v;
+        if (pass == 1) part_n += v * v;
       }
-      __syncthreads();
+      if (pass == 1)
+        for (int j = tid; j < k; j += NT) part_a += Rk[j] * yv[j];
+      if (pass == 0) __syncthreads();
     }
-    double nn2 = 0.0;
-    for (int m = tid; m < r; m += NT) nn2 += x[m] * x[m];
-    const double nrmx = sqrt(block_sum(nn2, red));
-    double acc = 0.0;
-    for (int j = tid; j < k; j += NT) acc += Rk[j] * yv[j];
-    acc = block_sum(acc, red);
-    const double yk = (yv[k] - acc) / nrmx;  // yv[k] still holds c_k
+    // one block reduction of the two partial sums (red was last read before the previous
+    // column's final barrier)
+    part_n = wave_sum(part_n);
+    part_a = wave_sum(part_a);
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = part_n;
+      red[8 + (tid >> 6)] = part_a;
+    }
     __syncthreads();
+    double nn2 = 0.0, acc = 0.0;
+    for (int w8 = 0; w8 < NT / 64; ++w8) {
+      nn2 += red[w8];
+      acc += red[8 + w8];
+    }
+    const double nrmx = sqrt(nn2);
+    const double yk = (yv[k] - acc) / nrmx;  // yv[k] still holds c_k
     const double inv = 1.0 / nrmx;
     for (int m = tid; m < r; m += NT) {
       const double qm = x[m] * inv;
