@@ -512,8 +512,9 @@ def row_gauss_rhs(fx, cl, supp_i, S_i, i, fam, cache):
 
 
 def sample_rows(fx, rows, families=("mass", "x", "y"), tau=1e-12, coef=None, glob=None):
-    """Everything the method produces for the given rows: S_i, Q_i, weights per family,
-    and mass / stiffness rows (coef: dict kind -> callable of x, or None for 1).
+    """Everything the method produces for the given rows: S_i, Q_i, the system of each
+    family (A_fam, b_fam, z) with its weights, and mass / stiffness rows (coef: dict
+    kind -> callable of x, or None for 1).
     glob: optional precomputed {"cls", "s", "cells"} of the whole mesh."""
     if glob is None:
         cls = classify(fx)
@@ -552,6 +553,8 @@ def sample_rows(fx, rows, families=("mass", "x", "y"), tau=1e-12, coef=None, glo
             w, t, _ = tsvd_solve(A, z, b, tau)
             res["W"][fam] = w
             res["b_" + fam] = b
+            res["A_" + fam] = A
+        res["z"] = z
         cm = np.ones(len(q)) if coef is None or "mass" not in coef else coef["mass"](x)
         ck = np.ones(len(q)) if coef is None or "stiffness" not in coef else coef["stiffness"](x)
         if "mass" in families:
