@@ -117,7 +117,7 @@ typedef enum {
 int64_t wq_points_size(const wq_points* pts, wq_array what);
 
 /* Scalar sizes of the built structures (host): 0 max n_i, 1 max r_i, 2 Bezier cells,
- * 3 assembly tiles (16 rows each), 4 tile entries, 5 largest tile nnz, 6 largest tile
+ * 3 assembly tiles (8 consecutive rows each), 4 tile entries, 5 largest tile nnz, 6 largest tile
  * entry count, 7 largest tile member count, 8 (row, cell) pairs, 9 largest points x
  * functions of a cell entry, 10 largest member rows x points of a cell entry.
  * -1 if unknown. */

@@ -39,9 +39,10 @@ struct Src {
 constexpr int PFD = 4;  // register slots (x 64 lanes) prefetched for a cell's basis block
 constexpr int PFW = 1;  // ... for the member rows' weights on the cell
 constexpr int PFS = 4;  // ... for the members' column slots
+constexpr int DEPTH = 2;  // cell entries in flight per wavefront
 
 // Entry e of a tile: cell block at d0, points pt0.., np points, m functions; member rows
-// are the set bits of the 16-bit mask, their records at smem[mb ..] in row order.
+// are the set bits of the row mask (bits 0..15), their records at smem[mb ..] in row order.
 struct Ent {
   int64_t d0, pt0;
   int np, m, R, mb;
@@ -237,53 +238,52 @@ __global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, i
   for (int t = lane; t < NACC * acc_stride; t += WAVE) acc[t] = 0.0;
   for (int t = lane; t < nm; t += WAVE) smem[t] = mem[m0 + t];
   __syncthreads();
+  // Entries are pipelined DEPTH deep: while entry e is computed from the LDS stage, the
+  // loads of entries e+1 .. e+DEPTH-1 are in flight in registers (ring slot e % DEPTH).
   if (ne > 0) {
-    Pre<K> p;
-    Ent cur = decode(ent[e0], m0);
-    prefetch<K>(cur, lane, S, smem, slot, p);
-    stage<K>(cur, lane, S, smem, p, sd, nd_cap, sw, nw_cap, rho);
-    int cs[PFS], cr[PFS];
+    Pre<K> p[DEPTH];
+    Ent en[DEPTH];
 #pragma unroll
-    for (int u = 0; u < PFS; ++u) {
-      cs[u] = p.s[u];
-      cr[u] = p.rl[u];
-    }
+    for (int u = 0; u < DEPTH; ++u)
+      if (u < ne) {
+        en[u] = decode(ent[e0 + u], m0);
+        prefetch<K>(en[u], lane, S, smem, slot, p[u]);
+      }
+    stage<K>(en[0], lane, S, smem, p[0], sd, nd_cap, sw, nw_cap, rho);
     __syncthreads();
-    for (int e = 0; e < ne; ++e) {
-      Ent nxt;
-      const bool more = e + 1 < ne;
-      if (more) {
-        nxt = decode(ent[e0 + e + 1], m0);
-        prefetch<K>(nxt, lane, S, smem, slot, p);
-      }
-      const int ns = cur.R * cur.m;
+    for (int eb = 0; eb < ne; eb += DEPTH) {
 #pragma unroll
-      for (int u = 0; u < PFS; ++u) {
-        const int t = lane + WAVE * u;
-        if (t < ns) accumulate<K>(cur, t, cs[u], cr[u], sd, nd_cap, sw, nw_cap, ro, acc, acc_stride);
-      }
-      for (int t = lane + WAVE * PFS; t < ns; t += WAVE) {
-        const int j = qdiv(t, cur.rm), k = t - j * cur.m;
-        const int2 mm = smem[cur.mb + j];
-        accumulate<K>(cur, t, slot[(uint32_t)mm.y + k], (int)((unsigned)mm.x >> 28), sd, nd_cap, sw, nw_cap, ro,
-                      acc, acc_stride);
-      }
-      if (RES && lane < cur.R) {
-        double v = 0.0;
-        for (int q = 0; q < cur.np; ++q) v += rho[lane * cur.np + q];
-        racc[(unsigned)smem[cur.mb + lane].x >> 28] += v;
-      }
-      __syncthreads();
-      if (more) {
-        stage<K>(nxt, lane, S, smem, p, sd, nd_cap, sw, nw_cap, rho);
+      for (int u = 0; u < DEPTH; ++u) {
+        const int e = eb + u;
+        if (e < ne) {
+          const Ent& cur = en[u];
+          const int ns = cur.R * cur.m;
 #pragma unroll
-        for (int u = 0; u < PFS; ++u) {
-          cs[u] = p.s[u];
-          cr[u] = p.rl[u];
+          for (int v = 0; v < PFS; ++v) {
+            const int t = lane + WAVE * v;
+            if (t < ns) accumulate<K>(cur, t, p[u].s[v], p[u].rl[v], sd, nd_cap, sw, nw_cap, ro, acc, acc_stride);
+          }
+          for (int t = lane + WAVE * PFS; t < ns; t += WAVE) {
+            const int j = qdiv(t, cur.rm), k = t - j * cur.m;
+            const int2 mm = smem[cur.mb + j];
+            accumulate<K>(cur, t, slot[(uint32_t)mm.y + k], (int)((unsigned)mm.x >> 28), sd, nd_cap, sw, nw_cap, ro,
+                          acc, acc_stride);
+          }
+          if (RES && lane < cur.R) {
+            double v = 0.0;
+            for (int q = 0; q < cur.np; ++q) v += rho[lane * cur.np + q];
+            racc[(unsigned)smem[cur.mb + lane].x >> 28] += v;
+          }
+          __syncthreads();
+          const int un = (u + 1) % DEPTH;
+          if (e + 1 < ne) stage<K>(en[un], lane, S, smem, p[un], sd, nd_cap, sw, nw_cap, rho);
+          if (e + DEPTH < ne) {  // slot u is free: start entry e + DEPTH
+            en[u] = decode(ent[e0 + e + DEPTH], m0);
+            prefetch<K>(en[u], lane, S, smem, slot, p[u]);
+          }
+          __syncthreads();
         }
-        cur = nxt;
       }
-      __syncthreads();
     }
   }
   for (int t = lane; t < nz; t += WAVE) {
@@ -639,7 +639,7 @@ __device__ inline f4 contract_split(const double* sw, int nw_cap, const uint32_t
   return c;
 }
 
-// The FP64 tile kernel's structure (tiles of 16 rows, cell entries in order, LDS stage),
+// The FP64 tile kernel's structure (row tiles, cell entries in order, LDS stage),
 // with the per-entry contraction on MFMA. K = 0 mass, 1 stiffness, 2 biharmonic,
 // 3 mass + stiffness. Output FP32.
 template <int K, int PREC>

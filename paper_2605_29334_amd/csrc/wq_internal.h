@@ -84,7 +84,7 @@ struct wq_points {
       qptr /*int64*/, qidx /*int32*/;
   // per (row, cell) pair = supp entry
   wq::DBuf soff /*int64 [pairs+1]*/, slot /*uint8*/, kself /*uint8*/;
-  // assembly tiles: 16 consecutive rows; one entry per (tile, cell) in ascending cell order
+  // assembly tiles: TILE_ROWS consecutive rows; one entry per (tile, cell), cells ascending
   int64_t n_tiles = 0, n_entries = 0;
   int32_t max_tile_nnz = 0, max_tile_ent = 0, max_tile_mem = 0;
   int32_t max_tile_nd = 0 /*max np*m of an entry*/, max_tile_nw = 0 /*max members*np*/;
@@ -154,7 +154,7 @@ struct KTimer {
   void stop();
 };
 
-constexpr int TILE_ROWS = 16;
+constexpr int TILE_ROWS = 8;
 
 // 64-bit index launch helper
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
