@@ -80,6 +80,101 @@ def roofline_of(name, e):
             "traffic": None, "avg_launch_ms": avg_ms, "launches": e["launches"]}
 
 
+def small_pool(seed=3000):
+    """Seeded small meshes for the batched and served measurements: grids and EP meshes
+    of 16..64 control faces per side (displacement 0.05)."""
+    import fixtures as fx
+    pool = []
+    for j, N in enumerate((16, 24, 32, 40, 48, 64)):
+        pool.append(fx.fixture_grid(N, displace=0.05, seed=seed + j))
+    for j, N in enumerate((32, 48, 64)):
+        pool.append(fx.fixture_eps(N, 0.02, (3, 5, 6), displace=0.05, seed=seed + 10 + j))
+    return pool
+
+
+def measure_batched(W, torch, pool, copies):
+    """The same meshes one by one (points, weights, mass + stiffness each) against one
+    batch of all of them (one set of launches), and the batch's assembly replayed as a
+    HIP graph against eager per-mesh assemblies."""
+    meshes = [pool[i % len(pool)] for i in range(copies * len(pool))]
+    mask = W.WQ_FAM_MASS | W.WQ_FAM_DX | W.WQ_FAM_DY
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per = []
+    nnz = 0
+    for F in meshes:
+        m = W.Mesh(F)
+        p = W.Points(m)
+        w = W.Weights(m, p, mask)
+        W.assemble_mass_stiffness(p, w)
+        per.append((m, p, w))
+        nnz += 2 * p.nnz
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    B = W.Batch(meshes).build(mask)
+    Mb, Kb = W.assemble_mass_stiffness(B.points, B.weights)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    s = torch.cuda.Stream()
+    B.graph_assemble(None, None, Mb, Kb, stream=s)
+    s.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        B.graph_assemble(None, None, Mb, Kb, stream=s)
+    e1.record(s)
+    e1.synchronize()
+    g_ms = e0.elapsed_time(e1) / reps
+    outs = [(W.assemble_mass_stiffness(p, w)) for (_, p, w) in per]  # outputs allocated once
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        for (_, p, w), (M, K) in zip(per, outs):
+            W.assemble_mass_stiffness(p, w, None, None, M, K)
+    e1.record()
+    e1.synchronize()
+    s_ms = e0.elapsed_time(e1) / reps
+    return {"meshes": len(meshes), "rows": int(B.points.n_rows), "nnz_M_plus_K": int(nnz),
+            "setup_to_matrices_s": {"one_by_one": t_single, "batched": t_batch},
+            "nnz_per_s_setup_to_matrices": {"one_by_one": nnz / t_single, "batched": nnz / t_batch},
+            "assembly_ms": {"eager_per_mesh": s_ms, "batched_graph": g_ms},
+            "nnz_per_s_assembly": {"eager_per_mesh": nnz / (s_ms * 1e-3), "batched_graph": nnz / (g_ms * 1e-3)}}
+
+
+def measure_served(W, pool, n_requests, rate, slots, seed=5):
+    """Nonlinear heat requests (k = 1 + u^2, manufactured source, 2 steps of dt 0.1) from
+    the pool, arriving as a Poisson stream of `rate` per second, served with continuous
+    admission on `slots` concurrent streams; latency = completion - arrival."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    picks = rng.integers(0, len(pool), n_requests)
+    S = W.Server(32 << 30, slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for a, j in zip(arrivals, picks):
+        now = time.perf_counter() - t0
+        if a > now:
+            time.sleep(a - now)
+        F = pool[j]
+        tickets.append(S.submit(F, F["dir1"], 0.1, 2, k=(W.K_QUADRATIC, 1.0, 1.0)))
+    res = [S.poll(t)[1] for t in tickets]
+    wall = time.perf_counter() - t0
+    S.close()
+    lat = np.array([r["finished"] - r["submitted"] for r in res]) * 1e3
+    ok = sum(r["status"] == 0 for r in res)
+    failed = [{"status": r["status"], "rows": r["n_rows"], "newton_iters": r["newton_iters"],
+               "krylov_iters": r["cg_iters"], "residual": r["residual"]} for r in res if r["status"] != 0]
+    return {"requests": n_requests, "arrival_rate_per_s": rate, "slots": slots, "completed_ok": int(ok),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "solves_per_s": ok / wall, "newton_iters_mean": float(np.mean([r["newton_iters"] for r in res])),
+            "failed": failed,
+            "workload": "pool of 9 meshes (16..64 faces per side, grids and 2% EPs), k = 1 + u^2, "
+                        "2 steps of dt 0.1 (the paper's step) from T = 0, theta = 1, Newton to ||R|| <= 1e-10"}
+
+
 def make_fixture(N, density, seed):
     import fixtures as fx
     return fx.fixture_eps(N, density, (3, 5, 6), displace=0.05, seed=seed)
@@ -128,6 +223,7 @@ def main():
     ap.add_argument("--assembly-reps", type=int, default=30)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-forms", action="store_true", help="skip the batched and served measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -234,6 +330,11 @@ def main():
         "solve_report": wts.report,
         "structure": pts.info(),
     }
+    if not args.no_extra_forms:
+        print("[bench] batched and served forms", file=sys.stderr, flush=True)
+        pool = small_pool()
+        out["batched"] = measure_batched(W, torch, pool, copies=4)
+        out["served"] = measure_served(W, pool, n_requests=40, rate=200.0, slots=4)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(F, args.cpu_budget)
