@@ -126,12 +126,15 @@ wq_status wq_points_get(const wq_points* pts, wq_array what, void* dst_device, w
 
 /* ------------------------------------------------------------------ solve_weights
  * For every row i and every family in fam_mask: the right-hand side b (the exact
- * integrals, Section 2: "precomputed") by 4x4 Gauss quadrature on every Bezier cell
- * (Section 4.2), then the truncated-SVD weights of Eqs. (20)-(22):
+ * integrals, computed ahead of the weights as Section 2 prescribes) by 4x4 Gauss
+ * quadrature on every Bezier cell (Section 4.2), then the truncated-SVD weights of
+ * Eqs. (20)-(22):
  *   A = U S V^T, keep sigma_k > tsvd_rel_cutoff * sigma_1,
  *   w = Z^2 V_t (V_t^T Z^2 V_t)^{-1} S_t^{-1} U_t^T b,  Z = diag(N_i(x_q)),
  * with the inverse applied through a QR factorisation of Z V_t (as Eq. (7) does for
- * A Z^2 A^T). One-sided Jacobi SVD in FP64. Weights are stored aligned with Q_i.
+ * A Z^2 A^T). The SVD in FP64: Householder QR of A^T with column pivoting, one-sided
+ * Jacobi on the n x n triangular factor (left singular vectors directly), V_t formed as
+ * A^T U_t S_t^{-1}. Weights are stored aligned with Q_i.
  * report (host, nullable): per family counts and worst cases, see wq_solve_report.
  * Synchronises `stream`. Returns WQ_ESVD if a Jacobi SVD hit its sweep limit. */
 typedef struct {
