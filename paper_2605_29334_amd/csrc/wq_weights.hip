@@ -211,6 +211,20 @@ __device__ inline double group_sum(double v) {
   return v;
 }
 
+// 1/x and 1/sqrt(x) for positive normal x: the hardware estimates refined by two Newton
+// steps (each doubles the number of correct bits).
+__device__ inline double rcp_f64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+
+__device__ inline double rsq_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -223,7 +237,7 @@ struct TsvdArgs {
   const int32_t* rows;
   int64_t nsys;
   int ld;   // leading dimension (doubles) of a column of A^T in LDS, >= r_max + 1
-  int ldm;  // leading dimension of a column of R^T in LDS, >= n_max, <= ld
+  int ldm;  // leading dimension of a column of R^T in LDS, >= n_max rounded up to 8, <= ld
   int fam;
   double tau;
   const int64_t* sptr;
@@ -326,6 +340,46 @@ __device__ inline void qr_update(double* G, int ld, int r, int ncol, int j, cons
   }
 }
 
+// One Jacobi rotation of the columns p, q (LPP lanes, rows sub + e LPP at gp[e LPP],
+// gq[e LPP]): the 2x2 Gram block is diagonalised when the columns are not yet orthogonal
+// to working precision and neither is negligible. Rows past the column's length are
+// zero. GUARD: only the first ne rows of a lane exist; otherwise all EPJ do.
+template <int LPP, int EPJ, bool GUARD>
+__device__ inline int jacobi_pair(double* gp, double* gq, int ne, double negl) {
+  double u[EPJ], v[EPJ];
+#pragma unroll
+  for (int e = 0; e < EPJ; ++e) {
+    u[e] = (!GUARD || e < ne) ? gp[e * LPP] : 0.0;
+    v[e] = (!GUARD || e < ne) ? gq[e * LPP] : 0.0;
+  }
+  double al = 0, be = 0, ga = 0;
+#pragma unroll
+  for (int e = 0; e < EPJ; ++e) {
+    al += u[e] * u[e];
+    be += v[e] * v[e];
+    ga += u[e] * v[e];
+  }
+  al = group_sum<LPP>(al);
+  be = group_sum<LPP>(be);
+  ga = group_sum<LPP>(ga);
+  if (!(ga * ga > 1e-30 * al * be && fmin(al, be) > negl)) return 0;
+  // t = tan of the rotation angle (the smaller root), c = 1 / sqrt(1 + t^2), s = c t. t
+  // only has to be close to the exact angle; c is accurate to rounding for the t used, so
+  // the rotation is orthogonal to working precision.
+  const double dba = be - al;
+  const double h = dba * dba + 4.0 * ga * ga;
+  const double t = (dba >= 0 ? 2.0 * ga : -2.0 * ga) * rcp_f64(fabs(dba) + h * rsq_f64(h));
+  const double cs = rsq_f64(1.0 + t * t);
+  const double sn = cs * t;
+#pragma unroll
+  for (int e = 0; e < EPJ; ++e)
+    if (!GUARD || e < ne) {
+      gp[e * LPP] = cs * u[e] - sn * v[e];
+      gq[e * LPP] = sn * u[e] + cs * v[e];
+    }
+  return 1;
+}
+
 // Weight system of one (row i, family): A (n x r, A[l][m] = D N_{S_i[l]}(x_{Q_i[m]})),
 // z (r, z_m = N_i(x_{Q_i[m]})), b (n). Truncated SVD of Eqs. (20)-(22) with the weighted
 // solution of Eqs. (5)-(6):
@@ -350,6 +404,10 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   const int n = (int)(a.row_ptr[i + 1] - a.row_ptr[i]);
   const int r = (int)(a.qptr[i + 1] - a.qptr[i]);
   const int ld = a.ld, ldm = a.ldm;
+  if ((n + LPP - 1) / LPP * LPP > ldm || ldm > ld) {  // host sizing violated: report, touch nothing
+    if (tid == 0) atomicOr(a.fail, 2);
+    return;
+  }
   double* G = sh;                   // n * ld: columns of A^T, later of X
   double* z = G + (size_t)n * ld;   // r
   double* wacc = z + r;             // r
@@ -473,58 +531,31 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       const int k = e / n, ii = e - k * n;
       if (e < n * n) M[(size_t)k * ldm + ii] = val[s2];
     }
+    for (int e = tid; e < n * (ldm - n); e += NT) M[(size_t)(e / (ldm - n)) * ldm + n + e % (ldm - n)] = 0.0;
     for (int l = tid; l < n; l += NT) pinv[piv[l]] = l;
   }
   __syncthreads();
-  // ---- one-sided Jacobi on the columns of M, circle-method ordering
+  // ---- one-sided Jacobi on the columns of M, circle-method ordering. Rows [n, ldm) of
+  // every column are zero, and ne LPP <= ldm.
   const int nn = n + (n & 1);
   const int npair = nn / 2;
+  const int ne = (n + LPP - 1) / LPP;
+  const bool full = ldm >= EPJ * LPP;  // all EPJ rows of a lane inside the column: no checks
   int sweeps = 0;
   bool converged = false;
   for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
     int rotated = 0;
+    // pair g starts as (g, nn - 1 - g); position 0 stays, positions 1..nn-1 advance by
+    // one per round (cyclically), so every pair meets once per sweep
+    int P = g, Q = nn - 1 - g;
     for (int rd = 0; rd < nn - 1; ++rd) {
-      if (g < npair) {
-        const int pa = g, pb = nn - 1 - g;
-        const int P = (pa == 0) ? 0 : 1 + (pa - 1 + rd) % (nn - 1);
-        const int Q = 1 + (pb - 1 + rd) % (nn - 1);
-        if (P < n && Q < n) {
-          double* gp = M + (size_t)P * ldm;
-          double* gq = M + (size_t)Q * ldm;
-          double u[EPJ], v[EPJ];
-#pragma unroll
-          for (int e = 0; e < EPJ; ++e) {
-            const int m = sub + e * LPP;
-            u[e] = (m < n) ? gp[m] : 0.0;
-            v[e] = (m < n) ? gq[m] : 0.0;
-          }
-          double al = 0, be = 0, ga = 0;
-#pragma unroll
-          for (int e = 0; e < EPJ; ++e) {
-            al += u[e] * u[e];
-            be += v[e] * v[e];
-            ga += u[e] * v[e];
-          }
-          al = group_sum<LPP>(al);
-          be = group_sum<LPP>(be);
-          ga = group_sum<LPP>(ga);
-          if (ga * ga > 1e-30 * al * be && fmin(al, be) > negl) {
-            const double dba = be - al;
-            const double t = (dba >= 0 ? 2.0 * ga : -2.0 * ga) / (fabs(dba) + sqrt(dba * dba + 4.0 * ga * ga));
-            const double cs = rsqrt(1.0 + t * t);
-            const double sn = cs * t;
-#pragma unroll
-            for (int e = 0; e < EPJ; ++e) {
-              const int m = sub + e * LPP;
-              if (m < n) {
-                gp[m] = cs * u[e] - sn * v[e];
-                gq[m] = sn * u[e] + cs * v[e];
-              }
-            }
-            rotated = 1;
-          }
-        }
+      if (g < npair && P < n && Q < n) {
+        double* gp = M + (size_t)P * ldm + sub;
+        double* gq = M + (size_t)Q * ldm + sub;
+        rotated |= full ? jacobi_pair<LPP, EPJ, false>(gp, gq, ne, negl) : jacobi_pair<LPP, EPJ, true>(gp, gq, ne, negl);
       }
+      P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
+      Q = (Q == nn - 1) ? 1 : Q + 1;
       __syncthreads();
     }
     converged = !__syncthreads_or(rotated);
@@ -605,7 +636,10 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   }
   for (int m = tid; m < r; m += NT) wacc[m] = 0.0;
   __syncthreads();
-  // ---- 4. CGS2 on the columns of X; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk; w += y_k q_k
+  // ---- 4. CGS2 on the columns of X; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk; w += y_k q_k.
+  // y_k goes to ys (beta is free once M is formed): yv[k] = c_k is read by every thread
+  // after the column's last barrier but one, so it must not be overwritten in place.
+  double* ys = beta;
   constexpr int DL = 4;  // lanes per dot product
   for (int k = 0; k < t; ++k) {
     double* x = G + (size_t)k * ld;
@@ -629,13 +663,21 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       // x -= sum_j h_j q_j (thread per row); the second pass also forms the partial sums
       // of |x|^2 and of sum_j R_jk y_j
       for (int m = tid; m < r; m += NT) {
-        double v = x[m];
-        for (int j = 0; j < k; ++j) v -= G[(size_t)j * ld + m] * sig[j];
+        double v0 = x[m], v1 = 0.0, v2 = 0.0, v3 = 0.0;  // four chains in flight
+        int j = 0;
+        for (; j + 4 <= k; j += 4) {
+          v0 -= G[(size_t)j * ld + m] * sig[j];
+          v1 -= G[(size_t)(j + 1) * ld + m] * sig[j + 1];
+          v2 -= G[(size_t)(j + 2) * ld + m] * sig[j + 2];
+          v3 -= G[(size_t)(j + 3) * ld + m] * sig[j + 3];
+        }
+        for (; j < k; ++j) v0 -= G[(size_t)j * ld + m] * sig[j];
+        const double v = (v0 + v1) + (v2 + v3);
         x[m] = v;
         if (pass == 1) part_n += v * v;
       }
       if (pass == 1)
-        for (int j = tid; j < k; j += NT) part_a += Rk[j] * yv[j];
+        for (int j = tid; j < k; j += NT) part_a += Rk[j] * ys[j];
       if (pass == 0) __syncthreads();
     }
     // one block reduction of the two partial sums (red was last read before the previous
@@ -653,14 +695,14 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       acc += red[8 + w8];
     }
     const double nrmx = sqrt(nn2);
-    const double yk = (yv[k] - acc) / nrmx;  // yv[k] still holds c_k
+    const double yk = (yv[k] - acc) / nrmx;
     const double inv = 1.0 / nrmx;
     for (int m = tid; m < r; m += NT) {
       const double qm = x[m] * inv;
       x[m] = qm;
       wacc[m] += qm * yk;
     }
-    if (tid == 0) yv[k] = yk;
+    if (tid == 0) ys[k] = yk;
     __syncthreads();
   }
   double* W = a.W + a.qptr[i];
@@ -793,8 +835,12 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       };
       if (lds_of(ld) > 160 * 1024) ld = (mr + 1) | 1;  // largest systems: minimal odd stride
       // M = R1^T columns: stride = 8 (mod 16) doubles, at most ld
+      // (at least mn rounded up to the 8 lanes of a Jacobi pair: those rows are zero-padded;
+      // for 48 < n <= 64 all 64 rows of the lanes, which saves the per-row checks)
       int ldm = ((mn + 8) / 16) * 16 + 8;
-      if (ldm > ld) ldm = mn;
+      if (mn > 48 && mn <= 64 && ld >= 72) ldm = 72;
+      if (ldm > ld) ldm = (mn + 7) / 8 * 8;
+      if (ldm > ld) ld = ldm;
       const size_t lds = lds_of(ld);
       if (lds > 160 * 1024) {
         set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
@@ -871,7 +917,10 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   dfree(dstart);
   dfree(dflops);
   dfree(drep);
-  if (s == WQ_OK && hrep.fail) {
+  if (s == WQ_OK && (hrep.fail & 2)) {
+    set_error("solve_weights: internal LDS sizing error (column stride)");
+    s = WQ_EDEVICE;
+  } else if (s == WQ_OK && hrep.fail) {
     set_error("solve_weights: a Jacobi SVD did not converge in 40 sweeps");
     s = WQ_ESVD;
   }
