@@ -192,10 +192,11 @@ __global__ void k_sys_scatter(int64_t n, const uint8_t* bkt, const int64_t* star
 }
 
 // Cross-lane moves inside a row of 16 lanes by DPP (VALU, no LDS round trip).
+// Every lane reads an existing lane of its row (no bound_ctrl case), so no old value.
 template <int CTRL>
 __device__ inline double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -344,23 +345,22 @@ __device__ inline void qr_update(double* G, int ld, int r, int ncol, int j, cons
 // gq[e LPP]): the 2x2 Gram block is diagonalised when the columns are not yet orthogonal
 // to working precision and neither is negligible. Rows past the column's length are
 // zero. GUARD: only the first ne rows of a lane exist; otherwise all EPJ do.
+// The squared column norms are tracked in *np, *nq (the exact update of a rotation that
+// zeroes the off-diagonal: |p'|^2 = |p|^2 - t g, |q'|^2 = |q|^2 + t g), so only the inner
+// product is reduced per rotation; where the update cancels (a norm drops below 1e-3 of
+// its old value) both are recomputed from the rotated columns.
 template <int LPP, int EPJ, bool GUARD>
-__device__ inline int jacobi_pair(double* gp, double* gq, int ne, double negl) {
+__device__ inline int jacobi_pair(double* gp, double* gq, double* np, double* nq, int sub, int ne, double negl) {
   double u[EPJ], v[EPJ];
 #pragma unroll
   for (int e = 0; e < EPJ; ++e) {
     u[e] = (!GUARD || e < ne) ? gp[e * LPP] : 0.0;
     v[e] = (!GUARD || e < ne) ? gq[e * LPP] : 0.0;
   }
-  double al = 0, be = 0, ga = 0;
+  const double al = *np, be = *nq;
+  double ga = 0;
 #pragma unroll
-  for (int e = 0; e < EPJ; ++e) {
-    al += u[e] * u[e];
-    be += v[e] * v[e];
-    ga += u[e] * v[e];
-  }
-  al = group_sum<LPP>(al);
-  be = group_sum<LPP>(be);
+  for (int e = 0; e < EPJ; ++e) ga += u[e] * v[e];
   ga = group_sum<LPP>(ga);
   if (!(ga * ga > 1e-30 * al * be && fmin(al, be) > negl)) return 0;
   // t = tan of the rotation angle (the smaller root), c = 1 / sqrt(1 + t^2), s = c t. t
@@ -372,11 +372,32 @@ __device__ inline int jacobi_pair(double* gp, double* gq, int ne, double negl) {
   const double cs = rsq_f64(1.0 + t * t);
   const double sn = cs * t;
 #pragma unroll
-  for (int e = 0; e < EPJ; ++e)
+  for (int e = 0; e < EPJ; ++e) {
+    const double pu = cs * u[e] - sn * v[e];
+    const double qv = sn * u[e] + cs * v[e];
+    u[e] = pu;
+    v[e] = qv;
     if (!GUARD || e < ne) {
-      gp[e * LPP] = cs * u[e] - sn * v[e];
-      gq[e * LPP] = sn * u[e] + cs * v[e];
+      gp[e * LPP] = pu;
+      gq[e * LPP] = qv;
     }
+  }
+  double an = al - t * ga, bn = be + t * ga;
+  if (an < 1e-3 * al || bn < 1e-3 * be) {  // uniform over the LPP lanes of the pair
+    an = 0.0;
+    bn = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPJ; ++e) {
+      an += u[e] * u[e];
+      bn += v[e] * v[e];
+    }
+    an = group_sum<LPP>(an);
+    bn = group_sum<LPP>(bn);
+  }
+  if (sub == 0) {
+    *np = an;
+    *nq = bn;
+  }
   return 1;
 }
 
@@ -404,7 +425,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   const int n = (int)(a.row_ptr[i + 1] - a.row_ptr[i]);
   const int r = (int)(a.qptr[i + 1] - a.qptr[i]);
   const int ld = a.ld, ldm = a.ldm;
-  if ((n + LPP - 1) / LPP * LPP > ldm || ldm > ld) {  // host sizing violated: report, touch nothing
+  if (n > EPJ * LPP || (n + LPP - 1) / LPP * LPP > ldm || ldm > ld) {  // host sizing violated: report, touch nothing
     if (tid == 0) atomicOr(a.fail, 2);
     return;
   }
@@ -418,8 +439,8 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   double* beta = nrm + n;           // n: R_jj of a QR
   double* rv0 = beta + n;           // n: 1 / (x_jj - R_jj), scale of reflector j
   double* tau = rv0 + n;            // n: reflector coefficients
-  double* red = tau + n;            // 16
-  int* keep = (int*)(red + 16);     // n + 1
+  double* red = tau + n;            // 32: two values per wave
+  int* keep = (int*)(red + 32);     // n + 1
   int* piv = keep + n + 1;          // n
   int* pinv = piv + n;              // n
   int* cmap = pinv + n;             // n: physical column of logical column j (pivoting)
@@ -543,8 +564,17 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   const bool full = ldm >= EPJ * LPP;  // all EPJ rows of a lane inside the column: no checks
   int sweeps = 0;
   bool converged = false;
+  double* cn = nrm;  // squared column norms of M (nrm is free after the QR)
   for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
     int rotated = 0;
+    // fresh norms at each sweep bound the drift of the tracked updates
+    for (int l = g; l < n; l += NG) {
+      double s2 = 0.0;
+      for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+      s2 = group_sum<LPP>(s2);
+      if (sub == 0) cn[l] = s2;
+    }
+    __syncthreads();
     // pair g starts as (g, nn - 1 - g); position 0 stays, positions 1..nn-1 advance by
     // one per round (cyclically), so every pair meets once per sweep
     int P = g, Q = nn - 1 - g;
@@ -552,7 +582,8 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       if (g < npair && P < n && Q < n) {
         double* gp = M + (size_t)P * ldm + sub;
         double* gq = M + (size_t)Q * ldm + sub;
-        rotated |= full ? jacobi_pair<LPP, EPJ, false>(gp, gq, ne, negl) : jacobi_pair<LPP, EPJ, true>(gp, gq, ne, negl);
+        rotated |= full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + P, cn + Q, sub, ne, negl)
+                        : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + P, cn + Q, sub, ne, negl);
       }
       P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
       Q = (Q == nn - 1) ? 1 : Q + 1;
@@ -686,13 +717,13 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     part_a = wave_sum(part_a);
     if ((tid & 63) == 0) {
       red[tid >> 6] = part_n;
-      red[8 + (tid >> 6)] = part_a;
+      red[NT / 64 + (tid >> 6)] = part_a;
     }
     __syncthreads();
     double nn2 = 0.0, acc = 0.0;
     for (int w8 = 0; w8 < NT / 64; ++w8) {
       nn2 += red[w8];
-      acc += red[8 + w8];
+      acc += red[NT / 64 + w8];
     }
     const double nrmx = sqrt(nn2);
     const double yk = (yv[k] - acc) / nrmx;
@@ -826,23 +857,32 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       if (ns == 0) continue;
       const int mn = hist[2 * (NBKT + 1) + 2 * b];      // largest n in the bucket
       const int mr = hist[2 * (NBKT + 1) + 2 * b + 1];  // largest r in the bucket
-      // column stride = 8 (mod 32) doubles: consecutive columns start 16 banks apart
+      // column stride: 8 (mod 32) doubles (consecutive columns start 16 banks apart) unless
+      // a shorter stride fits more workgroups of the bucket on a CU (160 KiB of LDS,
+      // allocated in 512-byte granules); then the longest stride with the most workgroups
       int ld = ((mr + 1 + 23) / 32) * 32 + 8;
       if (ld < mr + 1) ld += 32;
       auto lds_of = [&](int l) {
-        return ((size_t)mn * l + 2 * (size_t)mr + 7 * (size_t)mn + 16) * sizeof(double) +
+        return ((size_t)mn * l + 2 * (size_t)mr + 7 * (size_t)mn + 32) * sizeof(double) +
                (4 * (size_t)mn + 1 + 2 * (size_t)mr) * sizeof(int);
       };
-      if (lds_of(ld) > 160 * 1024) ld = (mr + 1) | 1;  // largest systems: minimal odd stride
-      // M = R1^T columns: stride = 8 (mod 16) doubles, at most ld
-      // (at least mn rounded up to the 8 lanes of a Jacobi pair: those rows are zero-padded;
-      // for 48 < n <= 64 all 64 rows of the lanes, which saves the per-row checks)
+      // (the kernels also hold 256 bytes of static LDS; the launch checks the exact figure)
+      auto per_cu = [&](int l) { return (int)((160 * 1024) / ((lds_of(l) + 256 + 511) / 512 * 512)); };
+      for (int l = ld - 1, best = per_cu(ld); l >= mr + 1; --l)
+        if (per_cu(l) > best) {
+          best = per_cu(l);
+          ld = l;
+        }
+      // M = R1^T columns: stride = 8 (mod 16) doubles, at most ld, at least mn rounded up
+      // to the 8 lanes of a Jacobi pair (those rows are zero-padded). For 48 < n <= 64 this
+      // covers all EPJ rows of a lane of the instance chosen below (no per-row checks).
+      const int lpp = mn > 64 ? 16 : 8;  // lanes per column pair of the instance chosen below
       int ldm = ((mn + 8) / 16) * 16 + 8;
-      if (mn > 48 && mn <= 64 && ld >= 72) ldm = 72;
-      if (ldm > ld) ldm = (mn + 7) / 8 * 8;
+      if (ldm < (mn + lpp - 1) / lpp * lpp) ldm += 16;
+      if (ldm > ld) ldm = (mn + lpp - 1) / lpp * lpp;
       if (ldm > ld) ld = ldm;
       const size_t lds = lds_of(ld);
-      if (lds > 160 * 1024) {
+      if (lds + 256 > 160 * 1024) {
         set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
                   ") does not fit in LDS");
         s = WQ_EINVAL;
@@ -876,7 +916,8 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       ta.truncated = &R->truncated;
       ta.fail = &R->fail;
       // 8 lanes per column pair; systems with more than 64 constraints (more than 32
-      // pairs) take 512 threads. EPL: register elements of a column per lane.
+      // pairs) take 1024 threads with 16 lanes per column pair (more waves per CU to hide
+      // latency: such systems fill most of a CU's LDS on their own).
       const bool wide = mn > 64;
       const void* fn = nullptr;
       const char* kname = nullptr;  // timing record: the kernel instance
@@ -884,15 +925,25 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       {
         // EPR: register elements per lane of a column of A^T (r), EPJ: of M (n)
         const int epr = (mr + 7) / 8;
-        nt = wide ? 512 : 256;
-        if (!wide && epr <= 8) fn = (const void*)k_tsvd2<8, 8, 8, 256>, kname = "k_tsvd2<8,8,8,256>";
+        nt = wide ? 1024 : 256;
+        const bool j7 = mn > 48 && mn <= 56;  // 7 rows of M per lane
+        if (!wide && epr <= 8 && j7) fn = (const void*)k_tsvd2<8, 8, 7, 256>, kname = "k_tsvd2<8,8,7,256>";
+        else if (!wide && epr <= 16 && j7) fn = (const void*)k_tsvd2<8, 16, 7, 256>, kname = "k_tsvd2<8,16,7,256>";
+        else if (!wide && epr <= 8) fn = (const void*)k_tsvd2<8, 8, 8, 256>, kname = "k_tsvd2<8,8,8,256>";
         else if (!wide && epr <= 16) fn = (const void*)k_tsvd2<8, 16, 8, 256>, kname = "k_tsvd2<8,16,8,256>";
         else if (!wide) fn = (const void*)k_tsvd2<8, 32, 8, 256>, kname = "k_tsvd2<8,32,8,256>";
-        else if (epr <= 16) fn = (const void*)k_tsvd2<8, 16, 16, 512>, kname = "k_tsvd2<8,16,16,512>";
-        else fn = (const void*)k_tsvd2<8, 32, 16, 512>, kname = "k_tsvd2<8,32,16,512>";
+        else fn = (const void*)k_tsvd2<16, 16, 8, 1024>, kname = "k_tsvd2<16,16,8,1024>";
+      }
+      hipFuncAttributes fa{};
+      if (hipFuncGetAttributes(&fa, fn) != hipSuccess || fa.sharedSizeBytes + lds > 160 * 1024) {
+        set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
+                  ") does not fit in LDS");
+        s = WQ_EINVAL;
+        break;
       }
       if (lds > 64 * 1024 &&
           hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+        set_error("solve_weights: cannot raise the LDS limit of the TSVD kernel");
         s = WQ_EDEVICE;
         break;
       }
