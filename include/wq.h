@@ -317,8 +317,9 @@ void wq_batch_destroy(wq_batch* batch);
 
 /* wq_autotune_assembly: times the FP64 mass + stiffness assembly on `pts` for each
  * candidate length of the runs of consecutive row tiles that one XCD takes in turn
- * (4 .. 256), keeps the fastest in the handle (later assembly calls on it use it) and
- * returns it with its median time in ms. Synchronises `stream`. */
+ * (powers of two from 4 to 1024 below ceil(n_tiles / 8), then ceil(n_tiles / 8): one
+ * contiguous band of tiles per XCD), keeps the fastest in the handle (later assembly
+ * calls on it use it) and returns it with its median time in ms. Synchronises `stream`. */
 wq_status wq_autotune_assembly(wq_points* pts, const wq_weights* w, wq_stream stream, int32_t* chosen_chunk,
                                double* best_ms);
 

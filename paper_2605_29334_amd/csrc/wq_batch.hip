@@ -188,7 +188,11 @@ extern "C" wq_status wq_autotune_assembly(wq_points* P, const wq_weights* w, wq_
   DBuf M, K;
   WQ_TRY(dalloc_n<double>(M, P->nnz));
   WQ_TRY(dalloc_n<double>(K, P->nnz));
-  static const int cand[] = {4, 8, 16, 32, 64, 128, 256};
+  // run lengths up to one contiguous band of tiles per XCD
+  const int band = (int)((P->n_tiles + 7) / 8);
+  std::vector<int> cand;
+  for (int c = 4; c < band && c <= 1024; c *= 2) cand.push_back(c);
+  cand.push_back(band);
   hipEvent_t e0, e1;
   WQ_HIP(hipEventCreate(&e0));
   WQ_HIP(hipEventCreate(&e1));
