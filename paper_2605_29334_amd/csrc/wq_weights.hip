@@ -308,21 +308,61 @@ __device__ inline void householder(double x0, double s2, double* rjj, double* rv
   *tau = (b - x0) / b;
 }
 
-// Apply reflector j (stored unscaled in logical column j) to logical columns l > j, LPP
-// lanes per column, and recompute their trailing squared norms (rows > j) exactly.
+// double <-> lane moves for the pivot search
+__device__ inline double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Largest (value, index) of a wave, ties to the smaller index; every LPP-lane group holds
+// one candidate (the same bits in all its lanes). Lane 0 stores it at cv[w], ci[w].
+template <int LPP>
+__device__ inline void wave_argmax(double v, int i, double* cv, double* ci) {
+  if (LPP == 8) {  // the two groups of a 16-lane row: rotate the row by 8
+    const double ov = dpp_f64<0x128>(v);
+    const int oi = __builtin_amdgcn_mov_dpp(i, 0x128, 0xF, 0xF, false);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+  double bv = readlane_f64(v, 0);
+  int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+  for (int row = 1; row < 4; ++row) {
+    const double rv = readlane_f64(v, 16 * row);
+    const int ri = __builtin_amdgcn_readlane(i, 16 * row);
+    if (rv > bv || (rv == bv && ri < bi)) {
+      bv = rv;
+      bi = ri;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    cv[threadIdx.x >> 6] = bv;
+    ci[threadIdx.x >> 6] = (double)bi;
+  }
+}
+
+// Apply reflector j (stored unscaled in physical column pc: v_j = 1, v_m = x_m rv0 below)
+// to the logical columns l > j (physical phys(l): cur[l], except cj for l = bi, the pivot's
+// old position), LPP lanes per column, and recompute their trailing squared norms (rows
+// > j) exactly; returns this group's largest (norm, l), ties to the smaller l.
 template <int LPP, int EPR, int NG>
-__device__ inline void qr_update(double* G, int ld, int r, int ncol, int j, const int* cmap, double tau, double rv0,
-                                 double* nrm, int g, int sub) {
-  const double* cj = G + (size_t)cmap[j] * ld;
+__device__ inline double qr_update(double* G, int ld, int r, int ncol, int j, int pc, const int* cur, int bi, int cj,
+                                   double tau, double rv0, int g, int sub, int* best_l) {
+  const double* cp = G + (size_t)pc * ld;
+  double best = -1.0;
+  int bl = 0x7fffffff;
   for (int l = j + 1 + g; l < ncol; l += NG) {
-    double* cl = G + (size_t)cmap[l] * ld;
+    double* cl = G + (size_t)(l == bi ? cj : cur[l]) * ld;
     double x[EPR], v[EPR];
     double s = 0.0;
 #pragma unroll
     for (int e = 0; e < EPR; ++e) {
       const int m = j + sub + LPP * e;
       x[e] = (m < r) ? cl[m] : 0.0;
-      v[e] = (m == j) ? 1.0 : ((m < r) ? cj[m] * rv0 : 0.0);
+      v[e] = (m == j) ? 1.0 : ((m < r) ? cp[m] * rv0 : 0.0);
       s += v[e] * x[e];
     }
     s = tau * group_sum<LPP>(s);
@@ -337,8 +377,13 @@ __device__ inline void qr_update(double* G, int ld, int r, int ncol, int j, cons
       }
     }
     ns = group_sum<LPP>(ns);
-    if (sub == 0) nrm[l] = ns;
+    if (ns > best) {  // l ascends: ties keep the smaller l
+      best = ns;
+      bl = l;
+    }
   }
+  *best_l = bl;
+  return best;
 }
 
 // One Jacobi rotation of the columns p, q (LPP lanes, rows sub + e LPP at gp[e LPP],
@@ -435,15 +480,13 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   double* sig = wacc + r;           // n
   double* Rk = sig + n;             // n: b
   double* yv = Rk + n;              // n: c
-  double* nrm = yv + n;             // n: trailing column norms^2 in a QR
+  double* nrm = yv + n;             // n: squared column norms of M in the Jacobi sweeps
   double* beta = nrm + n;           // n: R_jj of a QR
-  double* rv0 = beta + n;           // n: 1 / (x_jj - R_jj), scale of reflector j
-  double* tau = rv0 + n;            // n: reflector coefficients
-  double* red = tau + n;            // 32: two values per wave
-  int* keep = (int*)(red + 32);     // n + 1
-  int* piv = keep + n + 1;          // n
+  double* red = beta + n;           // 96: block reductions [0, 32), pivot candidates [32, 96)
+  int* keep = (int*)(red + 96);     // n + 1
+  int* piv = keep + n + 1;          // n: the column permutation (two buffers in the QR)
   int* pinv = piv + n;              // n
-  int* cmap = pinv + n;             // n: physical column of logical column j (pivoting)
+  int* cmap = pinv + n;             // n
   int* ptc = cmap + n;              // r: support entry of the point's cell
   int* ptq = ptc + r;               // r: point index inside its cell
   // ---- 1. gather A^T, z, b
@@ -473,7 +516,6 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     for (int l = tid; l < n; l += NT) {
       Rk[l] = a.rhs[a.row_ptr[i] + l];
       piv[l] = l;
-      cmap[l] = l;
     }
   }
   __syncthreads();
@@ -487,52 +529,55 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   }
   const double negl = 1e-30 * block_sum(fro2, red);
   // ---- 2. Householder QR of A^T with column pivoting (largest trailing norm first).
-  // Columns are addressed through cmap (no data swaps); reflector j is kept unscaled in
-  // column j (v_j = 1, v_m = x_m / (x_j - R_jj) below), R_jj in beta[j].
-  for (int l = g; l < n; l += NG) {
-    double s2 = 0.0;
-    for (int m = sub; m < r; m += LPP) s2 += G[(size_t)l * ld + m] * G[(size_t)l * ld + m];
-    s2 = group_sum<LPP>(s2);
-    if (sub == 0) nrm[l] = s2;
+  // Columns are addressed through a permutation (no data swaps); reflector j is kept
+  // unscaled in its column (v_j = 1, v_m = x_m / (x_j - R_jj) below), R_jj in beta[j].
+  // One barrier per column: every thread picks the pivot from the per-wave candidates of
+  // the previous update and forms the reflector itself; the permutation and the
+  // candidates are double-buffered (read one buffer, write the other).
+  constexpr int NW = NT / 64;
+  {
+    double best = -1.0;
+    int bl = 0x7fffffff;
+    for (int l = g; l < n; l += NG) {
+      double s2 = 0.0;
+      for (int m = sub; m < r; m += LPP) s2 += G[(size_t)l * ld + m] * G[(size_t)l * ld + m];
+      s2 = group_sum<LPP>(s2);
+      if (s2 > best) {
+        best = s2;
+        bl = l;
+      }
+    }
+    wave_argmax<LPP>(best, bl, red + 32, red + 48);
   }
   __syncthreads();
   const int kmax = min(n, r);
   for (int j = 0; j < kmax; ++j) {
-    if (tid < 64) {  // pivot: largest trailing norm, ties to the smaller index
-      double best = -1.0;
-      int bi = j;
-      for (int l = j + tid; l < n; l += 64)
-        if (nrm[l] > best) {
-          best = nrm[l];
-          bi = l;
-        }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (tid == 0) {
-        if (bi != j) {
-          const double tn = nrm[j];
-          nrm[j] = nrm[bi];
-          nrm[bi] = tn;
-          int tp = piv[j];
-          piv[j] = piv[bi];
-          piv[bi] = tp;
-          tp = cmap[j];
-          cmap[j] = cmap[bi];
-          cmap[bi] = tp;
-        }
-        householder(G[(size_t)cmap[j] * ld + j], nrm[j], beta + j, rv0 + j, tau + j);
+    const double* cv = red + 32 + 32 * (j & 1);
+    const int* cur = (j & 1) ? cmap : piv;
+    int* nxt = (j & 1) ? piv : cmap;
+    double s2 = cv[0];
+    int bi = (int)cv[16];
+    for (int w = 1; w < NW; ++w) {
+      const double v = cv[w];
+      const int i2 = (int)cv[16 + w];
+      if (v > s2 || (v == s2 && i2 < bi)) {
+        s2 = v;
+        bi = i2;
       }
     }
-    __syncthreads();
-    qr_update<LPP, EPR, NG>(G, ld, r, n, j, cmap, tau[j], rv0[j], nrm, g, sub);
+    const int cj = cur[j], pc = cur[bi];
+    double rjj, rv0, tj;
+    householder(G[(size_t)pc * ld + j], s2, &rjj, &rv0, &tj);
+    if (tid == 0) beta[j] = rjj;
+    for (int l = tid; l < n; l += NT) nxt[l] = l == j ? pc : (l == bi ? cj : cur[l]);
+    int bl;
+    const double best = qr_update<LPP, EPR, NG>(G, ld, r, n, j, pc, cur, bi, cj, tj, rv0, g, sub, &bl);
+    double* nv = red + 32 + 32 * ((j + 1) & 1);
+    wave_argmax<LPP>(best, bl, nv, nv + 16);
     __syncthreads();
   }
+  // the final permutation: logical column l of R is constraint perm[l]
+  const int* perm = (kmax & 1) ? cmap : piv;
   // ---- M = R1^T: column k of M is row k of R1, M[k][i] = R1[k][i] = G[i][k] for i >= k.
   // M sits at the end of the G area (X is later written from the start; see step 3).
   double* M = G + (size_t)n * ld - (size_t)n * ldm;
@@ -543,7 +588,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     for (int s2 = 0; s2 < MS; ++s2) {
       const int e = tid + NT * s2;
       const int k = e / n, ii = e - k * n;
-      val[s2] = (e < n * n && ii >= k && k < kmax) ? (ii == k ? beta[k] : G[(size_t)cmap[ii] * ld + k]) : 0.0;
+      val[s2] = (e < n * n && ii >= k && k < kmax) ? (ii == k ? beta[k] : G[(size_t)perm[ii] * ld + k]) : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -553,7 +598,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       if (e < n * n) M[(size_t)k * ldm + ii] = val[s2];
     }
     for (int e = tid; e < n * (ldm - n); e += NT) M[(size_t)(e / (ldm - n)) * ldm + n + e % (ldm - n)] = 0.0;
-    for (int l = tid; l < n; l += NT) pinv[piv[l]] = l;
+    for (int l = tid; l < n; l += NT) pinv[perm[l]] = l;
   }
   __syncthreads();
   // ---- one-sided Jacobi on the columns of M, circle-method ordering. Rows [n, ldm) of
@@ -625,7 +670,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   for (int k = g; k < t; k += NG) {
     const double* wk = M + (size_t)keep[k] * ldm;
     double s2 = 0.0;
-    for (int m = sub; m < n; m += LPP) s2 += wk[m] * Rk[piv[m]];
+    for (int m = sub; m < n; m += LPP) s2 += wk[m] * Rk[perm[m]];
     s2 = group_sum<LPP>(s2);
     if (sub == 0) yv[k] = s2 / (sig[keep[k]] * sig[keep[k]]);
   }
@@ -863,7 +908,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       int ld = ((mr + 1 + 23) / 32) * 32 + 8;
       if (ld < mr + 1) ld += 32;
       auto lds_of = [&](int l) {
-        return ((size_t)mn * l + 2 * (size_t)mr + 7 * (size_t)mn + 32) * sizeof(double) +
+        return ((size_t)mn * l + 2 * (size_t)mr + 5 * (size_t)mn + 96) * sizeof(double) +
                (4 * (size_t)mn + 1 + 2 * (size_t)mr) * sizeof(int);
       };
       // (the kernels also hold 256 bytes of static LDS; the launch checks the exact figure)
