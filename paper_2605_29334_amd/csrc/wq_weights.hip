@@ -670,40 +670,51 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     if (sub == 0) yv[k] = s2 / (sig[keep[k]] * sig[keep[k]]);
   }
   // X[m][k] = z_m sum_l A[l][m] U[l][k] / sigma_k with U[l][k] = M[pinv[l]][keep[k]] /
-  // sigma_k. Columns k are written from the start of G, M's columns sit at the end: the
-  // writes of a chunk never reach a column of M still to be read (n ld >= k ld + n ldm -
-  // (n - k) ldm for k <= n), and a chunk's own columns are read before the barrier.
+  // sigma_k. The threads form NP parts of RW (r rounded up to whole waves) rows each; part
+  // g2 forms columns k0 + g2 KC + (0 .. KC-1) of a chunk of NP KC columns. Columns are
+  // written from the start of G, M's columns sit at the end: the writes of a chunk never
+  // reach a column of M still to be read (n ld >= k ld + n ldm - (n - k) ldm for k <= n,
+  // as ldm <= ld), and a chunk's own columns are read before the barrier.
   constexpr int KC = 8;
-  for (int k0 = 0; k0 < t; k0 += KC) {
-    double acc[KC];
-#pragma unroll
-    for (int kq = 0; kq < KC; ++kq) acc[kq] = 0.0;
-    const int m = tid;
-    if (m < r) {
+  {
+    const int RW = (r + 63) / 64 * 64;
+    const int NP = NT / RW;  // >= 1: r <= NT
+    const int g2 = tid / RW, m = tid - g2 * RW;
+    const bool row = g2 < NP && m < r;
+    const double* Dc = nullptr;
+    const uint8_t* sl = nullptr;
+    int mc = 0;
+    if (row) {
       const int64_t p = a.sptr[i] + ptc[m];
-      const int q = ptq[m];
       const int32_t c = a.scell[p];
-      const int mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
-      const double* Dc = a.D + a.dptr[c] + (int64_t)q * mc;
-      const uint8_t* sl = a.slot + a.soff[p];
-      for (int kk = 0; kk < mc; ++kk) {
-        const double av = Dc[kk];
-        const int ii = pinv[sl[kk]];
+      mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
+      Dc = a.D + a.dptr[c] + (int64_t)ptq[m] * mc;
+      sl = a.slot + a.soff[p];
+    }
+    for (int k0 = 0; k0 < t; k0 += NP * KC) {
+      const int kb = k0 + g2 * KC;
+      double acc[KC];
+#pragma unroll
+      for (int kq = 0; kq < KC; ++kq) acc[kq] = 0.0;
+      if (row)
+        for (int kk = 0; kk < mc; ++kk) {
+          const double av = Dc[kk];
+          const int ii = pinv[sl[kk]];
+#pragma unroll
+          for (int kq = 0; kq < KC; ++kq)
+            if (kb + kq < t) acc[kq] += av * M[(size_t)keep[kb + kq] * ldm + ii];
+        }
+      __syncthreads();
+      if (row) {
 #pragma unroll
         for (int kq = 0; kq < KC; ++kq)
-          if (k0 + kq < t) acc[kq] += av * M[(size_t)keep[k0 + kq] * ldm + ii];
+          if (kb + kq < t) {
+            const double sk = sig[keep[kb + kq]];
+            G[(size_t)(kb + kq) * ld + m] = z[m] * acc[kq] / (sk * sk);
+          }
       }
+      __syncthreads();
     }
-    __syncthreads();
-    if (m < r) {
-#pragma unroll
-      for (int kq = 0; kq < KC; ++kq)
-        if (k0 + kq < t) {
-          const double sk = sig[keep[k0 + kq]];
-          G[(size_t)(k0 + kq) * ld + m] = z[m] * acc[kq] / (sk * sk);
-        }
-    }
-    __syncthreads();
   }
   for (int m = tid; m < r; m += NT) wacc[m] = 0.0;
   __syncthreads();
