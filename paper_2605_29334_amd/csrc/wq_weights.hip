@@ -612,15 +612,22 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       if (sub == 0) cn[l] = s2;
     }
     __syncthreads();
-    // pair g starts as (g, nn - 1 - g); position 0 stays, positions 1..nn-1 advance by
-    // one per round (cyclically), so every pair meets once per sweep
-    int P = g, Q = nn - 1 - g;
+    // Circle method on positions 0..nn-1: pair p starts at positions (p, nn - 1 - p);
+    // position 0 stays, positions 1..nn-1 advance by one per round (cyclically), so every
+    // two positions meet once per sweep. Position 0 holds column nn - 1 (the padding
+    // column when n is odd), position c > 0 column c - 1; pair 0 (which holds the padding
+    // column in every round for odd n) runs on the last group, so for odd n the last pair
+    // group does no work and a wave whose groups are all past the real pairs skips the
+    // round entirely.
+    const int pp = (g + 1 == npair) ? 0 : g + 1;
+    int P = pp, Q = nn - 1 - pp;
     for (int rd = 0; rd < nn - 1; ++rd) {
-      if (g < npair && P < n && Q < n) {
-        double* gp = M + (size_t)P * ldm + sub;
-        double* gq = M + (size_t)Q * ldm + sub;
-        c2max = fmax(c2max, full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + P, cn + Q, sub, ne, negl)
-                                 : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + P, cn + Q, sub, ne, negl));
+      const int cP = P == 0 ? nn - 1 : P - 1, cQ = Q - 1;
+      if (g < npair && cP < n && cQ < n) {
+        double* gp = M + (size_t)cP * ldm + sub;
+        double* gq = M + (size_t)cQ * ldm + sub;
+        c2max = fmax(c2max, full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + cP, cn + cQ, sub, ne, negl)
+                                 : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + cP, cn + cQ, sub, ne, negl));
       }
       P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
       Q = (Q == nn - 1) ? 1 : Q + 1;
