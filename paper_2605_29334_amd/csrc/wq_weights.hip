@@ -468,8 +468,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   }
   double* G = sh;                   // n * ld: columns of A^T, later of X
   double* z = G + (size_t)n * ld;   // r
-  double* wacc = z + r;             // r
-  double* sig = wacc + r;           // n
+  double* sig = z + r;              // n
   double* Rk = sig + n;             // n: b
   double* yv = Rk + n;              // n: c
   double* nrm = yv + n;             // n: squared column norms of M in the Jacobi sweeps
@@ -723,18 +722,36 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       __syncthreads();
     }
   }
-  for (int m = tid; m < r; m += NT) wacc[m] = 0.0;
-  __syncthreads();
-  // ---- 4. CGS2 on the columns of X; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk; w += y_k q_k.
-  // y_k goes to ys (beta is free once M is formed): yv[k] = c_k is read by every thread
-  // after the column's last barrier but one, so it must not be overwritten in place.
+  // ---- 4. CGS2 on the columns of X; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk, w = Z Q y.
+  // The columns stay unnormalised: column j keeps x_j = R_jj q_j and iq[j] = 1 / R_jj, so
+  // no pass rescales them. The norm and the sum_j R_jk y_j of column k are reduced into
+  // red at the column's last barrier; every thread reads them at the start of column k+1
+  // (or after the loop), and thread 0 stores iq[k], ys[k] (beta is free once M is formed),
+  // visible from the next barrier on. yv[k] = c_k is only read.
   double* ys = beta;
+  double* iq = nrm;  // free after the Jacobi sweeps
   constexpr int DL = 4;  // lanes per dot product
+  double inv_prev = 0.0;  // 1 / R_{k-1,k-1}, in every thread
+  auto finish = [&](int k) {  // column k's R_kk and y_k from the reduced partial sums
+    double nn2 = 0.0, acc = 0.0;
+    for (int w8 = 0; w8 < NT / 64; ++w8) {
+      nn2 += red[w8];
+      acc += red[NT / 64 + w8];
+    }
+    const double nrmx = sqrt(nn2);
+    inv_prev = 1.0 / nrmx;
+    if (tid == 0) {
+      iq[k] = inv_prev;
+      ys[k] = (yv[k] - acc) / nrmx;
+    }
+  };
   for (int k = 0; k < t; ++k) {
+    if (k > 0) finish(k - 1);
     double* x = G + (size_t)k * ld;
     double part_n = 0.0, part_a = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
-      // h_j = q_j . x for j < k (DL lanes per j); R_jk accumulates both passes
+      // d_j = x_j . x for j < k (DL lanes per j): R_jk += d_j / R_jj (both passes), and
+      // the coefficient of x_j in the update, d_j / R_jj^2
       for (int jb = 0; jb < k; jb += NT / DL) {
         const int j = jb + tid / DL, s4 = tid % DL;
         double d = 0.0;
@@ -744,13 +761,15 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
         }
         d = group_sum<DL>(d);
         if (j < k && s4 == 0) {
-          Rk[j] = pass == 0 ? d : Rk[j] + d;
-          sig[j] = d;  // this pass's coefficients (sig is free now)
+          const double ij = (pass == 0 && j == k - 1) ? inv_prev : iq[j];
+          const double h = d * ij;
+          Rk[j] = pass == 0 ? h : Rk[j] + h;
+          sig[j] = h * ij;  // this pass's coefficients (sig is free now)
         }
       }
       __syncthreads();
-      // x -= sum_j h_j q_j (thread per row); the second pass also forms the partial sums
-      // of |x|^2 and of sum_j R_jk y_j
+      // x -= sum_j sig_j x_j (thread per row); the second pass also forms the partial
+      // sums of |x|^2 and of sum_j R_jk y_j
       for (int m = tid; m < r; m += NT) {
         double v0 = x[m], v1 = 0.0, v2 = 0.0, v3 = 0.0;  // four chains in flight
         int j = 0;
@@ -769,8 +788,9 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
         for (int j = tid; j < k; j += NT) part_a += Rk[j] * ys[j];
       if (pass == 0) __syncthreads();
     }
-    // one block reduction of the two partial sums (red was last read before the previous
-    // column's final barrier)
+    // one block reduction of the two partial sums into red (read by every thread at the
+    // start of column k+1; the previous values were read before this column's first
+    // barrier)
     part_n = wave_sum(part_n);
     part_a = wave_sum(part_a);
     if ((tid & 63) == 0) {
@@ -778,24 +798,21 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       red[NT / 64 + (tid >> 6)] = part_a;
     }
     __syncthreads();
-    double nn2 = 0.0, acc = 0.0;
-    for (int w8 = 0; w8 < NT / 64; ++w8) {
-      nn2 += red[w8];
-      acc += red[NT / 64 + w8];
-    }
-    const double nrmx = sqrt(nn2);
-    const double yk = (yv[k] - acc) / nrmx;
-    const double inv = 1.0 / nrmx;
-    for (int m = tid; m < r; m += NT) {
-      const double qm = x[m] * inv;
-      x[m] = qm;
-      wacc[m] += qm * yk;
-    }
-    if (tid == 0) ys[k] = yk;
-    __syncthreads();
   }
+  if (t > 0) finish(t - 1);
+  __syncthreads();
+  // w = Z sum_k x_k y_k / R_kk
   double* W = a.W + a.qptr[i];
-  for (int m = tid; m < r; m += NT) W[m] = z[m] * wacc[m];
+  for (int m = tid; m < r; m += NT) {
+    double v0 = 0.0, v1 = 0.0;
+    int k = 0;
+    for (; k + 2 <= t; k += 2) {
+      v0 += G[(size_t)k * ld + m] * (ys[k] * iq[k]);
+      v1 += G[(size_t)(k + 1) * ld + m] * (ys[k + 1] * iq[k + 1]);
+    }
+    if (k < t) v0 += G[(size_t)k * ld + m] * (ys[k] * iq[k]);
+    W[m] = z[m] * (v0 + v1);
+  }
 }
 
 
@@ -921,7 +938,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       int ld = ((mr + 1 + 23) / 32) * 32 + 8;
       if (ld < mr + 1) ld += 32;
       auto lds_of = [&](int l) {
-        return ((size_t)mn * l + 2 * (size_t)mr + 5 * (size_t)mn + 96) * sizeof(double) +
+        return ((size_t)mn * l + (size_t)mr + 5 * (size_t)mn + 96) * sizeof(double) +
                (4 * (size_t)mn + 1 + 2 * (size_t)mr) * sizeof(int);
       };
       // (the kernels also hold 256 bytes of static LDS; the launch checks the exact figure)
