@@ -220,6 +220,9 @@ __global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, i
   double* sw = sd + N * nd_cap;
   double* rho = sw + N * nw_cap;  // tangent only (nw_cap doubles)
   int2* smem = (int2*)(rho + (RES ? nw_cap : 0));
+  // the tile's entry records (16-byte aligned after the member records): decoding an entry
+  // then waits on LDS, not on a global load ahead of the entry's own loads
+  int4* sent = (int4*)(((uintptr_t)(smem + mem_cap) + 15) & ~(uintptr_t)15);
   const int64_t b = blockIdx.x;
   const int64_t turn = b / NXCD;
   const int64_t tile = (turn / chunk) * (NXCD * chunk) + (b % NXCD) * chunk + turn % chunk;
@@ -237,6 +240,7 @@ __global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, i
   if (RES && lane < TILE_ROWS) racc[lane] = 0.0;
   for (int t = lane; t < NACC * acc_stride; t += WAVE) acc[t] = 0.0;
   for (int t = lane; t < nm; t += WAVE) smem[t] = mem[m0 + t];
+  for (int t = lane; t < ne; t += WAVE) sent[t] = ent[e0 + t];
   __syncthreads();
   // Entries are pipelined DEPTH deep: while entry e is computed from the LDS stage, the
   // loads of entries e+1 .. e+DEPTH-1 are in flight in registers (ring slot e % DEPTH).
@@ -246,7 +250,7 @@ __global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, i
 #pragma unroll
     for (int u = 0; u < DEPTH; ++u)
       if (u < ne) {
-        en[u] = decode(ent[e0 + u], m0);
+        en[u] = decode(sent[u], m0);
         prefetch<K>(en[u], lane, S, smem, slot, p[u]);
       }
     stage<K>(en[0], lane, S, smem, p[0], sd, nd_cap, sw, nw_cap, rho);
@@ -278,7 +282,7 @@ __global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, i
           const int un = (u + 1) % DEPTH;
           if (e + 1 < ne) stage<K>(en[un], lane, S, smem, p[un], sd, nd_cap, sw, nw_cap, rho);
           if (e + DEPTH < ne) {  // slot u is free: start entry e + DEPTH
-            en[u] = decode(ent[e0 + e + DEPTH], m0);
+            en[u] = decode(sent[e + DEPTH], m0);
             prefetch<K>(en[u], lane, S, smem, slot, p[u]);
           }
           __syncthreads();
@@ -300,7 +304,7 @@ wq_status launch(const wq_points* P, const wq_weights* w, Src S, double* o0, dou
   const int nd_cap = P->max_tile_nd, nw_cap = P->max_tile_nw;
   const size_t lds = (size_t)NACC * P->max_tile_nnz * sizeof(double) +
                      (size_t)(N * (nd_cap + nw_cap) + (Fam<K>::RES ? nw_cap : 0)) * sizeof(double) +
-                     (size_t)P->max_tile_mem * sizeof(int2);
+                     (size_t)P->max_tile_mem * sizeof(int2) + 16 + (size_t)P->max_tile_ent * sizeof(int4);
   WQ_CHECK(lds <= 150 * 1024, WQ_EINVAL, "assemble: tile accumulators and stage exceed LDS");
   WQ_CHECK(nw_cap < 4096 && (int64_t)TILE_ROWS * 255 < 4096, WQ_EINVAL, "assemble: entry too large");
   if (K == 0) {
