@@ -462,7 +462,9 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   const int n = (int)(a.row_ptr[i + 1] - a.row_ptr[i]);
   const int r = (int)(a.qptr[i + 1] - a.qptr[i]);
   const int ld = a.ld, ldm = a.ldm;
-  if (n > EPJ * LPP || (n + LPP - 1) / LPP * LPP > ldm || ldm > ld) {  // host sizing violated: report, touch nothing
+  // host sizing violated (QR row slots, X formation rows, Jacobi rows, strides): report,
+  // touch nothing
+  if (r > EPR * LPP || r > NT || n > EPJ * LPP || (n + LPP - 1) / LPP * LPP > ldm || ldm > ld || ld < r + 1) {
     if (tid == 0) atomicOr(a.fail, 2);
     return;
   }
