@@ -262,7 +262,12 @@ wq_status wq_heat_step(const wq_points* pts, const wq_weights* w, const wq_heat_
  *   wq_server_poll: 1 = done (result copied to *out, ticket released), 0 = pending
  *     (wait = 0), negative = bad ticket. wait != 0 blocks until done.
  *   wq_server_stop: finishes queued and running requests, then frees the server.
- * Times are seconds since wq_server_start. */
+ * Times are seconds since wq_server_start.
+ * Setups are kept: after a request completes, its domain's mesh, points and weights (the
+ * part computed once per fixed domain, Section 2) stay on the device, still charged to
+ * the budget at the request's estimate. A later request whose mesh arrays are identical
+ * takes an idle one over (one request at a time) and skips that work; a request that
+ * needs room releases idle setups, least recently used first. */
 typedef struct wq_server wq_server;
 typedef enum { WQ_SOURCE_NONE = 0, WQ_SOURCE_MANUFACTURED = 1 } wq_source;
 typedef struct {
@@ -280,7 +285,9 @@ typedef struct {
   int64_t n_rows, nnz;
   double residual;            /* final ||R_free||_2 of the last step                     */
   double submitted, started, finished;
-  size_t hbm_estimate;        /* bytes charged against the budget while running          */
+  size_t hbm_estimate;        /* bytes charged against the budget while running, and
+                                 while the server holds the request's setup afterwards   */
+  int32_t setup_reused;       /* 1 if a held setup of the same domain was taken over     */
 } wq_result;
 wq_status wq_server_start(size_t hbm_budget_bytes, int32_t slots, wq_server** out);
 wq_status wq_server_submit(wq_server* server, const wq_request* req, double* T_out, int64_t* ticket);

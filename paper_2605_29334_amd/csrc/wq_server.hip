@@ -3,9 +3,12 @@
 // admitted in arrival order when a slot is free and their HBM estimate fits the budget;
 // each slot is a host thread with its own non-blocking stream, so admitted requests
 // overlap on the device. All state of a request stays on the device until its final
-// temperature is copied out.
+// temperature is copied out. The setup of a domain (mesh, points, weights: computed once
+// per fixed domain) stays on the device after its request; a later request on an
+// identical domain takes it over instead of recomputing it.
 #include "wq_internal.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -43,6 +46,31 @@ __global__ void k_manufactured_source(int64_t np, const double* __restrict__ x, 
   f[q] = lam * e * sx * sy - (dk * (ux * ux + uy * uy) + k * lap);
 }
 
+// A domain's setup on the device. Its request's HBM estimate stays charged to the budget
+// while it is held (running or idle); busy = in use by a running request (the points
+// handle carries per-call Newton scratch, so a setup serves one request at a time).
+struct Setup {
+  std::vector<int32_t> face_vtx, ext_fn;
+  std::vector<uint8_t> split;
+  std::vector<int64_t> ext_ptr, coef_ptr;
+  std::vector<double> coef, ctrl;
+  int32_t nv = 0;
+  wq_mesh* mesh = nullptr;
+  wq_points* pts = nullptr;
+  wq_weights* w = nullptr;
+  size_t bytes = 0;
+  bool busy = false;
+  int64_t last_used = 0;
+  void release() {
+    wq_weights_destroy(w);
+    wq_points_destroy(pts);
+    wq_mesh_destroy(mesh);
+    w = nullptr;
+    pts = nullptr;
+    mesh = nullptr;
+  }
+};
+
 struct Request {
   int64_t id = 0;
   // deep copies of the host inputs
@@ -58,7 +86,13 @@ struct Request {
   size_t est = 0;
   wq_result res{};
   bool done = false;
+  Setup* setup = nullptr;  // a held setup of the same domain taken over at admission
 };
+
+bool same_domain(const Setup& a, const Request& r) {
+  return a.nv == r.desc.nv && a.face_vtx == r.face_vtx && a.split == r.split && a.ext_ptr == r.ext_ptr &&
+         a.ext_fn == r.ext_fn && a.coef_ptr == r.coef_ptr && a.coef == r.coef && a.ctrl == r.ctrl;
+}
 
 double now_s(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -68,7 +102,9 @@ double now_s(std::chrono::steady_clock::time_point t0) {
 
 struct wq_server {
   int device = 0;
-  size_t budget = 0, in_use = 0;
+  size_t budget = 0, in_use = 0;  // in_use: running requests and held setups
+  std::vector<Setup*> setups;     // held setups (busy or idle)
+  int64_t clock = 0;              // admission counter (least recently used setup first)
   bool stopping = false;
   int64_t next_id = 1;
   std::deque<Request*> queue;
@@ -88,15 +124,24 @@ size_t hbm_estimate(const wq_mesh_desc& d) {
   return (size_t)16384 * (size_t)d.nf + (size_t)256 * (size_t)d.n_fn + ((size_t)8 << 20);
 }
 
-wq_status run_request(Request* r, hipStream_t st) {
-  wq_mesh* mesh = nullptr;
-  wq_points* pts = nullptr;
-  wq_weights* w = nullptr;
+// Runs one request. With r->setup, its mesh, points and weights are reused; otherwise
+// they are built and returned in *built (nullptr on failure) for the server to hold.
+wq_status run_request(Request* r, hipStream_t st, Setup** built) {
+  wq_mesh* mesh = r->setup ? r->setup->mesh : nullptr;
+  wq_points* pts = r->setup ? r->setup->pts : nullptr;
+  wq_weights* w = r->setup ? r->setup->w : nullptr;
   DBuf T, Td, S, dir, f;
-  wq_status s = wq_mesh_create(&r->desc, &mesh);
+  wq_status s = WQ_OK;
   int64_t n = 0, nnz = 0, np = 0;
-  if (s == WQ_OK) s = build_points(mesh, 0, st, &pts, &n, &nnz, &np);
-  if (s == WQ_OK) s = solve_weights(mesh, pts, WQ_FAM_MASS | WQ_FAM_DX | WQ_FAM_DY, 1e-12, st, &w, nullptr);
+  if (r->setup) {
+    n = pts->n_rows;
+    nnz = pts->nnz;
+    np = pts->n_points;
+  } else {
+    s = wq_mesh_create(&r->desc, &mesh);
+    if (s == WQ_OK) s = build_points(mesh, 0, st, &pts, &n, &nnz, &np);
+    if (s == WQ_OK) s = solve_weights(mesh, pts, WQ_FAM_MASS | WQ_FAM_DX | WQ_FAM_DY, 1e-12, st, &w, nullptr);
+  }
   if (s == WQ_OK) s = dalloc_n<double>(T, n);
   if (s == WQ_OK) s = dalloc_n<double>(Td, n);
   if (s == WQ_OK) s = dalloc_n<double>(S, nnz);
@@ -136,9 +181,29 @@ wq_status run_request(Request* r, hipStream_t st) {
   dfree(S);
   dfree(dir);
   dfree(f);
-  wq_weights_destroy(w);
-  wq_points_destroy(pts);
-  wq_mesh_destroy(mesh);
+  *built = nullptr;
+  if (!r->setup) {
+    if (s == WQ_OK) {
+      Setup* h = new Setup();
+      h->face_vtx = r->face_vtx;
+      h->ext_fn = r->ext_fn;
+      h->split = r->split;
+      h->ext_ptr = r->ext_ptr;
+      h->coef_ptr = r->coef_ptr;
+      h->coef = r->coef;
+      h->ctrl = r->ctrl;
+      h->nv = r->desc.nv;
+      h->mesh = mesh;
+      h->pts = pts;
+      h->w = w;
+      h->bytes = r->est;
+      *built = h;
+    } else {
+      wq_weights_destroy(w);
+      wq_points_destroy(pts);
+      wq_mesh_destroy(mesh);
+    }
+  }
   return s;
 }
 
@@ -148,23 +213,65 @@ void worker(wq_server* sv) {
   const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
   for (;;) {
     Request* r = nullptr;
+    std::vector<Setup*> evicted;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      // FIFO admission: the oldest request starts as soon as its estimate fits
+      // FIFO admission: the oldest request starts as soon as an idle setup of its domain
+      // is held, or its estimate fits once idle setups are released (least recently used
+      // first)
+      auto idle_match = [&](const Request& q) -> Setup* {
+        for (Setup* h : sv->setups)
+          if (!h->busy && same_domain(*h, q)) return h;
+        return nullptr;
+      };
+      auto idle_bytes = [&]() {
+        size_t b = 0;
+        for (Setup* h : sv->setups)
+          if (!h->busy) b += h->bytes;
+        return b;
+      };
       sv->cv_work.wait(lk, [&] {
-        return (sv->stopping && sv->queue.empty()) ||
-               (!sv->queue.empty() && sv->in_use + sv->queue.front()->est <= sv->budget);
+        if (sv->queue.empty()) return sv->stopping;
+        const Request& q = *sv->queue.front();
+        return idle_match(q) != nullptr || sv->in_use - idle_bytes() + q.est <= sv->budget;
       });
       if (sv->queue.empty()) break;
       r = sv->queue.front();
       sv->queue.pop_front();
-      sv->in_use += r->est;
+      r->setup = idle_match(*r);
+      if (r->setup) {
+        r->setup->busy = true;  // its bytes are already charged
+      } else {
+        while (sv->in_use + r->est > sv->budget) {
+          Setup* lru = nullptr;
+          for (Setup* h : sv->setups)
+            if (!h->busy && (!lru || h->last_used < lru->last_used)) lru = h;
+          sv->setups.erase(std::find(sv->setups.begin(), sv->setups.end(), lru));
+          sv->in_use -= lru->bytes;
+          evicted.push_back(lru);
+        }
+        sv->in_use += r->est;
+      }
+      r->res.setup_reused = r->setup ? 1 : 0;
       r->res.started = now_s(sv->t0);
     }
-    const wq_status s = have_stream ? run_request(r, st) : WQ_EDEVICE;
+    for (Setup* h : evicted) {  // device frees outside the lock
+      h->release();
+      delete h;
+    }
+    Setup* built = nullptr;
+    const wq_status s = have_stream ? run_request(r, st, &built) : WQ_EDEVICE;
     {
       std::lock_guard<std::mutex> lk(sv->mu);
-      sv->in_use -= r->est;
+      if (r->setup) {
+        r->setup->busy = false;
+        r->setup->last_used = ++sv->clock;
+      } else if (built) {
+        built->last_used = ++sv->clock;
+        sv->setups.push_back(built);  // r->est stays charged for the held setup
+      } else {
+        sv->in_use -= r->est;
+      }
       r->res.status = s;
       r->res.finished = now_s(sv->t0);
       r->done = true;
@@ -262,5 +369,9 @@ extern "C" void wq_server_stop(wq_server* sv) {
   sv->cv_work.notify_all();
   for (auto& t : sv->workers) t.join();
   for (auto& kv : sv->all) delete kv.second;
+  for (Setup* h : sv->setups) {
+    h->release();
+    delete h;
+  }
   delete sv;
 }

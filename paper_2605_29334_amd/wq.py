@@ -70,7 +70,7 @@ class Request(C.Structure):
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32), ("cg_iters", C.c_int32), ("n_rows", C.c_int64),
                 ("nnz", C.c_int64), ("residual", C.c_double), ("submitted", C.c_double), ("started", C.c_double),
-                ("finished", C.c_double), ("hbm_estimate", C.c_size_t)]
+                ("finished", C.c_double), ("hbm_estimate", C.c_size_t), ("setup_reused", C.c_int32)]
 
 _LIB = None
 

@@ -7,6 +7,9 @@
   the weights' conditioning).
 * Admission follows the HBM budget: with room for one request at a time they run one
   after the other; a request larger than the whole budget is refused.
+* A domain's setup (mesh, points, weights) is held after its request: a later request on
+  the same domain takes it over with bit-identical results, and an idle setup is released
+  when a request needs its room.
 """
 import numpy as np
 import pytest
@@ -117,3 +120,34 @@ def test_request_larger_than_budget_is_refused(pool):
         _submit(S, _requests(pool)[0])
     S.close()
     assert e.value.status == -2
+
+
+def test_held_setup_is_reused_with_identical_results(pool):
+    W = _wq()
+    req = (pool[3], KINDS[0], 0.3)
+    S = W.Server(8 << 30, 1)
+    T1, r1 = S.poll(_submit(S, req))
+    T2, r2 = S.poll(_submit(S, req))
+    S.close()
+    print(f"[gpu] held setup: first {r1['finished'] - r1['started']:.3f} s, reused {r2['finished'] - r2['started']:.3f} s")
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert r1["setup_reused"] == 0 and r2["setup_reused"] == 1
+    assert np.array_equal(T1, T2)
+
+
+def test_idle_setup_is_released_when_room_is_needed(pool):
+    W = _wq()
+    a, b = (pool[0], KINDS[0], 0.3), (pool[3], KINDS[0], 0.3)
+    probe = W.Server(8 << 30, 1)
+    ea = probe.poll(_submit(probe, a))[1]["hbm_estimate"]
+    eb = probe.poll(_submit(probe, b))[1]["hbm_estimate"]
+    probe.close()
+    # room for one held setup at a time: b releases a's idle setup, a is then rebuilt
+    S = W.Server(int(max(ea, eb) * 1.5), 1)
+    Ta1, r1 = S.poll(_submit(S, a))
+    _, r2 = S.poll(_submit(S, b))
+    Ta2, r3 = S.poll(_submit(S, a))
+    S.close()
+    assert [r["status"] for r in (r1, r2, r3)] == [0, 0, 0]
+    assert [r["setup_reused"] for r in (r1, r2, r3)] == [0, 0, 0]
+    assert np.array_equal(Ta1, Ta2)
