@@ -512,8 +512,9 @@ def row_gauss_rhs(fx, cl, supp_i, S_i, i, fam, cache):
 
 
 def sample_rows(fx, rows, families=("mass", "x", "y"), tau=1e-12, coef=None, glob=None):
-    """Everything the method produces for the given rows: S_i, Q_i, the system of each
-    family (A_fam, b_fam, z) with its weights, and mass / stiffness rows (coef: dict
+    """Everything the method produces for the given rows: S_i, Q_i, the points' coordinates
+    x, the system of each family (A_fam, b_fam, z) with its weights, and mass / stiffness
+    rows (coef: dict
     kind -> callable of x, or None for 1).
     glob: optional precomputed {"cls", "s", "cells"} of the whole mesh."""
     if glob is None:
@@ -555,6 +556,7 @@ def sample_rows(fx, rows, families=("mass", "x", "y"), tau=1e-12, coef=None, glo
             res["b_" + fam] = b
             res["A_" + fam] = A
         res["z"] = z
+        res["x"] = x
         cm = np.ones(len(q)) if coef is None or "mass" not in coef else coef["mass"](x)
         ck = np.ones(len(q)) if coef is None or "stiffness" not in coef else coef["stiffness"](x)
         if "mass" in families:
