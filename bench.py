@@ -185,7 +185,13 @@ def cpu_baseline(F, budget_s):
     """The FP64 oracle on this host: the whole-mesh classification and point allocation
     once, then the per-row path (points/basis of the row's cells, Gauss right-hand
     sides, TSVD weights, mass + stiffness row) on seeded sampled rows until the time
-    budget is spent; extrapolated to all rows."""
+    budget is spent; extrapolated to all rows. BLAS is held to one thread."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(F, budget_s)
+
+
+def _cpu_baseline(F, budget_s):
     import oracle as O
     t0 = time.perf_counter()
     cls = O.classify(F)
@@ -210,7 +216,7 @@ def cpu_baseline(F, budget_s):
     return {"value": total_nnz / total_s, "unit": "nnz/s", "cores": 1, "kind": "oracle",
             "sample": f"whole-mesh classification + point allocation ({t_glob:.1f} s) and {done} seeded "
                       f"rows of the per-row path ({t_rows:.1f} s), extrapolated to {F['n_fn']} rows; "
-                      f"one Python/NumPy thread"}
+                      f"one Python thread, BLAS limited to one thread"}
 
 
 def main():
