@@ -101,7 +101,10 @@ __global__ void k_gauss_basis(int32_t ncell, const int32_t* cell_face, const uin
 // Row i of the Gauss matrices on the CSR pattern, one 16-lane group per row:
 // b^f_i[slot(j)] = sum_{cells c in supp i} sum_g gw_g D^f N_i(g) D^f N_j(g).
 // Cells are visited in ascending order and each lane owns distinct slots at every
-// step, so the summation order is fixed (deterministic, no atomics).
+// step, so the summation order is fixed (deterministic, no atomics). Per cell, lane g of
+// the group forms u_g = gw_g D^f N_i(g) once into LDS for the whole group (a group is
+// part of one wave: its LDS accesses are ordered, the wave barriers only keep the
+// compiler from moving them). LDS: the families in the mask, compacted.
 __global__ void k_gauss_rows(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cfn_ptr,
                              const int64_t* soff, const uint8_t* slot, const uint8_t* kself, const int64_t* row_ptr,
                              const double* G0, const double* G1, const double* G2, const double* G3,
@@ -111,11 +114,13 @@ __global__ void k_gauss_rows(int64_t n, const int64_t* sptr, const int32_t* scel
   const int grp = threadIdx.x / GQ_GROUP;
   const int lane = threadIdx.x % GQ_GROUP;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / GQ_GROUP) + grp;
-  double* acc = sh_acc + (size_t)grp * 4 * max_row;
+  const int nfam = __popc(mask);
+  double* acc = sh_acc + (size_t)grp * nfam * max_row;
+  double* su = sh_acc + (size_t)(blockDim.x / GQ_GROUP) * nfam * max_row + grp * 4 * GQ_GROUP;
   const double* Gs[4] = {G0, G1, G2, G3};
   double* Rs[4] = {R0, R1, R2, R3};
   const bool active = i < n;
-  for (int t = lane; t < 4 * max_row; t += GQ_GROUP) acc[t] = 0.0;
+  for (int t = lane; t < nfam * max_row; t += GQ_GROUP) acc[t] = 0.0;
   __syncthreads();
   if (active) {
     for (int64_t p = sptr[i]; p < sptr[i + 1]; ++p) {
@@ -124,24 +129,38 @@ __global__ void k_gauss_rows(int64_t n, const int64_t* sptr, const int32_t* scel
       const int m = (int)(cfn_ptr[c + 1] - f0);
       const int ks = kself[p];
       const uint8_t* sl = slot + soff[p];
+      for (int fam = 0, a = 0; fam < 4; ++fam) {
+        if (!(mask & (1u << fam))) continue;
+        su[a * GQ_GROUP + lane] = gw[16 * (int64_t)c + lane] * Gs[fam][16 * f0 + lane * m + ks];
+        ++a;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int k = lane; k < m; k += GQ_GROUP) {
         const int sk = sl[k];
-        for (int fam = 0; fam < 4; ++fam) {
+        for (int fam = 0, a = 0; fam < 4; ++fam) {
           if (!(mask & (1u << fam))) continue;
           const double* G = Gs[fam] + 16 * f0;
+          const double* u = su + a * GQ_GROUP;
           double v = 0.0;
-          for (int g = 0; g < 16; ++g) v += (gw[16 * (int64_t)c + g] * G[g * m + ks]) * G[g * m + k];
-          acc[fam * max_row + sk] += v;
+          for (int g = 0; g < 16; ++g) v += u[g] * G[g * m + k];
+          acc[a * max_row + sk] += v;
+          ++a;
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   __syncthreads();
   if (active) {
     const int ni = (int)(row_ptr[i + 1] - row_ptr[i]);
-    for (int fam = 0; fam < 4; ++fam) {
+    for (int fam = 0, a = 0; fam < 4; ++fam) {
       if (!(mask & (1u << fam))) continue;
-      for (int t = lane; t < ni; t += GQ_GROUP) Rs[fam][row_ptr[i] + t] = acc[fam * max_row + t];
+      for (int t = lane; t < ni; t += GQ_GROUP) Rs[fam][row_ptr[i] + t] = acc[a * max_row + t];
+      ++a;
     }
   }
 }
@@ -860,7 +879,9 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     if (fam_mask & (1u << f)) s = dalloc_n<double>(w->rhs[f], P->nnz);
   if (s == WQ_OK) {
     const int rows_per_block = BS / GQ_GROUP;
-    const size_t lds = (size_t)rows_per_block * 4 * P->max_row * sizeof(double);
+    int nfam = 0;
+    for (int f = 0; f < 4; ++f) nfam += (fam_mask >> f) & 1;
+    const size_t lds = (size_t)rows_per_block * (nfam * P->max_row + 4 * GQ_GROUP) * sizeof(double);
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute((const void*)k_gauss_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
             hipSuccess)
