@@ -181,33 +181,63 @@ constexpr int NB_N = 5, NB_R = 7, NBKT = NB_N * NB_R;
 // full rank (2 r n^2 - 2 n^3 / 3); the measure of useful work for the roofline.
 __global__ void k_sys_bucket(int64_t n, const int64_t* row_ptr, const int64_t* qptr, uint8_t* bkt, int* hist,
                              int* bad, unsigned long long* flops) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int ni = (int)(row_ptr[i + 1] - row_ptr[i]);
-  const int ri = (int)(qptr[i + 1] - qptr[i]);
-  int bn = 0, br = 0;
-  while (bn < NB_N && ni > c_nb[bn]) ++bn;
-  while (br < NB_R && ri > c_rb[br]) ++br;
-  if (bn == NB_N || br == NB_R) {
-    atomicOr(bad, 1);
-    bn = NB_N - 1;
-    br = NB_R - 1;
+  // per-workgroup tallies in LDS, then one global update per touched bucket
+  __shared__ int cnt[NBKT], mxn[NBKT], mxr[NBKT];
+  __shared__ unsigned long long fl[NBKT];
+  for (int b = threadIdx.x; b < NBKT; b += blockDim.x) {
+    cnt[b] = 0;
+    mxn[b] = 0;
+    mxr[b] = 0;
+    fl[b] = 0ULL;
   }
-  const int b = bn * NB_R + br;
-  bkt[i] = (uint8_t)b;
-  atomicAdd(&hist[b], 1);
-  atomicMax(&hist[2 * (NBKT + 1) + 2 * b], ni);  // per-bucket maxima (LDS sizing)
-  atomicMax(&hist[2 * (NBKT + 1) + 2 * b + 1], ri);
-  const long long nn = ni, rr = ri;
-  atomicAdd(&flops[b], (unsigned long long)(6 * rr * nn * nn - 2 * nn * nn * nn));
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int ni = (int)(row_ptr[i + 1] - row_ptr[i]);
+    const int ri = (int)(qptr[i + 1] - qptr[i]);
+    int bn = 0, br = 0;
+    while (bn < NB_N && ni > c_nb[bn]) ++bn;
+    while (br < NB_R && ri > c_rb[br]) ++br;
+    if (bn == NB_N || br == NB_R) {
+      atomicOr(bad, 1);
+      bn = NB_N - 1;
+      br = NB_R - 1;
+    }
+    const int b = bn * NB_R + br;
+    bkt[i] = (uint8_t)b;
+    atomicAdd(&cnt[b], 1);
+    atomicMax(&mxn[b], ni);  // per-bucket maxima (LDS sizing)
+    atomicMax(&mxr[b], ri);
+    const long long nn = ni, rr = ri;
+    atomicAdd(&fl[b], (unsigned long long)(6 * rr * nn * nn - 2 * nn * nn * nn));
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < NBKT; b += blockDim.x)
+    if (cnt[b]) {
+      atomicAdd(&hist[b], cnt[b]);
+      atomicMax(&hist[2 * (NBKT + 1) + 2 * b], mxn[b]);
+      atomicMax(&hist[2 * (NBKT + 1) + 2 * b + 1], mxr[b]);
+      atomicAdd(&flops[b], fl[b]);
+    }
 }
 
+// Bucket lists: each workgroup reserves one range per touched bucket; the order of the
+// systems inside a bucket is irrelevant (they are independent).
 __global__ void k_sys_scatter(int64_t n, const uint8_t* bkt, const int64_t* start, int* cur, int32_t* lists) {
+  __shared__ int cnt[NBKT], base[NBKT];
+  for (int b = threadIdx.x; b < NBKT; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int b = bkt[i];
-  const int k = atomicAdd(&cur[b], 1);
-  lists[start[b] + k] = (int32_t)i;
+  int b = -1, k = 0;
+  if (i < n) {
+    b = bkt[i];
+    k = atomicAdd(&cnt[b], 1);
+  }
+  __syncthreads();
+  for (int bb = threadIdx.x; bb < NBKT; bb += blockDim.x)
+    if (cnt[bb]) base[bb] = atomicAdd(&cur[bb], cnt[bb]);
+  __syncthreads();
+  if (b >= 0) lists[start[b] + base[b] + k] = (int32_t)i;
 }
 
 // Cross-lane moves inside a row of 16 lanes by DPP (VALU, no LDS round trip).
