@@ -288,7 +288,7 @@ struct TsvdArgs {
   int64_t nsys;
   int ld;   // leading dimension (doubles) of a column of A^T in LDS, >= r_max + 1
   int ldm;  // leading dimension of a column of R^T in LDS, >= n_max rounded up to 8, <= ld
-  int fam;
+  int nfam;  // families in this launch: workgroup b solves system b % nsys of family b / nsys
   double tau;
   const int64_t* sptr;
   const int32_t* scell;
@@ -300,10 +300,10 @@ struct TsvdArgs {
   const uint8_t* kself;
   const int64_t* row_ptr;
   const int64_t* qptr;
-  const double* D;    // basis data of the family
-  const double* DN;   // values (for Z)
-  const double* rhs;  // Gauss right-hand side of the family, aligned with col
-  double* W;          // output weights aligned with qidx
+  const double* D[4];    // basis data of each family of the launch
+  const double* DN;      // values (for Z)
+  const double* rhs[4];  // Gauss right-hand side of each family, aligned with col
+  double* W[4];          // output weights of each family, aligned with qidx
   int* max_sweeps;
   unsigned long long* min_kept;     // bits of a double
   unsigned long long* max_dropped;  // bits of a double
@@ -504,7 +504,9 @@ template <int LPP, int EPR, int EPJ, int NT>
 __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   extern __shared__ double sh[];
   constexpr int NG = NT / LPP;  // lane groups
-  const int64_t sys = blockIdx.x;
+  const int fs = (int)(blockIdx.x / a.nsys);
+  const int64_t sys = blockIdx.x - (int64_t)fs * a.nsys;
+  const double* AD = a.D[fs];
   const int tid = threadIdx.x;
   const int g = tid / LPP, sub = tid % LPP;
   const int64_t i = a.rows[sys];
@@ -540,7 +542,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       const int32_t c = a.scell[p];
       const int m = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
       const int np = (int)(a.cell_pt_off[c + 1] - a.cell_pt_off[c]);
-      const double* Dc = a.D + a.dptr[c];
+      const double* Dc = AD + a.dptr[c];
       const double* Nc = a.DN + a.dptr[c];
       const uint8_t* sl = a.slot + a.soff[p];
       const int ks = a.kself[p];
@@ -556,7 +558,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       moff += np;
     }
     for (int l = tid; l < n; l += NT) {
-      Rk[l] = a.rhs[a.row_ptr[i] + l];
+      Rk[l] = a.rhs[fs][a.row_ptr[i] + l];
       piv[l] = l;
     }
   }
@@ -745,7 +747,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       const int64_t p = a.sptr[i] + ptc[m];
       const int32_t c = a.scell[p];
       mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
-      Dc = a.D + a.dptr[c] + (int64_t)ptq[m] * mc;
+      Dc = AD + a.dptr[c] + (int64_t)ptq[m] * mc;
       sl = a.slot + a.soff[p];
     }
     for (int k0 = 0; k0 < t; k0 += NP * KC) {
@@ -853,7 +855,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   if (t > 0) finish(t - 1);
   __syncthreads();
   // w = Z sum_k x_k y_k / R_kk
-  double* W = a.W + a.qptr[i];
+  double* W = a.W[fs] + a.qptr[i];
   for (int m = tid; m < r; m += NT) {
     double v0 = 0.0, v1 = 0.0;
     int k = 0;
@@ -975,11 +977,22 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     Rep init{0, 0, 0x7ff0000000000000ULL /* +inf */, 0ULL, 0ULL};
     if (hipMemcpyAsync(drep.p, &init, sizeof(Rep), hipMemcpyHostToDevice, st) != hipSuccess) s = WQ_EDEVICE;
   }
+  // one launch per size bucket covers every family asked for (more workgroups per launch,
+  // fewer partly idle tails)
+  int nfam = 0;
+  const double* famD[4] = {nullptr, nullptr, nullptr, nullptr};
+  const double* famR[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* famW[4] = {nullptr, nullptr, nullptr, nullptr};
   for (int f = 0; f < 4 && s == WQ_OK; ++f) {
     if (!(fam_mask & (1u << f))) continue;
     s = dalloc_n<double>(w->W[f], (size_t)(P->qidx.bytes / sizeof(int32_t)));
-    const double* D = f == 0 ? P->DN.as<double>() : f == 1 ? P->DX.as<double>() : f == 2 ? P->DY.as<double>()
-                                                                                        : P->DL.as<double>();
+    famD[nfam] = f == 0 ? P->DN.as<double>() : f == 1 ? P->DX.as<double>() : f == 2 ? P->DY.as<double>()
+                                                                                  : P->DL.as<double>();
+    famR[nfam] = w->rhs[f].as<double>();
+    famW[nfam] = w->W[f].as<double>();
+    ++nfam;
+  }
+  {
     for (int b = 0; b < NBKT && s == WQ_OK; ++b) {
       const int64_t ns = hist[b];
       if (ns == 0) continue;
@@ -1022,7 +1035,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       ta.nsys = ns;
       ta.ld = ld;
       ta.ldm = ldm;
-      ta.fam = f;
+      ta.nfam = nfam;
       ta.tau = tau;
       ta.sptr = P->supp_ptr.as<int64_t>();
       ta.scell = P->supp_cell.as<int32_t>();
@@ -1034,10 +1047,12 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       ta.kself = P->kself.as<uint8_t>();
       ta.row_ptr = P->row_ptr.as<int64_t>();
       ta.qptr = P->qptr.as<int64_t>();
-      ta.D = D;
+      for (int q = 0; q < 4; ++q) {
+        ta.D[q] = famD[q];
+        ta.rhs[q] = famR[q];
+        ta.W[q] = famW[q];
+      }
       ta.DN = P->DN.as<double>();
-      ta.rhs = w->rhs[f].as<double>();
-      ta.W = w->W[f].as<double>();
       ta.max_sweeps = &R->max_sweeps;
       ta.min_kept = &R->min_kept;
       ta.max_dropped = &R->max_dropped;
@@ -1075,9 +1090,9 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
         s = WQ_EDEVICE;
         break;
       }
-      KTimer tm(kname, (int64_t)bflops[b], st);
+      KTimer tm(kname, (int64_t)bflops[b] * nfam, st);
       void* args[] = {&ta};
-      if (hipLaunchKernel(fn, dim3((unsigned)ns), dim3(nt), args, lds, st) != hipSuccess) {
+      if (hipLaunchKernel(fn, dim3((unsigned)(ns * nfam)), dim3(nt), args, lds, st) != hipSuccess) {
         set_error("solve_weights: TSVD launch failed");
         s = WQ_EDEVICE;
       }
