@@ -1017,7 +1017,10 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       // M = R1^T columns: stride = 8 (mod 16) doubles, at most ld, at least mn rounded up
       // to the 8 lanes of a Jacobi pair (those rows are zero-padded). For 48 < n <= 64 this
       // covers all EPJ rows of a lane of the instance chosen below (no per-row checks).
-      const int lpp = mn > 64 ? 16 : 8;  // lanes per column pair of the instance chosen below
+      // n > 64: a 512-thread instance (8 lanes per pair) where two workgroups fit on a CU
+      // (n <= 96, r <= 128), else the 1024-thread one (16 lanes per pair)
+      const bool w512 = mn > 64 && mn <= 96 && mr <= 128 && per_cu(ld) >= 2;
+      const int lpp = (mn > 64 && !w512) ? 16 : 8;  // lanes per column pair of the instance
       int ldm = ((mn + 8) / 16) * 16 + 8;
       if (ldm < (mn + lpp - 1) / lpp * lpp) ldm += 16;
       if (ldm > ld) ldm = (mn + lpp - 1) / lpp * lpp;
@@ -1068,13 +1071,14 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       {
         // EPR: register elements per lane of a column of A^T (r), EPJ: of M (n)
         const int epr = (mr + 7) / 8;
-        nt = wide ? 1024 : 256;
+        nt = !wide ? 256 : w512 ? 512 : 1024;
         const bool j7 = mn > 48 && mn <= 56;  // 7 rows of M per lane
         if (!wide && epr <= 8 && j7) fn = (const void*)k_tsvd2<8, 8, 7, 256>, kname = "k_tsvd2<8,8,7,256>";
         else if (!wide && epr <= 16 && j7) fn = (const void*)k_tsvd2<8, 16, 7, 256>, kname = "k_tsvd2<8,16,7,256>";
         else if (!wide && epr <= 8) fn = (const void*)k_tsvd2<8, 8, 8, 256>, kname = "k_tsvd2<8,8,8,256>";
         else if (!wide && epr <= 16) fn = (const void*)k_tsvd2<8, 16, 8, 256>, kname = "k_tsvd2<8,16,8,256>";
         else if (!wide) fn = (const void*)k_tsvd2<8, 32, 8, 256>, kname = "k_tsvd2<8,32,8,256>";
+        else if (w512) fn = (const void*)k_tsvd2<8, 16, 12, 512>, kname = "k_tsvd2<8,16,12,512>";
         else fn = (const void*)k_tsvd2<16, 16, 8, 1024>, kname = "k_tsvd2<16,16,8,1024>";
       }
       hipFuncAttributes fa{};
