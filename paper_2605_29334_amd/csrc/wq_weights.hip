@@ -1020,7 +1020,10 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       // n > 64: a 512-thread instance (8 lanes per pair) where two workgroups fit on a CU
       // (n <= 96, r <= 128), else the 1024-thread one (16 lanes per pair)
       const bool w512 = mn > 64 && mn <= 96 && mr <= 128 && per_cu(ld) >= 2;
-      const int lpp = (mn > 64 && !w512) ? 16 : 8;  // lanes per column pair of the instance
+      // 48 < n <= 64, 64 < r <= 128, at most three workgroups per CU by LDS: 512 threads
+      // with 16 lanes per pair and per column (twice the resident waves)
+      const bool m512 = mn > 48 && mn <= 64 && mr > 64 && mr <= 128 && per_cu(ld) <= 3;
+      const int lpp = ((mn > 64 && !w512) || m512) ? 16 : 8;  // lanes per column pair of the instance
       int ldm = ((mn + 8) / 16) * 16 + 8;
       if (ldm < (mn + lpp - 1) / lpp * lpp) ldm += 16;
       if (ldm > ld) ldm = (mn + lpp - 1) / lpp * lpp;
@@ -1071,9 +1074,10 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       {
         // EPR: register elements per lane of a column of A^T (r), EPJ: of M (n)
         const int epr = (mr + 7) / 8;
-        nt = !wide ? 256 : w512 ? 512 : 1024;
+        nt = !wide ? (m512 ? 512 : 256) : w512 ? 512 : 1024;
         const bool j7 = mn > 48 && mn <= 56;  // 7 rows of M per lane
-        if (!wide && epr <= 8 && j7) fn = (const void*)k_tsvd2<8, 8, 7, 256>, kname = "k_tsvd2<8,8,7,256>";
+        if (m512) fn = (const void*)k_tsvd2<16, 8, 4, 512>, kname = "k_tsvd2<16,8,4,512>";
+        else if (!wide && epr <= 8 && j7) fn = (const void*)k_tsvd2<8, 8, 7, 256>, kname = "k_tsvd2<8,8,7,256>";
         else if (!wide && epr <= 16 && j7) fn = (const void*)k_tsvd2<8, 16, 7, 256>, kname = "k_tsvd2<8,16,7,256>";
         else if (!wide && epr <= 8) fn = (const void*)k_tsvd2<8, 8, 8, 256>, kname = "k_tsvd2<8,8,8,256>";
         else if (!wide && epr <= 16) fn = (const void*)k_tsvd2<8, 16, 8, 256>, kname = "k_tsvd2<8,16,8,256>";
