@@ -1019,11 +1019,20 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       // covers all EPJ rows of a lane of the instance chosen below (no per-row checks).
       // n > 64: a 512-thread instance (8 lanes per pair) where two workgroups fit on a CU
       // (n <= 96, r <= 128), else the 1024-thread one (16 lanes per pair)
-      const bool w512 = mn > 64 && mn <= 96 && mr <= 128 && per_cu(ld) >= 2;
-      // 48 < n <= 64, 64 < r <= 128, at most three workgroups per CU by LDS: 512 threads
-      // with 16 lanes per pair and per column (twice the resident waves)
-      const bool m512 = mn > 48 && mn <= 64 && mr > 64 && mr <= 128 && per_cu(ld) <= 3;
-      const int lpp = ((mn > 64 && !w512) || m512) ? 16 : 8;  // lanes per column pair of the instance
+      // The thread count and the lanes per pair or column set the summation orders, so they
+      // follow from the bucket's bounds alone: a system gets the same bits whatever else is
+      // in the bucket (a mesh alone or in a batch). Only strides and per-lane slot counts,
+      // which do not change the arithmetic, follow the bucket's actual maxima.
+      //  - 64 < n <= 96, r <= 128: 512 threads, 8 lanes per pair (two workgroups per CU fit
+      //    where the 1024-thread instance's registers allow one);
+      //  - 48 < n <= 64, 80 < r <= 128: 512 threads, 16 lanes per pair and per column (these
+      //    buckets hold two or three workgroups per CU by LDS: twice the resident waves);
+      //  - other n > 64: 1024 threads, 16 lanes; other n <= 64: 256 threads, 8 lanes.
+      const int bn = b / NB_R, br = b % NB_R;
+      const bool w512 = bn == 3 && br <= 3;
+      const bool m512 = bn == 2 && br >= 2 && br <= 3;
+      const bool wide = bn >= 3;
+      const int lpp = ((wide && !w512) || m512) ? 16 : 8;  // lanes per column pair of the instance
       int ldm = ((mn + 8) / 16) * 16 + 8;
       if (ldm < (mn + lpp - 1) / lpp * lpp) ldm += 16;
       if (ldm > ld) ldm = (mn + lpp - 1) / lpp * lpp;
@@ -1067,7 +1076,6 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       // 8 lanes per column pair; systems with more than 64 constraints (more than 32
       // pairs) take 1024 threads with 16 lanes per column pair (more waves per CU to hide
       // latency: such systems fill most of a CU's LDS on their own).
-      const bool wide = mn > 64;
       const void* fn = nullptr;
       const char* kname = nullptr;  // timing record: the kernel instance
       int nt = 0;
