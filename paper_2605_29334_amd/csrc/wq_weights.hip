@@ -487,6 +487,87 @@ __device__ inline double jacobi_pair(double* gp, double* gq, double* np, double*
   return ga * ga / (al * be);  // cos^2 of the angle between the columns before the rotation
 }
 
+// One rotation of the pair (s, t) where the lanes of the group hold column s in registers
+// (u, squared norm al, the same in every lane of the group) and column t sits in LDS at gq
+// (squared norm *nq). Only column t is read and written back. Returns cos^2 of the angle
+// between the columns before the rotation, 0 when the pair needs none.
+template <int LPP, int EPJ, bool GUARD>
+__device__ inline double jacobi_held(double (&u)[EPJ], double& al, double* gq, double* nq, int sub, int ne,
+                                     double negl) {
+  double v[EPJ];
+#pragma unroll
+  for (int e = 0; e < EPJ; ++e) v[e] = (!GUARD || e < ne) ? gq[e * LPP] : 0.0;
+  const double be = *nq;
+  double ga = 0;
+#pragma unroll
+  for (int e = 0; e < EPJ; ++e) ga += u[e] * v[e];
+  ga = group_sum<LPP>(ga);
+  if (!(ga * ga > 1e-30 * al * be && fmin(al, be) > negl)) return 0.0;
+  // t = tan of the rotation angle (the smaller root), c = 1 / sqrt(1 + t^2), s = c t
+  const double dba = be - al;
+  const double h = dba * dba + 4.0 * ga * ga;
+  const double t = (dba >= 0 ? 2.0 * ga : -2.0 * ga) * rcp_f64(fabs(dba) + h * rsq_f64(h));
+  const double cs = rsq_f64(1.0 + t * t);
+  const double sn = cs * t;
+#pragma unroll
+  for (int e = 0; e < EPJ; ++e) {
+    const double pu = cs * u[e] - sn * v[e];
+    const double qv = sn * u[e] + cs * v[e];
+    u[e] = pu;
+    v[e] = qv;
+    if (!GUARD || e < ne) gq[e * LPP] = qv;
+  }
+  double an = al - t * ga, bn = be + t * ga;
+  if (an < 1e-3 * al || bn < 1e-3 * be) {  // uniform over the LPP lanes of the pair
+    an = 0.0;
+    bn = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPJ; ++e) {
+      an += u[e] * u[e];
+      bn += v[e] * v[e];
+    }
+    an = group_sum<LPP>(an);
+    bn = group_sum<LPP>(bn);
+  }
+  const double c2 = ga * ga / (al * be);
+  al = an;
+  if (sub == 0) *nq = bn;
+  return c2;
+}
+
+// Recursive-halving pair ordering for the Jacobi sweeps. A block of m columns [lo, hi)
+// splits into S = its first ceil(m/2) columns and T = the rest; the S x T pairs take
+// ceil(m/2) rounds, in which the group of S column j meets T column (j + round) mod
+// ceil(m/2) (when that exists), holding its S column in registers throughout; then both
+// halves recurse, side by side. Level L holds the blocks L splits down. Every pair of
+// the n columns meets once per sweep, and in each round a column is touched by one group.
+__device__ inline int halving_groups(int m) { return m >= 2 ? (m + 1) / 2 : 0; }
+// groups used k levels below a block of m columns (its parts there have floor or ceil of
+// m / 2^k columns; m mod 2^k of them the larger)
+__device__ inline int halving_groups_at(int m, int k) {
+  const int q0 = m >> k, c = m - (q0 << k);
+  return c * halving_groups(q0 + 1) + ((1 << k) - c) * halving_groups(q0);
+}
+struct HalvingSlot {
+  int s, tlo, tcnt, h, j;  // S column, first T column, T count, S count of the block, rank in S
+};
+// the block and S column of group g at level L (j >= h: the group has no S column there)
+__device__ inline HalvingSlot halving_slot(int n, int L, int g) {
+  int lo = 0, hi = n, g0 = 0;
+  for (int l2 = 0; l2 < L; ++l2) {
+    const int a = (hi - lo + 1) / 2;
+    const int gA = halving_groups_at(a, L - l2 - 1);
+    if (g < g0 + gA) {
+      hi = lo + a;
+    } else {
+      g0 += gA;
+      lo += a;
+    }
+  }
+  const int m = hi - lo, h = halving_groups(m);
+  return HalvingSlot{lo + (g - g0), lo + h, m - h, h, g - g0};
+}
+
 // Weight system of one (row i, family): A (n x r, A[l][m] = D N_{S_i[l]}(x_{Q_i[m]})),
 // z (r, z_m = N_i(x_{Q_i[m]})), b (n). Truncated SVD of Eqs. (20)-(22) with the weighted
 // solution of Eqs. (5)-(6):
@@ -515,7 +596,8 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   const int ld = a.ld, ldm = a.ldm;
   // host sizing violated (QR row slots, X formation rows, Jacobi rows, strides): report,
   // touch nothing
-  if (r > EPR * LPP || r > NT || n > EPJ * LPP || (n + LPP - 1) / LPP * LPP > ldm || ldm > ld || ld < r + 1) {
+  if (r > EPR * LPP || r > NT || n > EPJ * LPP || n > 2 * NG || (n + LPP - 1) / LPP * LPP > ldm || ldm > ld ||
+      ld < r + 1) {
     if (tid == 0) atomicOr(a.fail, 2);
     return;
   }
@@ -645,50 +727,128 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     for (int l = tid; l < n; l += NT) pinv[perm[l]] = l;
   }
   __syncthreads();
-  // ---- one-sided Jacobi on the columns of M, circle-method ordering. Rows [n, ldm) of
-  // every column are zero, and ne LPP <= ldm.
-  const int nn = n + (n & 1);
-  const int npair = nn / 2;
+  // ---- one-sided Jacobi on the columns of M. Rows [n, ldm) of every column are zero, and
+  // ne LPP <= ldm. Two pair orderings (each visits every pair once per sweep):
+  //  - recursive halving: each group holds the S column of its pairs in registers for a
+  //    whole level, so a rotation reads and writes only its T column in LDS (half the LDS
+  //    traffic) and sweeps are fewer; it costs registers and a few more rounds and barriers;
+  //  - the circle method: both columns of a pair through LDS in every round.
+  // Instances take the ordering that measured faster for their buckets: halving for
+  // 48 < n <= 56 (r <= 128), for 48 < n <= 64 with 80 < r <= 128 and for n <= 64 with
+  // r > 128; circle for the rest, where the held column cost occupancy or the extra rounds
+  // cost more than the LDS traffic saved.
+  constexpr bool HALVING = (NT == 256 && (EPJ == 7 || EPR == 32)) || (NT == 512 && LPP == 16);
   const int ne = (n + LPP - 1) / LPP;
   const bool full = ldm >= EPJ * LPP;  // all EPJ rows of a lane inside the column: no checks
   int sweeps = 0;
   bool converged = false;
   double* cn = nrm;  // squared column norms of M (nrm is free after the QR)
-  for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
-    double c2max = 0.0;  // largest cos^2 of a rotated pair in this sweep
-    // fresh norms at each sweep bound the drift of the tracked updates
-    for (int l = g; l < n; l += NG) {
-      double s2 = 0.0;
-      for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
-      s2 = group_sum<LPP>(s2);
-      if (sub == 0) cn[l] = s2;
-    }
-    __syncthreads();
-    // Circle method on positions 0..nn-1: pair p starts at positions (p, nn - 1 - p);
-    // position 0 stays, positions 1..nn-1 advance by one per round (cyclically), so every
-    // two positions meet once per sweep. Position 0 holds column nn - 1 (the padding
-    // column when n is odd), position c > 0 column c - 1; pair 0 (which holds the padding
-    // column in every round for odd n) runs on the last group, so for odd n the last pair
-    // group does no work and a wave whose groups are all past the real pairs skips the
-    // round entirely.
-    const int pp = (g + 1 == npair) ? 0 : g + 1;
-    int P = pp, Q = nn - 1 - pp;
-    for (int rd = 0; rd < nn - 1; ++rd) {
-      const int cP = P == 0 ? nn - 1 : P - 1, cQ = Q - 1;
-      if (g < npair && cP < n && cQ < n) {
-        double* gp = M + (size_t)cP * ldm + sub;
-        double* gq = M + (size_t)cQ * ldm + sub;
-        c2max = fmax(c2max, full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + cP, cn + cQ, sub, ne, negl)
-                                 : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + cP, cn + cQ, sub, ne, negl));
+  if constexpr (HALVING) {
+    int nlev = 0;
+    while (((n + (1 << nlev) - 1) >> nlev) >= 2) ++nlev;
+    for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
+      double c2max = 0.0;  // largest cos^2 of a rotated pair in this sweep
+      // fresh norms at each sweep bound the drift of the tracked updates
+      for (int l = g; l < n; l += NG) {
+        double s2 = 0.0;
+        for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+        s2 = group_sum<LPP>(s2);
+        if (sub == 0) cn[l] = s2;
       }
-      P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
-      Q = (Q == nn - 1) ? 1 : Q + 1;
       __syncthreads();
+      double u[EPJ];
+      double al = 0.0;
+      int held = -1;  // the column in u, or -1
+      for (int L = 0; L < nlev; ++L) {
+        const HalvingSlot sl = halving_slot(n, L, g);
+        const bool act = sl.j < sl.h;
+        const int want = act ? sl.s : -1;
+        if (L > 0) {
+          // a column no longer held goes back to LDS before anyone reads it
+          if (held >= 0 && held != want) {
+            double* gp = M + (size_t)held * ldm + sub;
+#pragma unroll
+            for (int e = 0; e < EPJ; ++e)
+              if (full || e < ne) gp[e * LPP] = u[e];
+            if (sub == 0) cn[held] = al;
+            held = -1;
+          }
+          __syncthreads();
+        }
+        if (act && held != want) {
+          const double* gp = M + (size_t)want * ldm + sub;
+#pragma unroll
+          for (int e = 0; e < EPJ; ++e) u[e] = (full || e < ne) ? gp[e * LPP] : 0.0;
+          al = cn[want];
+          held = want;
+        }
+        const int rounds = halving_groups((n + (1 << L) - 1) >> L);
+        for (int rd = 0; rd < rounds; ++rd) {
+          if (act && rd < sl.h) {
+            int k = sl.j + rd;
+            if (k >= sl.h) k -= sl.h;
+            if (k < sl.tcnt) {
+              const int cQ = sl.tlo + k;
+              double* gq = M + (size_t)cQ * ldm + sub;
+              c2max = fmax(c2max, full ? jacobi_held<LPP, EPJ, false>(u, al, gq, cn + cQ, sub, ne, negl)
+                                       : jacobi_held<LPP, EPJ, true>(u, al, gq, cn + cQ, sub, ne, negl));
+            }
+          }
+          __syncthreads();
+        }
+      }
+      if (held >= 0) {
+        double* gp = M + (size_t)held * ldm + sub;
+#pragma unroll
+        for (int e = 0; e < EPJ; ++e)
+          if (full || e < ne) gp[e * LPP] = u[e];
+        if (sub == 0) cn[held] = al;
+      }
+      __syncthreads();
+      // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
+      // below 1e-9, the columns are orthogonal to |cos| ~ 1e-18, under the 1e-15 at which a
+      // pair is rotated at all, so the sweep that would only confirm it is skipped.
+      converged = !__syncthreads_or(c2max > 1e-18);
     }
-    // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
-    // below 1e-9, the columns are orthogonal to |cos| ~ 1e-18, under the 1e-15 at which a
-    // pair is rotated at all, so the sweep that would only confirm it is skipped.
-    converged = !__syncthreads_or(c2max > 1e-18);
+  } else {
+    const int nn = n + (n & 1);
+    const int npair = nn / 2;
+    for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
+      double c2max = 0.0;  // largest cos^2 of a rotated pair in this sweep
+      // fresh norms at each sweep bound the drift of the tracked updates
+      for (int l = g; l < n; l += NG) {
+        double s2 = 0.0;
+        for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+        s2 = group_sum<LPP>(s2);
+        if (sub == 0) cn[l] = s2;
+      }
+      __syncthreads();
+      // Circle method on positions 0..nn-1: pair p starts at positions (p, nn - 1 - p);
+      // position 0 stays, positions 1..nn-1 advance by one per round (cyclically), so every
+      // two positions meet once per sweep. Position 0 holds column nn - 1 (the padding
+      // column when n is odd), position c > 0 column c - 1; pair 0 (which holds the padding
+      // column in every round for odd n) runs on the last group, so for odd n the last pair
+      // group does no work and a wave whose groups are all past the real pairs skips the
+      // round entirely.
+      const int pp = (g + 1 == npair) ? 0 : g + 1;
+      int P = pp, Q = nn - 1 - pp;
+      for (int rd = 0; rd < nn - 1; ++rd) {
+        const int cP = P == 0 ? nn - 1 : P - 1, cQ = Q - 1;
+        if (g < npair && cP < n && cQ < n) {
+          double* gp = M + (size_t)cP * ldm + sub;
+          double* gq = M + (size_t)cQ * ldm + sub;
+          c2max = fmax(c2max, full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + cP, cn + cQ, sub, ne, negl)
+                                   : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + cP, cn + cQ, sub, ne, negl));
+        }
+        P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
+        Q = (Q == nn - 1) ? 1 : Q + 1;
+        __syncthreads();
+      }
+      // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
+      // below 1e-9, the columns are orthogonal to |cos| ~ 1e-18, under the 1e-15 at which a
+      // pair is rotated at all, so the sweep that would only confirm it is skipped.
+      converged = !__syncthreads_or(c2max > 1e-18);
+    }
   }
   if (!converged && tid == 0) atomicOr(a.fail, 1);
   if (tid == 0) atomicMax(a.max_sweeps, sweeps);
