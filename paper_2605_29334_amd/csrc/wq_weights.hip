@@ -943,7 +943,9 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   // visible from the next barrier on. yv[k] = c_k is only read.
   double* ys = beta;
   double* iq = nrm;  // free after the Jacobi sweeps
-  constexpr int DL = 4;  // lanes per dot product
+  // lanes per dot product: 8 in the 1024-thread instance (its k <= 128 dot products then
+  // still take one pass over the threads and each lane half the terms), else 4
+  constexpr int DL = NT >= 1024 ? 8 : 4;
   double inv_prev = 0.0;  // 1 / R_{k-1,k-1}, in every thread
   auto finish = [&](int k) {  // column k's R_kk and y_k from the reduced partial sums
     double nn2 = 0.0, acc = 0.0;
@@ -981,21 +983,52 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
         }
       }
       __syncthreads();
-      // x -= sum_j sig_j x_j (thread per row); the second pass also forms the partial
-      // sums of |x|^2 and of sum_j R_jk y_j
-      for (int m = tid; m < r; m += NT) {
-        double v0 = x[m], v1 = 0.0, v2 = 0.0, v3 = 0.0;  // four chains in flight
-        int j = 0;
-        for (; j + 4 <= k; j += 4) {
-          v0 -= G[(size_t)j * ld + m] * sig[j];
-          v1 -= G[(size_t)(j + 1) * ld + m] * sig[j + 1];
-          v2 -= G[(size_t)(j + 2) * ld + m] * sig[j + 2];
-          v3 -= G[(size_t)(j + 3) * ld + m] * sig[j + 3];
+      // x -= sum_j sig_j x_j as four chains, chain c taking j = c (mod 4) below 4 floor(k/4)
+      // and chain 0 also the rest, combined as (c0 + c1) + (c2 + c3). RS = 4, 2 or 1 lanes
+      // per row (as many as the threads allow for this r) share the chains of a row (RS = 4:
+      // one each; RS = 2: lane p takes chains p and p + 2), so x itself does not depend on
+      // RS. The second pass also forms the partial sums of |x|^2 (per wave, so their
+      // grouping follows RS, which depends on r and the instance only) and of
+      // sum_j R_jk y_j.
+      {
+        const int lg = 4 * r <= NT ? 2 : 2 * r <= NT ? 1 : 0;
+        const int m = tid >> lg, p = tid & ((1 << lg) - 1);
+        const int k4 = k & ~3;
+        if (m < r) {  // whole groups of 1 << lg lanes (r (1 << lg) <= NT)
+          double v;
+          if (lg == 2) {
+            v = p == 0 ? x[m] : 0.0;
+            for (int j = p; j < k4; j += 4) v -= G[(size_t)j * ld + m] * sig[j];
+            if (p == 0)
+              for (int j = k4; j < k; ++j) v -= G[(size_t)j * ld + m] * sig[j];
+            v = group_sum<4>(v);  // (c0 + c1) + (c2 + c3)
+          } else if (lg == 1) {
+            double va = p == 0 ? x[m] : 0.0, vb = 0.0;  // chains p and p + 2
+            for (int j = 0; j < k4; j += 4) {
+              va -= G[(size_t)(j + p) * ld + m] * sig[j + p];
+              vb -= G[(size_t)(j + p + 2) * ld + m] * sig[j + p + 2];
+            }
+            if (p == 0)
+              for (int j = k4; j < k; ++j) va -= G[(size_t)j * ld + m] * sig[j];
+            va += dpp_f64<0xB1>(va);  // c0 + c1 in both lanes
+            vb += dpp_f64<0xB1>(vb);  // c2 + c3
+            v = va + vb;
+          } else {
+            double v0 = x[m], v1 = 0.0, v2 = 0.0, v3 = 0.0;  // four chains in flight
+            for (int j = 0; j < k4; j += 4) {
+              v0 -= G[(size_t)j * ld + m] * sig[j];
+              v1 -= G[(size_t)(j + 1) * ld + m] * sig[j + 1];
+              v2 -= G[(size_t)(j + 2) * ld + m] * sig[j + 2];
+              v3 -= G[(size_t)(j + 3) * ld + m] * sig[j + 3];
+            }
+            for (int j = k4; j < k; ++j) v0 -= G[(size_t)j * ld + m] * sig[j];
+            v = (v0 + v1) + (v2 + v3);
+          }
+          if (p == 0) {
+            x[m] = v;
+            if (pass == 1) part_n += v * v;
+          }
         }
-        for (; j < k; ++j) v0 -= G[(size_t)j * ld + m] * sig[j];
-        const double v = (v0 + v1) + (v2 + v3);
-        x[m] = v;
-        if (pass == 1) part_n += v * v;
       }
       if (pass == 1)
         for (int j = tid; j < k; j += NT) part_a += Rk[j] * ys[j];
