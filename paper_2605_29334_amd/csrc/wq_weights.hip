@@ -1220,7 +1220,9 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       //    where the 1024-thread instance's registers allow one);
       //  - 48 < n <= 64, 80 < r <= 128: 512 threads, 16 lanes per pair and per column (these
       //    buckets hold two or three workgroups per CU by LDS: twice the resident waves);
-      //  - other n > 64: 1024 threads, 16 lanes; other n <= 64: 256 threads, 8 lanes.
+      //  - other n > 64: 1024 threads, 16 lanes (6 rows of M per lane up to n = 96, so that
+      //    no lane runs zero rows through the rotations, 8 above); other n <= 64: 256
+      //    threads, 8 lanes.
       const int bn = b / NB_R, br = b % NB_R;
       const bool w512 = bn == 3 && br <= 3;
       const bool m512 = bn == 2 && br >= 2 && br <= 3;
@@ -1284,6 +1286,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
         else if (!wide && epr <= 16) fn = (const void*)k_tsvd2<8, 16, 8, 256>, kname = "k_tsvd2<8,16,8,256>";
         else if (!wide) fn = (const void*)k_tsvd2<8, 32, 8, 256>, kname = "k_tsvd2<8,32,8,256>";
         else if (w512) fn = (const void*)k_tsvd2<8, 16, 12, 512>, kname = "k_tsvd2<8,16,12,512>";
+        else if (bn == 3) fn = (const void*)k_tsvd2<16, 16, 6, 1024>, kname = "k_tsvd2<16,16,6,1024>";
         else fn = (const void*)k_tsvd2<16, 16, 8, 1024>, kname = "k_tsvd2<16,16,8,1024>";
       }
       hipFuncAttributes fa{};
