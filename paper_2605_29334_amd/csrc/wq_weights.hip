@@ -385,6 +385,24 @@ __device__ inline void wave_argmax(double v, int i, double* cv, double* ci) {
   }
 }
 
+// Largest (value, index) over aligned groups of G = 8 or 16 lanes, ties to the smaller
+// index; every lane of a group gets the result. The choice is a maximum in a total order,
+// so it is the same as that of a scan in any order.
+template <int G>
+__device__ inline void group_argmax(double& v, int& i) {
+  static_assert(G == 8 || G == 16, "group of 8 or 16 lanes");
+  auto step = [&](double ov, int oi) {
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  };
+  step(dpp_f64<0xB1>(v), __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false));
+  step(dpp_f64<0x4E>(v), __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false));
+  step(dpp_f64<0x141>(v), __builtin_amdgcn_mov_dpp(i, 0x141, 0xF, 0xF, false));
+  if (G >= 16) step(dpp_f64<0x140>(v), __builtin_amdgcn_mov_dpp(i, 0x140, 0xF, 0xF, false));
+}
+
 // Apply reflector j (stored unscaled in physical column pc: v_j = 1, v_m = x_m rv0 below)
 // to the logical columns l > j (physical phys(l): cur[l], except cj for l = bi, the pivot's
 // old position), LPP lanes per column, and recompute their trailing squared norms (rows
@@ -681,14 +699,22 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     const double* cv = red + 32 + 32 * (j & 1);
     const int* cur = (j & 1) ? cmap : piv;
     int* nxt = (j & 1) ? piv : cmap;
-    double s2 = cv[0];
-    int bi = (int)cv[16];
-    for (int w = 1; w < NW; ++w) {
-      const double v = cv[w];
-      const int i2 = (int)cv[16 + w];
-      if (v > s2 || (v == s2 && i2 < bi)) {
-        s2 = v;
-        bi = i2;
+    double s2;
+    int bi;
+    if constexpr (NW >= 8) {  // one candidate per lane of each group of NW lanes
+      s2 = cv[tid & (NW - 1)];
+      bi = (int)cv[16 + (tid & (NW - 1))];
+      group_argmax<NW>(s2, bi);
+    } else {
+      s2 = cv[0];
+      bi = (int)cv[16];
+      for (int w = 1; w < NW; ++w) {
+        const double v = cv[w];
+        const int i2 = (int)cv[16 + w];
+        if (v > s2 || (v == s2 && i2 < bi)) {
+          s2 = v;
+          bi = i2;
+        }
       }
     }
     const int cj = cur[j], pc = cur[bi];
@@ -943,9 +969,10 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   // visible from the next barrier on. yv[k] = c_k is only read.
   double* ys = beta;
   double* iq = nrm;  // free after the Jacobi sweeps
-  // lanes per dot product: 8 in the 1024-thread instance (its k <= 128 dot products then
-  // still take one pass over the threads and each lane half the terms), else 4
-  constexpr int DL = NT >= 1024 ? 8 : 4;
+  // lanes per dot product: 8 where the k dot products still take one pass over the
+  // threads (the 1024-thread instance, k <= 128; the 512-thread one with 16 lanes per
+  // pair, k <= 64), each lane then taking half the terms; else 4
+  constexpr int DL = (NT >= 1024 || (NT == 512 && LPP == 16)) ? 8 : 4;
   double inv_prev = 0.0;  // 1 / R_{k-1,k-1}, in every thread
   auto finish = [&](int k) {  // column k's R_kk and y_k from the reduced partial sums
     double nn2 = 0.0, acc = 0.0;
