@@ -452,9 +452,10 @@ __device__ inline double qr_update(double* G, int ld, int r, int ncol, int j, in
 // The squared column norms are tracked in *np, *nq (the exact update of a rotation that
 // zeroes the off-diagonal: |p'|^2 = |p|^2 - t g, |q'|^2 = |q|^2 + t g), so only the inner
 // product is reduced per rotation; where the update cancels (a norm drops below 1e-3 of
-// its old value) both are recomputed from the rotated columns.
+// its old value) both are recomputed from the rotated columns. Returns whether the columns
+// met at |cos| above 1e-9 (cos^2 = g^2 / (|p|^2 |q|^2) > 1e-18, tested without a division).
 template <int LPP, int EPJ, bool GUARD>
-__device__ inline double jacobi_pair(double* gp, double* gq, double* np, double* nq, int sub, int ne, double negl) {
+__device__ inline bool jacobi_pair(double* gp, double* gq, double* np, double* nq, int sub, int ne, double negl) {
   double u[EPJ], v[EPJ];
 #pragma unroll
   for (int e = 0; e < EPJ; ++e) {
@@ -466,7 +467,7 @@ __device__ inline double jacobi_pair(double* gp, double* gq, double* np, double*
 #pragma unroll
   for (int e = 0; e < EPJ; ++e) ga += u[e] * v[e];
   ga = group_sum<LPP>(ga);
-  if (!(ga * ga > 1e-30 * al * be && fmin(al, be) > negl)) return 0.0;
+  if (!(ga * ga > 1e-30 * al * be && fmin(al, be) > negl)) return false;
   // t = tan of the rotation angle (the smaller root), c = 1 / sqrt(1 + t^2), s = c t. t
   // only has to be close to the exact angle; c is accurate to rounding for the t used, so
   // the rotation is orthogonal to working precision.
@@ -502,15 +503,15 @@ __device__ inline double jacobi_pair(double* gp, double* gq, double* np, double*
     *np = an;
     *nq = bn;
   }
-  return ga * ga / (al * be);  // cos^2 of the angle between the columns before the rotation
+  return ga * ga > 1e-18 * (al * be);
 }
 
 // One rotation of the pair (s, t) where the lanes of the group hold column s in registers
 // (u, squared norm al, the same in every lane of the group) and column t sits in LDS at gq
-// (squared norm *nq). Only column t is read and written back. Returns cos^2 of the angle
-// between the columns before the rotation, 0 when the pair needs none.
+// (squared norm *nq). Only column t is read and written back. Returns whether the columns
+// met at |cos| above 1e-9, as jacobi_pair does.
 template <int LPP, int EPJ, bool GUARD>
-__device__ inline double jacobi_held(double (&u)[EPJ], double& al, double* gq, double* nq, int sub, int ne,
+__device__ inline bool jacobi_held(double (&u)[EPJ], double& al, double* gq, double* nq, int sub, int ne,
                                      double negl) {
   double v[EPJ];
 #pragma unroll
@@ -520,7 +521,7 @@ __device__ inline double jacobi_held(double (&u)[EPJ], double& al, double* gq, d
 #pragma unroll
   for (int e = 0; e < EPJ; ++e) ga += u[e] * v[e];
   ga = group_sum<LPP>(ga);
-  if (!(ga * ga > 1e-30 * al * be && fmin(al, be) > negl)) return 0.0;
+  if (!(ga * ga > 1e-30 * al * be && fmin(al, be) > negl)) return false;
   // t = tan of the rotation angle (the smaller root), c = 1 / sqrt(1 + t^2), s = c t
   const double dba = be - al;
   const double h = dba * dba + 4.0 * ga * ga;
@@ -547,10 +548,10 @@ __device__ inline double jacobi_held(double (&u)[EPJ], double& al, double* gq, d
     an = group_sum<LPP>(an);
     bn = group_sum<LPP>(bn);
   }
-  const double c2 = ga * ga / (al * be);
+  const bool big = ga * ga > 1e-18 * (al * be);
   al = an;
   if (sub == 0) *nq = bn;
-  return c2;
+  return big;
 }
 
 // Recursive-halving pair ordering for the Jacobi sweeps. A block of m columns [lo, hi)
@@ -773,7 +774,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     int nlev = 0;
     while (((n + (1 << nlev) - 1) >> nlev) >= 2) ++nlev;
     for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
-      double c2max = 0.0;  // largest cos^2 of a rotated pair in this sweep
+      bool big = false;  // a pair of this sweep met at |cos| above 1e-9
       // fresh norms at each sweep bound the drift of the tracked updates
       for (int l = g; l < n; l += NG) {
         double s2 = 0.0;
@@ -816,8 +817,8 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
             if (k < sl.tcnt) {
               const int cQ = sl.tlo + k;
               double* gq = M + (size_t)cQ * ldm + sub;
-              c2max = fmax(c2max, full ? jacobi_held<LPP, EPJ, false>(u, al, gq, cn + cQ, sub, ne, negl)
-                                       : jacobi_held<LPP, EPJ, true>(u, al, gq, cn + cQ, sub, ne, negl));
+              big |= full ? jacobi_held<LPP, EPJ, false>(u, al, gq, cn + cQ, sub, ne, negl)
+                          : jacobi_held<LPP, EPJ, true>(u, al, gq, cn + cQ, sub, ne, negl);
             }
           }
           __syncthreads();
@@ -834,13 +835,13 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
       // below 1e-9, the columns are orthogonal to |cos| ~ 1e-18, under the 1e-15 at which a
       // pair is rotated at all, so the sweep that would only confirm it is skipped.
-      converged = !__syncthreads_or(c2max > 1e-18);
+      converged = !__syncthreads_or(big);
     }
   } else {
     const int nn = n + (n & 1);
     const int npair = nn / 2;
     for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
-      double c2max = 0.0;  // largest cos^2 of a rotated pair in this sweep
+      bool big = false;  // a pair of this sweep met at |cos| above 1e-9
       // fresh norms at each sweep bound the drift of the tracked updates
       for (int l = g; l < n; l += NG) {
         double s2 = 0.0;
@@ -863,8 +864,8 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
         if (g < npair && cP < n && cQ < n) {
           double* gp = M + (size_t)cP * ldm + sub;
           double* gq = M + (size_t)cQ * ldm + sub;
-          c2max = fmax(c2max, full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + cP, cn + cQ, sub, ne, negl)
-                                   : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + cP, cn + cQ, sub, ne, negl));
+          big |= full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + cP, cn + cQ, sub, ne, negl)
+                      : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + cP, cn + cQ, sub, ne, negl);
         }
         P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
         Q = (Q == nn - 1) ? 1 : Q + 1;
@@ -873,7 +874,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
       // below 1e-9, the columns are orthogonal to |cos| ~ 1e-18, under the 1e-15 at which a
       // pair is rotated at all, so the sweep that would only confirm it is skipped.
-      converged = !__syncthreads_or(c2max > 1e-18);
+      converged = !__syncthreads_or(big);
     }
   }
   if (!converged && tid == 0) atomicOr(a.fail, 1);
