@@ -182,6 +182,34 @@ def overlap_sets(fx, cl, supp):
     return out
 
 
+def minmax_row_requirement(n_i, elems):
+    """Eq. (18) for one test function N_i. elems lists (element type, m_k) for every
+    element k of supp(N_i). Regular and boundary elements (the set R) keep the standard
+    WQ counts, 4 and 16 points; every other element k gets the share
+    r_{i,k} = m_k / (sum over l in supp(N_i) minus R of m_l) * (n_i - 4 e^r_i - 16 e^b_i),
+    rounded up (READING X9). Returns r_{i,k} per element, None for elements in R."""
+    e_r = sum(1 for t, _ in elems if t == ET_REGULAR)
+    e_b = sum(1 for t, _ in elems if t == ET_BOUNDARY)
+    msum = sum(mk for t, mk in elems if t not in (ET_REGULAR, ET_BOUNDARY))
+    out = []
+    for t, mk in elems:
+        if t in (ET_REGULAR, ET_BOUNDARY):
+            out.append(None)
+        else:
+            out.append(math.ceil(mk / msum * (n_i - 4 * e_r - 16 * e_b) - 1e-12))
+    return out
+
+
+def minmax_points_per_direction(r_k, split):
+    """s_k = smallest s >= 2 with s^2 >= r_k, where r_k = max_i r_{i,k} (Eq. (18) and
+    the sentence after it); even on a split element so that no point falls on a
+    sub-element edge (READING)."""
+    sk = 2
+    while sk * sk < r_k or (split and sk % 2):
+        sk += 1
+    return sk
+
+
 def points_per_element(fx, cls, s_init=None):
     """Table 2 counts, then the well-posedness check r_i >= n_i and, where it fails,
     the "min-max" allocation of Eq. (18) for the non-regular, non-boundary elements.
@@ -206,20 +234,13 @@ def points_per_element(fx, cls, s_init=None):
         need = {}
         for i in range(fx["n_fn"]):
             els = sorted({int(cl["elem"][c]) for c in supp[i]})
-            er = sum(1 for f in els if etype[f] == ET_REGULAR)
-            eb = sum(1 for f in els if etype[f] == ET_BOUNDARY)
-            others = [f for f in els if etype[f] not in (ET_REGULAR, ET_BOUNDARY)]
-            if not others:
-                continue
-            msum = sum(m[f] for f in others)
-            for k in others:
-                r_ik = m[k] / msum * (len(S[i]) - 4 * er - 16 * eb)
-                need[k] = max(need.get(k, 0), math.ceil(r_ik - 1e-12))
+            req = minmax_row_requirement(len(S[i]), [(int(etype[f]), int(m[f])) for f in els])
+            for f, r_ik in zip(els, req):
+                if r_ik is not None:
+                    need[f] = max(need.get(f, 0), r_ik)
         changed = False
         for k, rk in need.items():
-            sk = 2
-            while sk * sk < rk or (cls["split"][k] and sk % 2):
-                sk += 1
+            sk = minmax_points_per_direction(rk, bool(cls["split"][k]))
             if sk > s[k]:
                 s[k] = sk
                 changed = True
