@@ -210,6 +210,17 @@ wq_status assemble_tangent(const wq_points* pts, const wq_weights* w, const doub
                            double inv_theta_dt, wq_conductivity k, const double* f_at_pts, void* S_vals,
                            double* R, wq_precision prec, wq_stream stream);
 
+/* assemble_tangent_exact: as assemble_tangent, with the exact Newton tangent of Eq. (34):
+ * S also carries the non-symmetric term that Eq. (35) drops, read as the derivative of R
+ * (the printed term is garbled):
+ *   S_ij += sum_{q in Q_i} k'(T_q) N_j(x_q) (w^x_iq dT/dx(x_q) + w^y_iq dT/dy(x_q)).
+ * Newton then converges quadratically. Same arguments, residual and asynchrony as
+ * assemble_tangent; its scratch in `pts` holds 6 doubles per point (allocated on the
+ * first call). */
+wq_status assemble_tangent_exact(const wq_points* pts, const wq_weights* w, const double* T, const double* Tdot,
+                                 double inv_theta_dt, wq_conductivity k, const double* f_at_pts, void* S_vals,
+                                 double* R, wq_precision prec, wq_stream stream);
+
 /* wq_heat_step: one time step t_n -> t_{n+1} (Section 5.2). Predictor
  * T = T_n + (1 - theta) dt Tdot_n with T = g on prescribed DOFs; corrector iterations:
  * Tdot = (T - T_n - (1 - theta) dt Tdot_n) / (theta dt), S and R by assemble_tangent,
@@ -221,9 +232,12 @@ wq_status assemble_tangent(const wq_points* pts, const wq_weights* w, const doub
  *   NULL (prescribed values 0); f_at_pts: device double[n_points] (f at t_{n+1}) or NULL;
  *   T, Tdot: device double[n_rows], in: T_n, Tdot_n; out: T_{n+1}, Tdot_{n+1};
  *   S_vals: device double[nnz], receives the last tangent.
+ * hp->tangent: WQ_TANGENT_SYMMETRIC (Eq. (35), as the paper) or WQ_TANGENT_EXACT (Eq. (34),
+ * assemble_tangent_exact: quadratic convergence).
  * Synchronises `stream` (convergence tests read norms on the host). Returns
  * WQ_ENOCONV if Newton or BiCGStab hit their caps (T, Tdot then hold the last iterate).
  * Uses scratch owned by `pts`: calls on the same handle must not overlap. */
+typedef enum { WQ_TANGENT_SYMMETRIC = 0, WQ_TANGENT_EXACT = 1 } wq_tangent;
 typedef struct {
   double dt, theta;     /* time step, trapezoidal parameter in (0, 1]                 */
   wq_conductivity k;
@@ -231,6 +245,7 @@ typedef struct {
   int32_t max_newton;   /* Newton iteration cap                                       */
   double cg_rtol;       /* Krylov stop: ||r||_2 <= max(cg_rtol ||R_free||_2, tol/10) */
   int32_t max_cg;       /* Krylov iteration cap per solve                             */
+  int32_t tangent;      /* wq_tangent                                                 */
 } wq_heat_params;
 typedef struct {
   int32_t newton_iters; /* corrector solves taken                                     */

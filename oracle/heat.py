@@ -62,15 +62,19 @@ def point_field(data, vec):
     return np.concatenate(u), np.concatenate(ux), np.concatenate(uy)
 
 
-def tangent_residual(fx, pat, data, W, T, Tdot, inv_theta_dt, kfun, f_pts=None):
+def tangent_residual(fx, pat, data, W, T, Tdot, inv_theta_dt, kfun, f_pts=None, dkfun=None):
     """Eq. (36) row by row: S_il = sum_q [inv_theta_dt w0_iq N_l(x_q)
     + k(T_q) (wx_iq dN_l/dx(x_q) + wy_iq dN_l/dy(x_q))] on the CSR pattern, and the
-    residual R (module READINGS). Returns (S values aligned with pat['col'], R)."""
+    residual R (module READINGS). With dkfun = k' given, S also carries the non-symmetric
+    term of the exact tangent (Eq. 34, module READING):
+    + sum_q k'(T_q) N_l(x_q) (wx_iq dT/dx(x_q) + wy_iq dT/dy(x_q)).
+    Returns (S values aligned with pat['col'], R)."""
     n = fx["n_fn"]
     Tq, Tx, Ty = point_field(data, T)
     Dq, _, _ = point_field(data, Tdot)
     kq = kfun(Tq)
     fq = np.zeros_like(Tq) if f_pts is None else f_pts
+    dq = None if dkfun is None else dkfun(Tq)
     from .wq import local_matrix
     S = np.zeros(len(pat["col"]))
     R = np.zeros(n)
@@ -83,6 +87,8 @@ def tangent_residual(fx, pat, data, W, T, Tdot, inv_theta_dt, kfun, f_pts=None):
         Ay = local_matrix(fx, pat, data, i, "Ny")
         S[pat["row_ptr"][i]:pat["row_ptr"][i + 1]] = (A0 @ (inv_theta_dt * w0)
                                                       + Ax @ (kq[Q] * wx) + Ay @ (kq[Q] * wy))
+        if dq is not None:
+            S[pat["row_ptr"][i]:pat["row_ptr"][i + 1]] += A0 @ (dq[Q] * (wx * Tx[Q] + wy * Ty[Q]))
         R[i] = np.sum(w0 * (Dq[Q] - fq[Q]) + kq[Q] * (wx * Tx[Q] + wy * Ty[Q]))
     return S, R
 
@@ -97,12 +103,13 @@ def load_vector(pat, W, f_pts, n):
 
 
 def heat_step(fx, pat, data, W, T_n, Tdot_n, dt, theta, kfun, f_pts, dirichlet, g_next, tol=1e-10,
-              max_iter=50):
+              max_iter=50, dkfun=None):
     """One time step t_n -> t_{n+1} (Section 5.2): predictor T = T_n + (1-theta) dt Tdot_n
     with the Dirichlet values g_next imposed; corrector iterations
     Tdot = (T - T_n - (1-theta) dt Tdot_n) / (theta dt), S and R at (T, Tdot) by Eq. (36),
-    solve -S_ff dT_f = R_f (Eq. 33 with the tangent of Eq. 35), T_f += dT_f, until
-    ||R_f||_2 <= tol. Returns (T, Tdot, iterations, [||R_f|| per iteration])."""
+    solve -S_ff dT_f = R_f (Eq. 33 with the tangent of Eq. 35, or with the exact tangent
+    of Eq. 34 when dkfun = k' is given), T_f += dT_f, until ||R_f||_2 <= tol.
+    Returns (T, Tdot, iterations, [||R_f|| per iteration])."""
     n = fx["n_fn"]
     free = ~dirichlet.astype(bool)
     T = T_n + (1.0 - theta) * dt * Tdot_n
@@ -111,7 +118,7 @@ def heat_step(fx, pat, data, W, T_n, Tdot_n, dt, theta, kfun, f_pts, dirichlet, 
     it = 0
     while True:
         Tdot = (T - T_n - (1.0 - theta) * dt * Tdot_n) / (theta * dt)
-        Sv, R = tangent_residual(fx, pat, data, W, T, Tdot, 1.0 / (theta * dt), kfun, f_pts)
+        Sv, R = tangent_residual(fx, pat, data, W, T, Tdot, 1.0 / (theta * dt), kfun, f_pts, dkfun)
         nr = float(np.linalg.norm(R[free]))
         norms.append(nr)
         if nr <= tol or it >= max_iter:

@@ -14,7 +14,8 @@ constexpr int WAVE = 64;
 constexpr int NXCD = 8;    // MI355X: workgroups are dispatched round-robin over 8 XCDs
 
 // Families per kernel: K = 0 mass, 1 stiffness, 2 biharmonic, 3 mass + stiffness,
-// 4 tangent (Eq. (36)) + residual.
+// 4 tangent (Eq. (36)) + residual, 5 exact tangent (Eq. (34): Eq. (36) plus the
+// non-symmetric term k'(T) N_j grad T . grad N_i) + residual.
 // N basis arrays (N or Delta N; dN/dx, dN/dy) and as many weight families; weight family
 // a is scaled by the coefficient array cof(a) (or, for the tangent's mass term, by the
 // constant 1/(theta dt)).
@@ -22,10 +23,12 @@ template <int K> struct Fam {
   static constexpr int N = (K >= 3) ? 3 : (K == 1 ? 2 : 1);
   static constexpr int NACC = (K == 3) ? 2 : 1;
   static constexpr int NC = (K == 3) ? 2 : 1;
-  static constexpr bool RES = (K == 4);
+  static constexpr bool RES = (K >= 4);
+  static constexpr bool EXACT = (K == 5);
+  static constexpr int NPF = RES ? (EXACT ? 5 : 3) : 1;  // point fields read by the kernel
   __device__ static constexpr int cof(int a) { return (K == 3 && a > 0) ? 1 : 0; }
   // tangent: mass term scaled by a constant, conductivity terms by C[0]
-  __device__ static constexpr bool constant(int a) { return K == 4 && a == 0; }
+  __device__ static constexpr bool constant(int a) { return K >= 4 && a == 0; }
 };
 
 struct Src {
@@ -33,13 +36,9 @@ struct Src {
   const double* W[3];   // weights aligned with Q_i
   const double* C[2];   // coefficients at the points (nullptr: 1)
   double scale;         // tangent: 1 / (theta dt) on the mass term
-  const double* Pf[3];  // tangent residual point fields: Tdot - f, k dT/dx, k dT/dy
+  const double* Pf[5];  // tangent point fields: Tdot - f, k dT/dx, k dT/dy (residual);
+                        // k' dT/dx, k' dT/dy (non-symmetric term of the exact tangent)
 };
-
-constexpr int PFD = 4;  // register slots (x 64 lanes) prefetched for a cell's basis block
-constexpr int PFW = 1;  // ... for the member rows' weights on the cell
-constexpr int PFS = 4;  // ... for the members' column slots
-constexpr int DEPTH = 2;  // cell entries in flight per wavefront
 
 // Entry e of a tile: cell block at d0, points pt0.., np points, m functions; member rows
 // are the set bits of the row mask (bits 0..15), their records at smem[mb ..] in row order.
@@ -67,246 +66,332 @@ __device__ inline Ent decode(const int4 E, int64_t m0) {
 // product errs by < 4096 * 2^-23 < 5e-4, so truncation is exact.
 __device__ inline int qdiv(int t, float r) { return (int)(((float)t + 0.5f) * r); }
 
-template <int K> struct Pre {
-  double d[Fam<K>::N][PFD];
-  double w[Fam<K>::N][PFW];
-  double c[Fam<K>::NC][PFW];
-  double pf[Fam<K>::RES ? 3 : 1][PFW];
-  int s[PFS];
-  int rl[PFS];
+// ------------------------------------------------------------------ cell-major MFMA kernel
+// One wavefront owns a tile of up to 16 consecutive rows; its CSR values are accumulated in
+// LDS. It visits the cells of the tile rows' supports once each, in ascending order. For a
+// cell with np points and m functions, the contribution to member row i and cell function
+// k is P[k][i] = sum_q D_k(x_q) (w_iq coef_q): the cell's basis block (transposed, m x np)
+// times the member rows' weights (np x 16), on the FP64 MFMA 16 x 16 x 4, one step per 4
+// points and 16 functions. The A operand of a step is one row of the point-major basis
+// block (a coalesced load), the B operand the rows' weights (each row's weights on a cell
+// are consecutive). Lane (row r = lane % 16, g = lane / 16) then holds P for its own row and
+// functions g, g + 4, g + 8, g + 12 of the block (register v holds output row 4 v + g of the
+// MFMA) and adds them to the row's CSR slots in LDS (the (row, cell) pair's slot map, stored
+// so that those four slots are one dword). Every row receives its cells' contributions in ascending
+// cell order, and a row's contribution depends on that row's weights only: the values do
+// not depend on which rows share a tile (a mesh gives the same bits alone and in a batch).
+// No global atomics; LDS adds are to distinct slots within an instruction.
+// The steps of a tile run as a pipeline: the loads of the next STEPS - 1 steps are in
+// flight while one is multiplied and scattered. Every load is a buffer load; lanes with
+// nothing to load use an offset past the buffer's end, which returns 0 without a memory
+// access, so each step issues the same loads and the waits stay static.
+// Tangent (K = 4): each lane also sums its row's residual terms over its points; the four
+// lanes of a row are added in a fixed order at the end.
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr uint32_t OOB = 0x80000000u;  // byte offset past the end of every buffer (all < 2 GiB)
+constexpr int STEPS = 3;                // pipeline depth (steps in flight per wavefront)
+
+__device__ inline Rsrc make_rsrc(const void* p, int64_t bytes) {
+  // raw buffer (stride 0); the range check returns 0 for offsets at or past `bytes`
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, p ? (int)bytes : 0, 0x00020000);
+}
+__device__ inline double bload64(Rsrc r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ inline uint32_t bload32(Rsrc r, uint32_t off) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+
+template <int K> struct Bufs {
+  Rsrc D[Fam<K>::N], W[Fam<K>::N], C[Fam<K>::NC], Pf[Fam<K>::NPF], slot;
+  bool cnull[Fam<K>::NC];
 };
 
-// Issue the global loads of one entry into registers (consumed by stage()).
+// Per-lane constants: MFMA B column / output row r, point group g.
+struct Lane {
+  int r, g;
+  uint32_t lane8, g8;  // lane * 8, g * 8 (byte offsets inside a basis row block / point group)
+  uint32_t lowmask;    // rows of the tile below r
+  int ro;              // CSR offset of the lane's row inside the tile
+};
+
+// A step: entry e (record E), point block ks, function block cb. Uniform. Entries of
+// regular cells (4 points, 16 functions: one step) take a short path ("fast").
+struct Step {
+  int e, ks, cb;
+  int4 E;
+  bool valid, fast;
+};
+__device__ inline int st_np(const Step& s) { return (s.E.z >> 16) & 0xff; }
+__device__ inline int st_m(const Step& s) { return (int)((unsigned)s.E.z >> 24); }
+__device__ inline bool fast_record(const int4& E) { return ((E.z >> 16) & 0xff) == 4 && ((unsigned)E.z >> 24) == 16u; }
+
+__device__ inline int4 uniform_record(const int4* sent, int e) {
+  const int4 v = sent[e];
+  return make_int4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
+                   __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+}
+
+// The step after s; entering a new entry moves the lane's weight offset past the points of
+// the old cell if its row is a member there.
+__device__ inline Step advance(const Step& s, uint32_t& qoff, int r, int ne, const int4* sent) {
+  Step n = s;
+  if (!s.valid) return n;
+  const int np = st_np(s), m = st_m(s);
+  if (++n.ks * 4 < np) return n;
+  n.ks = 0;
+  if (++n.cb * 16 < m) return n;
+  n.cb = 0;
+  if ((((unsigned)s.E.z >> r) & 1u)) qoff += np;
+  if (++n.e < ne) {
+    n.E = uniform_record(sent, n.e);
+    n.fast = fast_record(n.E);
+  } else {
+    n.valid = false;
+    n.fast = false;
+    n.E = make_int4(0, 0, 0, 0);
+  }
+  return n;
+}
+
+template <int K> struct Ops {
+  double d[Fam<K>::N], w[Fam<K>::N], c[Fam<K>::NC], pf[Fam<K>::NPF];
+  uint32_t sl;
+};
+
+__device__ inline double bload64s(Rsrc r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ inline uint32_t bload32s(Rsrc r, uint32_t voff, uint32_t soff) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+
+// Issue the loads of one step. Every step issues the same loads in the same order (the
+// waits on them stay static); regular cells (4 points x 16 functions: the basis row block
+// is one contiguous run, lane = function + 16 point) take their basis offset from the
+// record and a lane constant instead of the general index arithmetic.
 template <int K>
-__device__ inline void prefetch(const Ent& e, int lane, const Src& S, const int2* smem,
-                                const uint8_t* __restrict__ slot, Pre<K>& p) {
+__device__ inline void fetch(const Step& s, uint32_t qoff, const Lane& L, const Bufs<K>& B, Ops<K>& o) {
   constexpr int N = Fam<K>::N;
-  const int nd = e.np * e.m, nw = e.R * e.np, ns = e.R * e.m;
+  const unsigned mask = (unsigned)s.E.z & 0xffffu;
+  const bool mem = (mask >> L.r) & 1u;
+  const int np = st_np(s), m = st_m(s);
+  const int q = 4 * s.ks + L.g;
+  const uint32_t d0 = (uint32_t)s.E.x, pt0 = (uint32_t)s.E.y;
+  uint32_t offD, sD;
+  if (s.fast) {
+    offD = L.lane8;
+    sD = d0 * 8u;
+  } else {
+    const int k = 16 * s.cb + L.r;
+    offD = (q < np && k < m) ? (d0 + (uint32_t)(q * m + k)) * 8u : OOB;
+    sD = 0u;
+  }
+  const bool wv = mem && q < np;
+  const uint32_t offW = wv ? (qoff + (uint32_t)q) * 8u : OOB;
+  const uint32_t offC = wv ? (pt0 + (uint32_t)q) * 8u : OOB;
+  const int kb = 16 * s.cb + L.g, mpad = (m + 15) & ~15;
+  const uint32_t offS = (mem && kb < m) ? (uint32_t)(__popc(mask & L.lowmask) * mpad + 16 * s.cb + 4 * L.g) : OOB;
 #pragma unroll
-  for (int u = 0; u < PFD; ++u) {
-    const int t = lane + WAVE * u;
-    if (t < nd) {
+  for (int a = 0; a < N; ++a) o.d[a] = bload64s(B.D[a], offD, sD);
 #pragma unroll
-      for (int a = 0; a < N; ++a) p.d[a][u] = S.D[a][e.d0 + t];
+  for (int a = 0; a < N; ++a) o.w[a] = bload64s(B.W[a], offW, 0u);
+#pragma unroll
+  for (int a = 0; a < Fam<K>::NC; ++a) o.c[a] = bload64s(B.C[a], offC, 0u);
+  if (Fam<K>::RES) {
+#pragma unroll
+    for (int a = 0; a < Fam<K>::NPF; ++a) o.pf[a] = bload64s(B.Pf[a], offC, 0u);
+  }
+  o.sl = bload32s(B.slot, offS, (uint32_t)s.E.w);
+}
+
+// The products of one step (4 points x 16 functions x the 16 rows of the tile).
+template <int K>
+__device__ inline void mfma_step(const double (&da)[Fam<K>::N], const double (&wb)[Fam<K>::N], d4& c0, d4& c1) {
+  const d4 z = {0.0, 0.0, 0.0, 0.0};
+  if (K == 0 || K == 2) {
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(da[0], wb[0], z, 0, 0, 0);
+  } else if (K == 1) {
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(da[0], wb[0], z, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(da[1], wb[1], c0, 0, 0, 0);
+  } else if (K == 3) {
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(da[0], wb[0], z, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(da[1], wb[1], z, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(da[2], wb[2], c1, 0, 0, 0);
+  } else {
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(da[0], wb[0], z, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(da[1], wb[1], c0, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(da[2], wb[2], c0, 0, 0, 0);
+  }
+}
+
+// Add the lane's four products (functions kb, kb + 4, kb + 8, kb + 12 of its row) to the
+// row's CSR slots (four slot bytes in sl).
+template <int NACC>
+__device__ inline void scatter(const d4& c0, const d4& c1, uint32_t sl, bool mem, int kb, int m, int ro, double* acc,
+                               int nzcap) {
+  // The products are moved to ordinary registers before the LDS adds read them: an LDS
+  // instruction that read the MFMA's accumulation registers directly was scheduled too
+  // soon after the FP64 MFMA on gfx950 and read unfinished sums (the register copies get
+  // the full wait).
+  double p0[4], p1[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    p0[v] = c0[v];
+    asm volatile("" : "+v"(p0[v]));
+    if (NACC == 2) {
+      p1[v] = c1[v];
+      asm volatile("" : "+v"(p1[v]));
     }
   }
+  if (mem && kb < m) {
 #pragma unroll
-  for (int u = 0; u < PFW; ++u) {
-    const int t = lane + WAVE * u;
-    if (t < nw) {
-      const int j = qdiv(t, e.rnp), q = t - j * e.np;
-      const int64_t qo = smem[e.mb + j].x & ((1 << 28) - 1);
-#pragma unroll
-      for (int a = 0; a < N; ++a) p.w[a][u] = S.W[a][qo + q];
-#pragma unroll
-      for (int a = 0; a < Fam<K>::NC; ++a) p.c[a][u] = S.C[a] ? S.C[a][e.pt0 + q] : 1.0;
-      if (Fam<K>::RES) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) p.pf[a][u] = S.Pf[a][e.pt0 + q];
+    for (int v = 0; v < 4; ++v) {
+      if (kb + 4 * v < m) {
+        const int at = ro + (int)((sl >> (8 * v)) & 0xffu);
+        __hip_atomic_fetch_add(acc + at, p0[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (NACC == 2) __hip_atomic_fetch_add(acc + nzcap + at, p1[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
       }
     }
   }
-#pragma unroll
-  for (int u = 0; u < PFS; ++u) {
-    const int t = lane + WAVE * u;
-    if (t < ns) {
-      const int j = qdiv(t, e.rm), k = t - j * e.m;
-      const int2 mm = smem[e.mb + j];
-      p.s[u] = slot[(uint32_t)mm.y + k];
-      p.rl[u] = (int)((unsigned)mm.x >> 28);
-    }
-  }
 }
 
+// Multiply one step and add its products to the member rows' CSR slots. A cell with more
+// than 4 points adds one partial sum per block of 4 points (in block order).
 template <int K>
-__device__ inline double scaled(const Src& S, int a, double w, double c) {
-  return Fam<K>::constant(a) ? w * S.scale : w * c;
-}
-
-// Write one prefetched entry into the LDS stage: basis blocks sd[a][q * m + k] and
-// coefficient-scaled weights sw[a][j * np + q]; parts beyond the register slots are
-// loaded here directly. Tangent: also the residual terms of (member j, point q),
-// rho[j * np + q] = w0 (Tdot - f) + wx k dT/dx + wy k dT/dy.
-template <int K>
-__device__ inline void stage(const Ent& e, int lane, const Src& S, const int2* smem, const Pre<K>& p,
-                             double* sd, int nd_cap, double* sw, int nw_cap, double* rho) {
+__device__ inline void compute(const Step& s, const Ops<K>& o, const Lane& L, int nzcap, const Src& S,
+                               const Bufs<K>& B, double* acc, double& rsum) {
   constexpr int N = Fam<K>::N;
-  const int nd = e.np * e.m, nw = e.R * e.np;
+  double wb[N];
 #pragma unroll
-  for (int u = 0; u < PFD; ++u) {
-    const int t = lane + WAVE * u;
-    if (t < nd) {
-#pragma unroll
-      for (int a = 0; a < N; ++a) sd[a * nd_cap + t] = p.d[a][u];
-    }
+  for (int a = 0; a < N; ++a) {
+    const double cf = B.cnull[Fam<K>::cof(a)] ? 1.0 : o.c[Fam<K>::cof(a)];
+    wb[a] = Fam<K>::constant(a) ? o.w[a] * S.scale : o.w[a] * cf;
   }
-  for (int t = lane + WAVE * PFD; t < nd; t += WAVE)
-    for (int a = 0; a < N; ++a) sd[a * nd_cap + t] = S.D[a][e.d0 + t];
-#pragma unroll
-  for (int u = 0; u < PFW; ++u) {
-    const int t = lane + WAVE * u;
-    if (t < nw) {
-#pragma unroll
-      for (int a = 0; a < N; ++a) sw[a * nw_cap + t] = scaled<K>(S, a, p.w[a][u], p.c[Fam<K>::cof(a)][u]);
-      if (Fam<K>::RES)
-        rho[t] = p.w[0][u] * p.pf[0][u] + (p.w[N - 2][u] * p.pf[1][u] + p.w[N - 1][u] * p.pf[2][u]);
-    }
-  }
-  for (int t = lane + WAVE * PFW; t < nw; t += WAVE) {
-    const int j = qdiv(t, e.rnp), q = t - j * e.np;
-    const int64_t qo = smem[e.mb + j].x & ((1 << 28) - 1);
-    double wv[N];
-    for (int a = 0; a < N; ++a) {
-      const double* C = S.C[Fam<K>::cof(a)];
-      wv[a] = S.W[a][qo + q];
-      sw[a * nw_cap + t] = scaled<K>(S, a, wv[a], C ? C[e.pt0 + q] : 1.0);
-    }
-    if (Fam<K>::RES)
-      rho[t] = wv[0] * S.Pf[0][e.pt0 + q] + (wv[N - 2] * S.Pf[1][e.pt0 + q] + wv[N - 1] * S.Pf[2][e.pt0 + q]);
-  }
+  // exact tangent: the mass-basis operand also carries k'(T_q) (w^x dT/dx + w^y dT/dy)
+  if (Fam<K>::EXACT) wb[0] += o.w[1] * o.pf[3] + o.w[2] * o.pf[4];
+  if (Fam<K>::RES && s.cb == 0) rsum += o.w[0] * o.pf[0] + (o.w[N - 2] * o.pf[1] + o.w[N - 1] * o.pf[2]);
+  d4 c0, c1;
+  mfma_step<K>(o.d, wb, c0, c1);
+  const unsigned mask = (unsigned)s.E.z & 0xffffu;
+  const bool mem = (mask >> L.r) & 1u;
+  if (s.fast) scatter<Fam<K>::NACC>(c0, c1, o.sl, mem, L.g, 16, L.ro, acc, nzcap);
+  else scatter<Fam<K>::NACC>(c0, c1, o.sl, mem, 16 * s.cb + L.g, st_m(s), L.ro, acc, nzcap);
 }
 
-// lane (j, k): v = sum_q sw[j][q] sd[q][k] (per family), added to acc[row j][slot k].
 template <int K>
-__device__ inline void accumulate(const Ent& e, int t, int sk, int rl, const double* sd, int nd_cap,
-                                  const double* sw, int nw_cap, const int* ro, double* acc, int acc_stride) {
-  const int j = qdiv(t, e.rm), k = t - j * e.m;
-  const double* w = sw + j * e.np;
-  double va = 0.0, vb = 0.0;
-  for (int q = 0; q < e.np; ++q) {
-    const int dq = q * e.m + k;
-    if (K == 0 || K == 2) {
-      va += w[q] * sd[dq];
-    } else if (K == 1) {
-      va += w[q] * sd[dq] + w[nw_cap + q] * sd[nd_cap + dq];
-    } else if (K == 3) {
-      va += w[q] * sd[dq];
-      vb += w[nw_cap + q] * sd[nd_cap + dq] + w[2 * nw_cap + q] * sd[2 * nd_cap + dq];
-    } else {
-      va += w[q] * sd[dq] + (w[nw_cap + q] * sd[nd_cap + dq] + w[2 * nw_cap + q] * sd[2 * nd_cap + dq]);
-    }
-  }
-  const int at = ro[rl] + sk;
-  acc[at] += va;
-  if (K == 3) acc[acc_stride + at] += vb;
-}
-
-// One wavefront owns a tile of TILE_ROWS consecutive rows and their accumulators in LDS.
-// It visits the tile's cells once each, in ascending order (one precomputed entry per
-// cell: basis block, points, member rows). Per entry, the whole wave loads the cell's
-// basis block and the members' weights with coalesced loads into an LDS stage, then
-// lane (j, k) forms v = sum_{points q of the cell} w_{i_j q} coef_q D_k(x_q) for member
-// row i_j and cell function k and adds it to acc[i_j][slot]. The next entry's loads are
-// issued into registers before the current one is computed. Within an entry the (j, k)
-// are distinct and entries are applied in order: no atomics, fixed summation order.
-// Tangent: lane j < R also adds its member's residual terms (sum over the cell's points,
-// in point order) to racc[i_j]; R is written once per row.
-// Workgroups of one XCD take chunks of consecutive tiles (L2 reuse between neighbours).
-template <int K>
-__global__ void __launch_bounds__(WAVE) k_assemble(int64_t n, int64_t n_tiles, int64_t chunk, int acc_stride,
-                                                   int mem_cap, int nd_cap, int nw_cap,
-                                                   const int64_t* __restrict__ eptr, const int4* __restrict__ ent,
-                                                   const int2* __restrict__ mem, const int64_t* __restrict__ sptr,
-                                                   const uint8_t* __restrict__ slot,
-                                                   const int64_t* __restrict__ row_ptr, Src S,
-                                                   double* __restrict__ out0, double* __restrict__ out1) {
+__global__ void __launch_bounds__(WAVE)
+    k_asm_mfma(int64_t n_tiles, int64_t chunk, int nzcap, int entcap, const int32_t* __restrict__ trow0,
+               const int64_t* __restrict__ teptr, const int4* __restrict__ tent, const uint8_t* __restrict__ tslot,
+               int64_t slot_bytes, const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ qptr,
+               int64_t basis_bytes, int64_t weight_bytes, int64_t point_bytes, Src S, double* __restrict__ out0,
+               double* __restrict__ out1) {
   constexpr int N = Fam<K>::N;
   constexpr int NACC = Fam<K>::NACC;
   constexpr bool RES = Fam<K>::RES;
   extern __shared__ double acc[];
-  __shared__ int ro[TILE_ROWS + 1];
-  __shared__ double racc[TILE_ROWS];
-  double* sd = acc + NACC * acc_stride;
-  double* sw = sd + N * nd_cap;
-  double* rho = sw + N * nw_cap;  // tangent only (nw_cap doubles)
-  int2* smem = (int2*)(rho + (RES ? nw_cap : 0));
-  // the tile's entry records (16-byte aligned after the member records): decoding an entry
-  // then waits on LDS, not on a global load ahead of the entry's own loads
-  int4* sent = (int4*)(((uintptr_t)(smem + mem_cap) + 15) & ~(uintptr_t)15);
+  const int lane = threadIdx.x;
+  // workgroup b runs on XCD b % 8; the XCD's workgroups take runs of `chunk` consecutive
+  // tiles (L2 reuse of the cells that neighbouring rows share)
   const int64_t b = blockIdx.x;
   const int64_t turn = b / NXCD;
   const int64_t tile = (turn / chunk) * (NXCD * chunk) + (b % NXCD) * chunk + turn % chunk;
   if (tile >= n_tiles) return;
-  const int lane = threadIdx.x;
-  const int64_t i0 = tile * TILE_ROWS;
-  const int nr = (int)min((int64_t)TILE_ROWS, n - i0);
+  Bufs<K> B;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    B.D[a] = make_rsrc(S.D[a], basis_bytes);
+    B.W[a] = make_rsrc(S.W[a], weight_bytes);
+  }
+#pragma unroll
+  for (int a = 0; a < Fam<K>::NC; ++a) {
+    B.C[a] = make_rsrc(S.C[a], point_bytes);
+    B.cnull[a] = S.C[a] == nullptr;
+  }
+  if (RES) {
+#pragma unroll
+    for (int a = 0; a < Fam<K>::NPF; ++a) B.Pf[a] = make_rsrc(S.Pf[a], point_bytes);
+  }
+  B.slot = make_rsrc(tslot, slot_bytes);
+  const int r = lane & 15, g = lane >> 4;
+  const int i0 = trow0[tile];
+  const int nr = trow0[tile + 1] - i0;
   const int64_t a0 = row_ptr[i0];
   const int nz = (int)(row_ptr[i0 + nr] - a0);
-  const int64_t e0 = eptr[tile];
-  const int ne = (int)(eptr[tile + 1] - e0);
-  const int64_t m0 = sptr[i0];
-  const int nm = (int)(sptr[i0 + nr] - m0);
-  if (lane <= nr) ro[lane] = (int)(row_ptr[i0 + lane] - a0);
-  if (RES && lane < TILE_ROWS) racc[lane] = 0.0;
-  for (int t = lane; t < NACC * acc_stride; t += WAVE) acc[t] = 0.0;
-  for (int t = lane; t < nm; t += WAVE) smem[t] = mem[m0 + t];
-  for (int t = lane; t < ne; t += WAVE) sent[t] = ent[e0 + t];
-  __syncthreads();
-  // Entries are pipelined DEPTH deep: while entry e is computed from the LDS stage, the
-  // loads of entries e+1 .. e+DEPTH-1 are in flight in registers (ring slot e % DEPTH).
+  const bool live = r < nr;
+  Lane L;
+  L.r = r;
+  L.g = g;
+  L.lane8 = (uint32_t)lane * 8u;
+  L.g8 = (uint32_t)g * 8u;
+  L.lowmask = (1u << r) - 1u;
+  L.ro = live ? (int)(row_ptr[i0 + r] - a0) : 0;
+  for (int t = lane; t < NACC * nzcap; t += WAVE) acc[t] = 0.0;
+  const int64_t e0 = teptr[tile];
+  const int ne = (int)(teptr[tile + 1] - e0);
+  // the tile's entry records, staged in LDS behind the accumulators (one coalesced read;
+  // the steps then decode them from LDS instead of waiting on memory for each cell)
+  int4* sent = (int4*)(acc + NACC * nzcap);
+  for (int t = lane; t < ne && t < entcap; t += WAVE) sent[t] = tent[e0 + t];
+  double rsum = 0.0;
   if (ne > 0) {
-    Pre<K> p[DEPTH];
-    Ent en[DEPTH];
+    Step st[STEPS];
+    uint32_t qo[STEPS];
+    Ops<K> op[STEPS];
+    uint32_t qnext = live ? (uint32_t)qptr[i0 + r] : 0u;
+    st[0].e = 0;
+    st[0].ks = 0;
+    st[0].cb = 0;
+    st[0].E = uniform_record(sent, 0);
+    st[0].valid = true;
+    st[0].fast = fast_record(st[0].E);
+    qo[0] = qnext;
+    fetch<K>(st[0], qo[0], L, B, op[0]);
 #pragma unroll
-    for (int u = 0; u < DEPTH; ++u)
-      if (u < ne) {
-        en[u] = decode(sent[u], m0);
-        prefetch<K>(en[u], lane, S, smem, slot, p[u]);
-      }
-    stage<K>(en[0], lane, S, smem, p[0], sd, nd_cap, sw, nw_cap, rho);
-    __syncthreads();
-    for (int eb = 0; eb < ne; eb += DEPTH) {
+    for (int u = 1; u < STEPS; ++u) {
+      st[u] = advance(st[u - 1], qnext, r, ne, sent);
+      qo[u] = qnext;
+      fetch<K>(st[u], qo[u], L, B, op[u]);
+    }
+    // Steps are valid up to some point and invalid after it; an invalid step computes
+    // nothing and fetches nothing but out-of-range offsets, so every pass of the loop body
+    // issues the same loads.
+    while (st[0].valid) {
 #pragma unroll
-      for (int u = 0; u < DEPTH; ++u) {
-        const int e = eb + u;
-        if (e < ne) {
-          const Ent& cur = en[u];
-          const int ns = cur.R * cur.m;
-#pragma unroll
-          for (int v = 0; v < PFS; ++v) {
-            const int t = lane + WAVE * v;
-            if (t < ns) accumulate<K>(cur, t, p[u].s[v], p[u].rl[v], sd, nd_cap, sw, nw_cap, ro, acc, acc_stride);
-          }
-          for (int t = lane + WAVE * PFS; t < ns; t += WAVE) {
-            const int j = qdiv(t, cur.rm), k = t - j * cur.m;
-            const int2 mm = smem[cur.mb + j];
-            accumulate<K>(cur, t, slot[(uint32_t)mm.y + k], (int)((unsigned)mm.x >> 28), sd, nd_cap, sw, nw_cap, ro,
-                          acc, acc_stride);
-          }
-          if (RES && lane < cur.R) {
-            double v = 0.0;
-            for (int q = 0; q < cur.np; ++q) v += rho[lane * cur.np + q];
-            racc[(unsigned)smem[cur.mb + lane].x >> 28] += v;
-          }
-          __syncthreads();
-          const int un = (u + 1) % DEPTH;
-          if (e + 1 < ne) stage<K>(en[un], lane, S, smem, p[un], sd, nd_cap, sw, nw_cap, rho);
-          if (e + DEPTH < ne) {  // slot u is free: start entry e + DEPTH
-            en[u] = decode(sent[e + DEPTH], m0);
-            prefetch<K>(en[u], lane, S, smem, slot, p[u]);
-          }
-          __syncthreads();
-        }
+      for (int u = 0; u < STEPS; ++u) {
+        if (st[u].valid) compute<K>(st[u], op[u], L, nzcap, S, B, acc, rsum);
+        st[u] = advance(st[(u + STEPS - 1) % STEPS], qnext, r, ne, sent);
+        qo[u] = qnext;
+        fetch<K>(st[u], qo[u], L, B, op[u]);
       }
     }
   }
+  if (RES) {
+    const double t0 = __shfl(rsum, r, WAVE), t1 = __shfl(rsum, r + 16, WAVE), t2 = __shfl(rsum, r + 32, WAVE),
+                 t3 = __shfl(rsum, r + 48, WAVE);
+    if (g == 0 && live) out1[i0 + r] = (t0 + t1) + (t2 + t3);
+  }
   for (int t = lane; t < nz; t += WAVE) {
     out0[a0 + t] = acc[t];
-    if (K == 3) out1[a0 + t] = acc[acc_stride + t];
+    if (K == 3) out1[a0 + t] = acc[nzcap + t];
   }
-  if (RES && lane < nr) out1[i0 + lane] = racc[lane];
 }
 
 template <int K>
-wq_status launch(const wq_points* P, const wq_weights* w, Src S, double* o0, double* o1, hipStream_t st) {
+wq_status launch(const wq_points* P, const wq_weights* w, Src S, double* o0, double* o1, hipStream_t st,
+                 bool timed = true) {
   constexpr int N = Fam<K>::N;
   constexpr int NACC = Fam<K>::NACC;
-  const int nd_cap = P->max_tile_nd, nw_cap = P->max_tile_nw;
-  const size_t lds = (size_t)NACC * P->max_tile_nnz * sizeof(double) +
-                     (size_t)(N * (nd_cap + nw_cap) + (Fam<K>::RES ? nw_cap : 0)) * sizeof(double) +
-                     (size_t)P->max_tile_mem * sizeof(int2) + 16 + (size_t)P->max_tile_ent * sizeof(int4);
-  WQ_CHECK(lds <= 150 * 1024, WQ_EINVAL, "assemble: tile accumulators and stage exceed LDS");
-  WQ_CHECK(nw_cap < 4096 && (int64_t)TILE_ROWS * 255 < 4096, WQ_EINVAL, "assemble: entry too large");
+  const int nzcap = (P->t2_maxnz + 1) & ~1;
+  const int entcap = P->t2_maxent;
+  const size_t lds = (size_t)NACC * nzcap * sizeof(double) + (size_t)entcap * sizeof(int4);
+  WQ_CHECK(lds <= 64 * 1024, WQ_EINVAL, "assemble: tile accumulators exceed LDS");
+  // buffer loads take 32-bit byte offsets
+  const int64_t sum_r = (int64_t)(P->qidx.bytes / sizeof(int32_t));
+  const int64_t lim = (int64_t)OOB;
+  WQ_CHECK(P->n_basis * 8 < lim && sum_r * 8 < lim && P->n_points * 8 < lim && (int64_t)P->t2_slot.bytes < lim,
+           WQ_EINVAL, "assemble: mesh too large for one launch (2 GiB per array); split it");
   if (K == 0) {
     S.D[0] = P->DN.as<double>();
     S.W[0] = w->W[0].as<double>();
@@ -326,27 +411,22 @@ wq_status launch(const wq_points* P, const wq_weights* w, Src S, double* o0, dou
     S.W[1] = w->W[1].as<double>();
     S.W[2] = w->W[2].as<double>();
   }
-  // workgroup b runs on XCD b % 8 and takes, in turn, chunks of `chunk` consecutive tiles
-  // (L2 reuse between neighbouring rows on one XCD); the grid covers whole rounds of
-  // 8 * chunk tiles and blocks past the end exit
   const int64_t chunk = P->asm_chunk;
-  const int64_t per_xcd = ((P->n_tiles + NXCD * chunk - 1) / (NXCD * chunk)) * chunk;
-  static const char* names[5] = {"k_assemble_mass", "k_assemble_stiffness", "k_assemble_biharmonic",
-                                  "k_assemble_mass_stiffness", "k_assemble_tangent"};
-  if (lds > 64 * 1024)
-    WQ_HIP(hipFuncSetAttribute((const void*)k_assemble<K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int64_t per_xcd = ((P->n_t2 + NXCD * chunk - 1) / (NXCD * chunk)) * chunk;
+  static const char* names[6] = {"k_assemble_mass", "k_assemble_stiffness", "k_assemble_biharmonic",
+                                  "k_assemble_mass_stiffness", "k_assemble_tangent", "k_assemble_tangent_exact"};
   // algorithmic bytes: every basis value and weight once, the coefficients, the output
-  const int64_t sum_r = (int64_t)(P->qidx.bytes / sizeof(int32_t));
   int64_t nc = 0;
   for (int a = 0; a < 2; ++a) nc += S.C[a] ? 1 : 0;
-  if (K == 4) nc = 4;  // k, Tdot - f, k dT/dx, k dT/dy
-  const int64_t outb = K == 4 ? P->nnz + P->n_rows : NACC * P->nnz;
-  KTimer tm(names[K], 8 * (2 * N * sum_r + nc * P->n_points + outb), st);
-  k_assemble<K><<<(unsigned)(per_xcd * NXCD), WAVE, lds, st>>>(
-      P->n_rows, P->n_tiles, chunk, P->max_tile_nnz, P->max_tile_mem, nd_cap, nw_cap, P->tile_eptr.as<int64_t>(),
-      P->tile_ent.as<int4>(), P->tile_mem.as<int2>(), P->supp_ptr.as<int64_t>(), P->slot.as<uint8_t>(),
-      P->row_ptr.as<int64_t>(), S, o0, o1);
-  tm.stop();
+  if (K >= 4) nc = 1 + Fam<K>::NPF;  // k and the point fields
+  const int64_t outb = K >= 4 ? P->nnz + P->n_rows : NACC * P->nnz;
+  KTimer tm(timed ? names[K] : nullptr, 8 * (2 * N * sum_r + nc * P->n_points + outb), timed ? st : nullptr);
+  if (P->n_t2 > 0)
+    k_asm_mfma<K><<<(unsigned)(per_xcd * NXCD), WAVE, lds, st>>>(
+        P->n_t2, chunk, nzcap, entcap, P->t2_row0.as<int32_t>(), P->t2_eptr.as<int64_t>(), P->t2_ent.as<int4>(),
+        P->t2_slot.as<uint8_t>(), (int64_t)P->t2_slot.bytes, P->row_ptr.as<int64_t>(), P->qptr.as<int64_t>(),
+        P->n_basis * 8, sum_r * 8, P->n_points * 8, S, o0, o1);
+  if (timed) tm.stop();
   WQ_HIP(hipGetLastError());
   return WQ_OK;
 }
@@ -377,15 +457,27 @@ __device__ inline double kval(const wq_conductivity& k, double u) {
   }
 }
 
+// k'(u)
+__device__ inline double kder(const wq_conductivity& k, double u) {
+  switch (k.kind) {
+    case WQ_K_LINEAR: return k.b;
+    case WQ_K_QUADRATIC: return 2.0 * k.b * u;
+    case WQ_K_EXP: return k.a * k.b * exp(k.b * u);
+    default: return k.a * k.b * cos(k.b * u);
+  }
+}
+
 // One thread per (cell, point): T, Tdot, dT/dx, dT/dy at the point from the cell's
-// functions (T(x_q) = sum_j T_j N_j(x_q)); k_q = k(T_q) and the residual point fields.
+// functions (T(x_q) = sum_j T_j N_j(x_q)); k_q = k(T_q) and the residual point fields;
+// with p3 (exact tangent) also k'(T_q) dT/dx and k'(T_q) dT/dy.
 __global__ void k_point_fields(int32_t ncell, int max_np, const int64_t* __restrict__ cell_pt_off,
                                const int64_t* __restrict__ cfn_ptr, const int32_t* __restrict__ cfn,
                                const int64_t* __restrict__ dptr, const double* __restrict__ DN,
                                const double* __restrict__ DX, const double* __restrict__ DY,
                                const double* __restrict__ T, const double* __restrict__ Td,
                                const double* __restrict__ f, wq_conductivity kc, double* __restrict__ kq,
-                               double* __restrict__ p0, double* __restrict__ p1, double* __restrict__ p2) {
+                               double* __restrict__ p0, double* __restrict__ p1, double* __restrict__ p2,
+                               double* __restrict__ p3, double* __restrict__ p4) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t c = g / max_np;
   const int q = (int)(g - c * max_np);
@@ -411,6 +503,11 @@ __global__ void k_point_fields(int32_t ncell, int max_np, const int64_t* __restr
   p0[pt] = ud - (f ? f[pt] : 0.0);
   p1[pt] = kk * ux;
   p2[pt] = kk * uy;
+  if (p3) {
+    const double dk = kder(kc, u);
+    p3[pt] = dk * ux;
+    p4[pt] = dk * uy;
+  }
 }
 
 // ------------------------------------------------------------------ split precision
@@ -815,30 +912,27 @@ extern "C" wq_status assemble_mass_stiffness(const wq_points* P, const wq_weight
   return dispatch<3>(P, w, c, k, mv, kv, prec, (hipStream_t)stream);
 }
 
-extern "C" wq_status assemble_tangent(const wq_points* P, const wq_weights* w, const double* T, const double* Tdot,
-                                      double inv_theta_dt, wq_conductivity k, const double* f_at_pts, void* S_vals,
-                                      double* R, wq_precision prec, wq_stream stream) {
-  WQ_TRY(check(P, w, WQ_FAM_MASS | WQ_FAM_DX | WQ_FAM_DY, S_vals, prec));
-  WQ_CHECK(prec == WQ_FP64, WQ_EINVAL, "assemble_tangent: the Newton tangent and residual are FP64 only");
-  WQ_CHECK(T && Tdot && R, WQ_EINVAL, "assemble_tangent: null T, Tdot or R");
-  WQ_CHECK(k.kind >= WQ_K_LINEAR && k.kind <= WQ_K_SIN, WQ_EINVAL, "assemble_tangent: unknown conductivity kind");
-  WQ_CHECK(std::isfinite(inv_theta_dt), WQ_EINVAL, "assemble_tangent: 1/(theta dt) not finite");
-  hipStream_t st = (hipStream_t)stream;
-  wq_points* Pm = const_cast<wq_points*>(P);
-  if (Pm->tangent_ws.bytes < 4 * (size_t)P->n_points * sizeof(double))
-    WQ_TRY(dalloc_n<double>(Pm->tangent_ws, 4 * (size_t)P->n_points));
-  double* kq = Pm->tangent_ws.as<double>();
+namespace {
+
+// Eq. (36) tangent and residual with the point fields (k_q and the three residual terms,
+// 4 x n_points doubles) in `ws`. `timed`: record kernel timings when enabled.
+wq_status tangent_impl(const wq_points* P, const wq_weights* w, const double* T, const double* Tdot,
+                       double inv_theta_dt, wq_conductivity k, const double* f_at_pts, void* S_vals, double* R,
+                       double* ws, hipStream_t st, bool timed, bool exact = false) {
+  double* kq = ws;
   double* p0 = kq + P->n_points;
   double* p1 = p0 + P->n_points;
   double* p2 = p1 + P->n_points;
+  double* p3 = exact ? p2 + P->n_points : nullptr;  // exact tangent: 6 x n_points in ws
+  double* p4 = exact ? p3 + P->n_points : nullptr;
   const int mnp = P->max_cell_np;
   {
-    KTimer tm("k_point_fields", P->n_points, st);
+    KTimer tm(timed ? "k_point_fields" : nullptr, P->n_points, timed ? st : nullptr);
     k_point_fields<<<nblocks((int64_t)P->ncell * mnp, 256), 256, 0, st>>>(
         P->ncell, mnp, P->cell_pt_off.as<int64_t>(), P->cfn_ptr.as<int64_t>(), P->cfn.as<int32_t>(),
         P->dptr.as<int64_t>(), P->DN.as<double>(), P->DX.as<double>(), P->DY.as<double>(), T, Tdot, f_at_pts, k, kq,
-        p0, p1, p2);
-    tm.stop();
+        p0, p1, p2, p3, p4);
+    if (timed) tm.stop();
     WQ_HIP(hipGetLastError());
   }
   Src S = src_coef(kq, nullptr);
@@ -846,5 +940,45 @@ extern "C" wq_status assemble_tangent(const wq_points* P, const wq_weights* w, c
   S.Pf[0] = p0;
   S.Pf[1] = p1;
   S.Pf[2] = p2;
-  return launch<4>(P, w, S, (double*)S_vals, R, st);
+  if (exact) {
+    S.Pf[3] = p3;
+    S.Pf[4] = p4;
+    return launch<5>(P, w, S, (double*)S_vals, R, st, timed);
+  }
+  return launch<4>(P, w, S, (double*)S_vals, R, st, timed);
+}
+
+wq_status tangent_check(const wq_points* P, const wq_weights* w, const double* T, const double* Tdot,
+                        double inv_theta_dt, wq_conductivity k, void* S_vals, double* R, wq_precision prec) {
+  WQ_TRY(check(P, w, WQ_FAM_MASS | WQ_FAM_DX | WQ_FAM_DY, S_vals, prec));
+  WQ_CHECK(prec == WQ_FP64, WQ_EINVAL, "assemble_tangent: the Newton tangent and residual are FP64 only");
+  WQ_CHECK(T && Tdot && R, WQ_EINVAL, "assemble_tangent: null T, Tdot or R");
+  WQ_CHECK(k.kind >= WQ_K_LINEAR && k.kind <= WQ_K_SIN, WQ_EINVAL, "assemble_tangent: unknown conductivity kind");
+  WQ_CHECK(std::isfinite(inv_theta_dt), WQ_EINVAL, "assemble_tangent: 1/(theta dt) not finite");
+  return WQ_OK;
+}
+
+}  // namespace
+
+extern "C" wq_status assemble_tangent(const wq_points* P, const wq_weights* w, const double* T, const double* Tdot,
+                                      double inv_theta_dt, wq_conductivity k, const double* f_at_pts, void* S_vals,
+                                      double* R, wq_precision prec, wq_stream stream) {
+  WQ_TRY(tangent_check(P, w, T, Tdot, inv_theta_dt, k, S_vals, R, prec));
+  wq_points* Pm = const_cast<wq_points*>(P);
+  if (Pm->tangent_ws.bytes < 4 * (size_t)P->n_points * sizeof(double))
+    WQ_TRY(dalloc_n<double>(Pm->tangent_ws, 4 * (size_t)P->n_points));
+  return tangent_impl(P, w, T, Tdot, inv_theta_dt, k, f_at_pts, S_vals, R, Pm->tangent_ws.as<double>(),
+                      (hipStream_t)stream, true);
+}
+
+extern "C" wq_status assemble_tangent_exact(const wq_points* P, const wq_weights* w, const double* T,
+                                            const double* Tdot, double inv_theta_dt, wq_conductivity k,
+                                            const double* f_at_pts, void* S_vals, double* R, wq_precision prec,
+                                            wq_stream stream) {
+  WQ_TRY(tangent_check(P, w, T, Tdot, inv_theta_dt, k, S_vals, R, prec));
+  wq_points* Pm = const_cast<wq_points*>(P);
+  if (Pm->tangent_ws.bytes < 6 * (size_t)P->n_points * sizeof(double))
+    WQ_TRY(dalloc_n<double>(Pm->tangent_ws, 6 * (size_t)P->n_points));
+  return tangent_impl(P, w, T, Tdot, inv_theta_dt, k, f_at_pts, S_vals, R, Pm->tangent_ws.as<double>(),
+                      (hipStream_t)stream, true, true);
 }

@@ -189,7 +189,7 @@ extern "C" wq_status wq_autotune_assembly(wq_points* P, const wq_weights* w, wq_
   WQ_TRY(dalloc_n<double>(M, P->nnz));
   WQ_TRY(dalloc_n<double>(K, P->nnz));
   // run lengths up to one contiguous band of tiles per XCD
-  const int band = (int)((P->n_tiles + 7) / 8);
+  const int band = (int)((P->n_t2 + 7) / 8);
   std::vector<int> cand;
   for (int c = 4; c < band && c <= 1024; c *= 2) cand.push_back(c);
   cand.push_back(band);

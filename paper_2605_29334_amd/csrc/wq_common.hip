@@ -123,7 +123,7 @@ static std::vector<TRec> g_trecs;
 bool timing_enabled() { return g_timing; }
 
 KTimer::KTimer(const char* n, int64_t w, hipStream_t s) : st(s), name(n), work(w) {
-  if (!g_timing) return;
+  if (!g_timing || !n) return;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
     a = b = nullptr;
     return;

@@ -227,7 +227,8 @@ extern "C" wq_status wq_heat_step(const wq_points* P, const wq_weights* w, const
                                   const uint8_t* dirichlet, const double* g_next, const double* f_at_pts, double* T,
                                   double* Tdot, double* S_vals, wq_heat_report* rep, wq_stream stream) {
   WQ_CHECK(P && w && hp && dirichlet && T && Tdot && S_vals, WQ_EINVAL, "wq_heat_step: null argument");
-  WQ_CHECK(hp->dt > 0 && hp->theta > 0 && hp->theta <= 1 && hp->tol > 0 && hp->max_newton >= 0 && hp->max_cg > 0,
+  WQ_CHECK(hp->dt > 0 && hp->theta > 0 && hp->theta <= 1 && hp->tol > 0 && hp->max_newton >= 0 && hp->max_cg > 0 &&
+               (hp->tangent == WQ_TANGENT_SYMMETRIC || hp->tangent == WQ_TANGENT_EXACT),
            WQ_EINVAL, "wq_heat_step: bad parameters");
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = P->n_rows;
@@ -256,7 +257,10 @@ extern "C" wq_status wq_heat_step(const wq_points* P, const wq_weights* w, const
   wq_status status = WQ_OK;
   for (int it = 0;; ++it) {
     k_rate<<<nb, RB, 0, st>>>(n, T, Tdot, ws, c1, inv_tdt);
-    WQ_TRY(assemble_tangent(P, w, T, Tdot, inv_tdt, hp->k, f_at_pts, S_vals, ws.R, WQ_FP64, stream));
+    if (hp->tangent == WQ_TANGENT_EXACT)
+      WQ_TRY(assemble_tangent_exact(P, w, T, Tdot, inv_tdt, hp->k, f_at_pts, S_vals, ws.R, WQ_FP64, stream));
+    else
+      WQ_TRY(assemble_tangent(P, w, T, Tdot, inv_tdt, hp->k, f_at_pts, S_vals, ws.R, WQ_FP64, stream));
     k_norm_free<<<nb, RB, 0, st>>>(n, ws.R, dirichlet, ws);
     WQ_HIP(hipGetLastError());
     double nr2 = 0.0;

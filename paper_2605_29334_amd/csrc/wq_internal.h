@@ -91,6 +91,14 @@ struct wq_points {
   int32_t asm_chunk = 64;  // consecutive tiles per XCD turn in the assembly launch (tunable)
   wq::DBuf tile_eptr /*int64 [tiles+1]*/, tile_ent /*int4 [entries]: dptr, pt0, mask|np<<16|m<<24, mbase*/,
       tile_mem /*int2 [pairs]: qoff | rowloc<<28, soff*/;
+  // cell-major assembly tiles: runs of up to T2_ROWS consecutive rows with at most T2_NZCAP CSR
+  // entries; one entry per (tile, cell in the support of some row of the tile), cells
+  // ascending: int4 (basis block offset, first point, member mask | np << 16 | m << 24, byte
+  // offset of the entry's slot maps in t2_slot: one per member row, rows ascending, each the
+  // (row, cell) pair's map padded to a multiple of 4 bytes)
+  int64_t n_t2 = 0, n_e2 = 0;
+  int32_t t2_maxnz = 0, t2_maxent = 0;  // largest CSR entries, largest cell entries of a tile
+  wq::DBuf t2_row0 /*int32 [n_t2+1]*/, t2_eptr /*int64 [n_t2+1]*/, t2_ent /*int4*/, t2_slot /*uint8*/;
   // per point
   wq::DBuf x /*double [2 np]*/, detJ /*double [np]*/;
   // per (cell, point, cell function)
@@ -155,6 +163,8 @@ struct KTimer {
 };
 
 constexpr int TILE_ROWS = 8;
+constexpr int T2_ROWS = 16;    // rows per cell-major assembly tile (MFMA 16 x 16 x 4 columns)
+constexpr int T2_NZCAP = 416;  // CSR entries per cell-major tile (8 rows of 52; 16 short rows)
 
 // 64-bit index launch helper
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }

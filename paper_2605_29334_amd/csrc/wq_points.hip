@@ -306,7 +306,7 @@ __global__ void k_pair_m(int64_t npairs, const int32_t* scell, const int64_t* cf
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= npairs) return;
   const int32_t c = scell[p];
-  m[p] = cfn_ptr[c + 1] - cfn_ptr[c];
+  m[p] = (cfn_ptr[c + 1] - cfn_ptr[c] + 3) & ~int64_t(3);  // padded: slot maps start 4-byte aligned
 }
 
 // slot of every cell function in row i (position in S_i) and of N_i itself in the cell
@@ -538,6 +538,69 @@ __global__ void k_tile_entries(int64_t n, const int64_t* sptr, const int32_t* sc
   }
 }
 
+// Cell-major tiles: merge of the (ascending) cell lists of the rows [row0[t], row0[t+1]).
+// FILL == false: count the distinct cells and the slot-map bytes of their members;
+// FILL == true: write one entry per cell and copy its member rows' slot maps behind the
+// tile's earlier ones (row order; each map padded to whole blocks of 16 functions and
+// stored in the order the assembly's lanes read it: byte 16 cb + 4 g + v of a map holds the
+// slot of function 16 cb + g + 4 v).
+template <bool FILL>
+__global__ void k_tile2_entries(int64_t n_tiles, const int32_t* row0, const int64_t* sptr, const int32_t* scell,
+                                const int64_t* cfn_ptr, const int64_t* cell_pt_off, const int64_t* dptr,
+                                const int64_t* soff, const uint8_t* slot, int64_t* eptr, int64_t* bptr, int4* ent,
+                                uint8_t* tslot, int* overflow) {
+  const int64_t tile = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (tile >= n_tiles) return;
+  const int i0 = row0[tile];
+  const int nr = row0[tile + 1] - i0;
+  int64_t pos[T2_ROWS], end[T2_ROWS];
+  for (int r = 0; r < nr; ++r) {
+    pos[r] = sptr[i0 + r];
+    end[r] = sptr[i0 + r + 1];
+  }
+  int64_t e = FILL ? eptr[tile] : 0;
+  int64_t sb = FILL ? bptr[tile] : 0;  // slot-map bytes
+  int count = 0;
+  while (true) {
+    int32_t best = INT_MAX;
+    for (int r = 0; r < nr; ++r)
+      if (pos[r] < end[r]) best = min(best, scell[pos[r]]);
+    if (best == INT_MAX) break;
+    const int np = (int)(cell_pt_off[best + 1] - cell_pt_off[best]);
+    const int m = (int)(cfn_ptr[best + 1] - cfn_ptr[best]);
+    const int mpad = (m + 15) & ~15;
+    const int64_t sb0 = sb;
+    unsigned mask = 0;
+    for (int r = 0; r < nr; ++r) {
+      if (pos[r] < end[r] && scell[pos[r]] == best) {
+        mask |= 1u << r;
+        if (FILL) {
+          const int64_t so = soff[pos[r]];
+          for (int t = 0; t < mpad; ++t) {
+            const int k = (t & ~15) + ((t >> 2) & 3) + 4 * (t & 3);
+            tslot[sb + t] = k < m ? slot[so + k] : (uint8_t)0;
+          }
+        }
+        sb += mpad;
+        ++pos[r];
+      }
+    }
+    if (FILL) {
+      const int64_t d0 = dptr[best];
+      if (d0 > (int64_t)INT32_MAX || cell_pt_off[best] > (int64_t)INT32_MAX || sb > (int64_t)INT32_MAX || np > 255 ||
+          m > 255)
+        atomicOr(overflow, 1);
+      ent[e] = make_int4((int)d0, (int)cell_pt_off[best], (int)(mask | (np << 16) | (m << 24)), (int)sb0);
+      ++e;
+    }
+    ++count;
+  }
+  if (!FILL) {
+    eptr[tile] = count;
+    bptr[tile] = sb;
+  }
+}
+
 struct Tmp {
   DBuf vptr, vcur, vidx, bnd, val, ep, passive, enriched, pvtx, tpoint, flags;
   void release() {
@@ -553,6 +616,7 @@ void release_points(wq_points* P) {
   dfree(P->soff); dfree(P->slot); dfree(P->kself); dfree(P->x); dfree(P->detJ);
   dfree(P->DN); dfree(P->DX); dfree(P->DY); dfree(P->DL);
   dfree(P->tile_eptr); dfree(P->tile_ent); dfree(P->tile_mem);
+  dfree(P->t2_row0); dfree(P->t2_eptr); dfree(P->t2_ent); dfree(P->t2_slot);
   dfree(P->tangent_ws); dfree(P->newton_ws);
   for (int f = 0; f < 4; ++f) dfree(P->DS[f]);
   P->ds_prec = 0;
@@ -798,6 +862,66 @@ wq_status build_tiles(wq_mesh* M, wq_points* P, DBuf& flags, hipStream_t st) {
   return WQ_OK;
 }
 
+// Cell-major tiles: runs of consecutive rows, at most T2_ROWS rows and T2_NZCAP CSR entries
+// each (the tile's accumulators live in LDS), cut greedily in row order on the host.
+wq_status build_tiles2(wq_points* P, DBuf& flags, hipStream_t st) {
+  const int64_t n = P->n_rows;
+  WQ_CHECK(n < INT32_MAX, WQ_EINVAL, "build_points: too many rows for 32-bit tile row ids");
+  std::vector<int64_t> rp(n + 1);
+  WQ_HIP(hipMemcpyAsync(rp.data(), P->row_ptr.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  WQ_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> row0;
+  row0.reserve(n / 8 + 2);
+  int32_t maxnz = 0;
+  for (int64_t i = 0; i < n;) {
+    const int64_t s = i;
+    int64_t nz = 0;
+    while (i < n && i - s < T2_ROWS && nz + (rp[i + 1] - rp[i]) <= T2_NZCAP) nz += rp[i + 1] - rp[i], ++i;
+    WQ_CHECK(i > s, WQ_EINVAL, "build_points: a row exceeds the cell-major tile capacity");
+    row0.push_back((int32_t)s);
+    maxnz = std::max(maxnz, (int32_t)nz);
+  }
+  row0.push_back((int32_t)n);
+  P->n_t2 = (int64_t)row0.size() - 1;
+  P->t2_maxnz = maxnz;
+  DBuf bptr;
+  WQ_TRY(dalloc_n<int32_t>(P->t2_row0, row0.size()));
+  WQ_HIP(hipMemcpyAsync(P->t2_row0.p, row0.data(), row0.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  WQ_TRY(dalloc_n<int64_t>(P->t2_eptr, P->n_t2 + 1));
+  WQ_TRY(dalloc_n<int64_t>(bptr, P->n_t2 + 1));
+  WQ_HIP(hipMemsetAsync(P->t2_eptr.p, 0, (P->n_t2 + 1) * sizeof(int64_t), st));
+  WQ_HIP(hipMemsetAsync(bptr.p, 0, (P->n_t2 + 1) * sizeof(int64_t), st));
+  WQ_HIP(hipMemsetAsync(flags.p, 0, 8 * sizeof(int), st));
+  k_tile2_entries<false><<<nblocks(P->n_t2, 64), 64, 0, st>>>(
+      P->n_t2, P->t2_row0.as<int32_t>(), P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
+      P->cfn_ptr.as<int64_t>(), P->cell_pt_off.as<int64_t>(), P->dptr.as<int64_t>(), P->soff.as<int64_t>(),
+      P->slot.as<uint8_t>(), P->t2_eptr.as<int64_t>(), bptr.as<int64_t>(), nullptr, nullptr, flags.as<int>());
+  int64_t nbytes = 0;
+  {
+    std::vector<int64_t> cnt(P->n_t2);
+    WQ_HIP(hipMemcpyAsync(cnt.data(), P->t2_eptr.p, P->n_t2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    WQ_HIP(hipStreamSynchronize(st));
+    int64_t mx = 0;
+    for (int64_t c : cnt) mx = std::max(mx, c);
+    P->t2_maxent = (int32_t)mx;
+  }
+  WQ_TRY(exclusive_scan_i64(P->t2_eptr.as<int64_t>(), P->n_t2 + 1, &P->n_e2, st));
+  WQ_TRY(exclusive_scan_i64(bptr.as<int64_t>(), P->n_t2 + 1, &nbytes, st));
+  WQ_TRY(dalloc(P->t2_ent, (size_t)P->n_e2 * sizeof(int4)));
+  WQ_TRY(dalloc(P->t2_slot, (size_t)nbytes + 4));
+  k_tile2_entries<true><<<nblocks(P->n_t2, 64), 64, 0, st>>>(
+      P->n_t2, P->t2_row0.as<int32_t>(), P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
+      P->cfn_ptr.as<int64_t>(), P->cell_pt_off.as<int64_t>(), P->dptr.as<int64_t>(), P->soff.as<int64_t>(),
+      P->slot.as<uint8_t>(), P->t2_eptr.as<int64_t>(), bptr.as<int64_t>(), P->t2_ent.as<int4>(),
+      P->t2_slot.as<uint8_t>(), flags.as<int>());
+  int hf[1];
+  WQ_TRY(sync_flags(flags, hf, 1, st));
+  dfree(bptr);
+  WQ_CHECK(!hf[0], WQ_EINVAL, "build_points: mesh too large for 32-bit cell-major tile offsets; split it");
+  WQ_HIP(hipGetLastError());
+  return WQ_OK;
+}
+
 wq_status build_points_impl(wq_mesh* M, int want_lap, const uint8_t* s_host, hipStream_t st, wq_points** out,
                             int64_t* n_rows, int64_t* nnz, int64_t* n_points) {
   WQ_CHECK(M && out, WQ_EINVAL, "build_points: null argument");
@@ -889,6 +1013,7 @@ wq_status build_points_impl(wq_mesh* M, int want_lap, const uint8_t* s_host, hip
   }
   // assembly tiles (need dptr)
   if (s == WQ_OK) s = build_tiles(M, P, flags, st);
+  if (s == WQ_OK) s = build_tiles2(P, flags, st);
   dfree(flags);
   if (s != WQ_OK) {
     release_points(P);
@@ -947,9 +1072,9 @@ extern "C" int64_t wq_points_info(const wq_points* P, int what) {
     case 0: return P->max_row;
     case 1: return P->max_r;
     case 2: return P->ncell;
-    case 3: return P->n_tiles;
-    case 4: return P->n_entries;
-    case 5: return P->max_tile_nnz;
+    case 3: return P->n_t2;
+    case 4: return P->n_e2;
+    case 5: return P->t2_maxnz;
     case 6: return P->max_tile_ent;
     case 7: return P->max_tile_mem;
     case 8: return P->n_pairs;

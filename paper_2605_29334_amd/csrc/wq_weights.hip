@@ -172,9 +172,11 @@ struct SysClass {
 
 // Size buckets of the weight systems: LDS is sized per bucket, so typical systems are
 // not charged for the largest one. n bounds x r bounds.
-__constant__ int c_nb[5] = {32, 48, 64, 96, 128};
+// (The split at n = 56 keeps the instances with 7 and with 8 rows of M per lane in buckets
+// of their own: a bucket's instance follows from its bounds alone.)
+__constant__ int c_nb[6] = {32, 48, 56, 64, 96, 128};
 __constant__ int c_rb[7] = {64, 80, 96, 128, 160, 192, 256};
-constexpr int NB_N = 5, NB_R = 7, NBKT = NB_N * NB_R;
+constexpr int NB_N = 6, NB_R = 7, NBKT = NB_N * NB_R;
 
 // Also sums, per bucket, the algorithmic FLOPs of its systems, 6 r n^2 - 2 n^3: one
 // bidiagonalisation of the r x n matrix (4 r n^2 - 4 n^3 / 3) plus the QR of Z V_t at
@@ -1252,9 +1254,9 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       //    no lane runs zero rows through the rotations, 8 above); other n <= 64: 256
       //    threads, 8 lanes.
       const int bn = b / NB_R, br = b % NB_R;
-      const bool w512 = bn == 3 && br <= 3;
-      const bool m512 = bn == 2 && br >= 2 && br <= 3;
-      const bool wide = bn >= 3;
+      const bool w512 = bn == 4 && br <= 3;                          // 64 < n <= 96, r <= 128
+      const bool m512 = (bn == 2 || bn == 3) && br >= 2 && br <= 3;  // 48 < n <= 64, 80 < r <= 128
+      const bool wide = bn >= 4;                                     // n > 64
       const int lpp = ((wide && !w512) || m512) ? 16 : 8;  // lanes per column pair of the instance
       int ldm = ((mn + 8) / 16) * 16 + 8;
       if (ldm < (mn + lpp - 1) / lpp * lpp) ldm += 16;
@@ -1306,7 +1308,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
         // EPR: register elements per lane of a column of A^T (r), EPJ: of M (n)
         const int epr = (mr + 7) / 8;
         nt = !wide ? (m512 ? 512 : 256) : w512 ? 512 : 1024;
-        const bool j7 = mn > 48 && mn <= 56;  // 7 rows of M per lane
+        const bool j7 = bn == 2;  // 48 < n <= 56: 7 rows of M per lane
         if (m512) fn = (const void*)k_tsvd2<16, 8, 4, 512>, kname = "k_tsvd2<16,8,4,512>";
         else if (!wide && epr <= 8 && j7) fn = (const void*)k_tsvd2<8, 8, 7, 256>, kname = "k_tsvd2<8,8,7,256>";
         else if (!wide && epr <= 16 && j7) fn = (const void*)k_tsvd2<8, 16, 7, 256>, kname = "k_tsvd2<8,16,7,256>";
@@ -1314,7 +1316,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
         else if (!wide && epr <= 16) fn = (const void*)k_tsvd2<8, 16, 8, 256>, kname = "k_tsvd2<8,16,8,256>";
         else if (!wide) fn = (const void*)k_tsvd2<8, 32, 8, 256>, kname = "k_tsvd2<8,32,8,256>";
         else if (w512) fn = (const void*)k_tsvd2<8, 16, 12, 512>, kname = "k_tsvd2<8,16,12,512>";
-        else if (bn == 3) fn = (const void*)k_tsvd2<16, 16, 6, 1024>, kname = "k_tsvd2<16,16,6,1024>";
+        else if (bn == 4) fn = (const void*)k_tsvd2<16, 16, 6, 1024>, kname = "k_tsvd2<16,16,6,1024>";
         else fn = (const void*)k_tsvd2<16, 16, 8, 1024>, kname = "k_tsvd2<16,16,8,1024>";
       }
       hipFuncAttributes fa{};

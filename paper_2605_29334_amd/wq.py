@@ -48,9 +48,12 @@ class Conductivity(C.Structure):
     _fields_ = [("kind", C.c_int32), ("a", C.c_double), ("b", C.c_double)]
 
 
+TANGENT_SYMMETRIC, TANGENT_EXACT = 0, 1
+
+
 class HeatParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("theta", C.c_double), ("k", Conductivity), ("tol", C.c_double),
-                ("max_newton", C.c_int32), ("cg_rtol", C.c_double), ("max_cg", C.c_int32)]
+                ("max_newton", C.c_int32), ("cg_rtol", C.c_double), ("max_cg", C.c_int32), ("tangent", C.c_int32)]
 
 
 class HeatReport(C.Structure):
@@ -100,6 +103,7 @@ def _lib():
             "assemble_biharmonic": ([P, P, P, P, C.c_int, P], C.c_int),
             "assemble_mass_stiffness": ([P, P, P, P, P, P, C.c_int, P], C.c_int),
             "assemble_tangent": ([P, P, P, P, D, Conductivity, P, P, P, C.c_int, P], C.c_int),
+            "assemble_tangent_exact": ([P, P, P, P, D, Conductivity, P, P, P, C.c_int, P], C.c_int),
             "wq_heat_step": ([P, P, C.POINTER(HeatParams), P, P, P, P, P, P, C.POINTER(HeatReport), P], C.c_int),
             "wq_server_start": ([C.c_size_t, C.c_int32, P], C.c_int),
             "wq_server_submit": ([P, C.POINTER(Request), P, P], C.c_int),
@@ -132,7 +136,7 @@ def exported_symbols():
     return ["wq_mesh_create", "wq_mesh_destroy", "build_points", "build_points_with_s", "wq_points_destroy",
             "wq_points_size", "wq_points_info", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
             "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
-            "assemble_tangent", "wq_heat_step", "wq_server_start", "wq_server_submit", "wq_server_poll",
+            "assemble_tangent", "assemble_tangent_exact", "wq_heat_step", "wq_server_start", "wq_server_submit", "wq_server_poll",
             "wq_server_stop", "wq_batch_create", "wq_batch_build", "wq_batch_info", "wq_batch_points",
             "wq_batch_weights", "wq_batch_graph_assemble", "wq_batch_destroy", "wq_autotune_assembly",
             "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
@@ -317,8 +321,9 @@ def _vec(t, n, dtype=torch.float64):
 
 
 def assemble_tangent(points, weights, T, Tdot, inv_theta_dt, k=(K_QUADRATIC, 1.0, 1.0), f=None, S_out=None,
-                     R_out=None, stream=None):
-    """Eq. (36) tangent S (CSR values) and residual R at the fields T, Tdot."""
+                     R_out=None, stream=None, exact=False):
+    """Eq. (36) tangent S (CSR values) and residual R at the fields T, Tdot; exact=True:
+    the exact tangent of Eq. (34) (assemble_tangent_exact)."""
     n = points.n_rows
     S_out = _out(points, S_out, WQ_FP64)
     if R_out is None:
@@ -326,14 +331,15 @@ def assemble_tangent(points, weights, T, Tdot, inv_theta_dt, k=(K_QUADRATIC, 1.0
     _vec(T, n), _vec(Tdot, n), _vec(R_out, n)
     if f is not None:
         _vec(f, points.n_points)
-    _check(_lib().assemble_tangent(points.h, weights.h, _ptr(T), _ptr(Tdot), float(inv_theta_dt),
-                                   Conductivity(*k), _ptr(f), _ptr(S_out), _ptr(R_out), WQ_FP64, _stream(stream)),
-           "assemble_tangent")
+    fn = _lib().assemble_tangent_exact if exact else _lib().assemble_tangent
+    _check(fn(points.h, weights.h, _ptr(T), _ptr(Tdot), float(inv_theta_dt), Conductivity(*k), _ptr(f), _ptr(S_out),
+              _ptr(R_out), WQ_FP64, _stream(stream)), "assemble_tangent")
     return S_out, R_out
 
 
 def heat_step(points, weights, dirichlet, T, Tdot, dt, theta=1.0, k=(K_QUADRATIC, 1.0, 1.0), f=None, g=None,
-              tol=1e-10, max_newton=50, cg_rtol=1e-6, max_cg=20000, S_out=None, stream=None):
+              tol=1e-10, max_newton=50, cg_rtol=1e-6, max_cg=20000, S_out=None, stream=None,
+              tangent=TANGENT_SYMMETRIC):
     """One time step of the nonlinear heat problem (Section 5.2); T and Tdot are
     updated in place. Returns the Newton/PCG report as a dict."""
     n = points.n_rows
@@ -344,7 +350,7 @@ def heat_step(points, weights, dirichlet, T, Tdot, dt, theta=1.0, k=(K_QUADRATIC
         _vec(g, n)
     S_out = _out(points, S_out, WQ_FP64)
     hp = HeatParams(float(dt), float(theta), Conductivity(*k), float(tol), int(max_newton), float(cg_rtol),
-                    int(max_cg))
+                    int(max_cg), int(tangent))
     rep = HeatReport()
     _check(_lib().wq_heat_step(points.h, weights.h, C.byref(hp), _ptr(dirichlet), _ptr(g), _ptr(f), _ptr(T),
                                _ptr(Tdot), _ptr(S_out), C.byref(rep), _stream(stream)), "wq_heat_step")
@@ -377,12 +383,12 @@ class Server:
         self._out = {}
 
     def submit(self, fx, dirichlet, dt, n_steps, theta=1.0, k=(K_QUADRATIC, 1.0, 1.0), source=SOURCE_MANUFACTURED,
-               lam=5.0, tol=1e-10, max_newton=50, cg_rtol=1e-6, max_cg=20000):
+               lam=5.0, tol=1e-10, max_newton=50, cg_rtol=1e-6, max_cg=20000, tangent=TANGENT_SYMMETRIC):
         keep = {}
         desc = _mesh_desc(fx, keep)
         keep["dirichlet"] = np.ascontiguousarray(dirichlet, dtype=np.uint8)
         hp = HeatParams(float(dt), float(theta), Conductivity(*k), float(tol), int(max_newton), float(cg_rtol),
-                        int(max_cg))
+                        int(max_cg), int(tangent))
         req = Request(desc, C.c_void_p(keep["dirichlet"].ctypes.data), hp, int(n_steps), int(source), float(lam))
         T = np.zeros(int(fx["n_fn"]), dtype=np.float64)
         ticket = C.c_int64()

@@ -6,11 +6,15 @@
 * The captured graph reproduces the eager assembly on every replay, with eager work and
   coefficient updates between the replays.
 * The autotuner's choice only reorders the schedule of tiles: values are unchanged.
+* Two meshes of the batch (the half strip and the 2 % EP mesh) against the oracle: the
+  mass matrix with a variable coefficient end to end (oracle weights) at 1e-12, and the
+  stiffness contraction with the batch's own weights at 1e-12.
 """
 import numpy as np
 import pytest
 
 import fixtures as fx
+import oracle as O
 
 pytestmark = pytest.mark.gpu
 
@@ -107,3 +111,32 @@ def test_autotune_changes_schedule_not_values(batch):
     assert (chunk in (4, 8, 16, 32, 64, 128, 256, 512, 1024) and chunk < band or chunk == band) and ms > 0
     M1, K1 = W.assemble_mass_stiffness(P, Wt)
     assert torch.equal(M0, M1) and torch.equal(K0, K1)
+
+
+def test_batch_meshes_against_oracle(batch):
+    W, pool, B = batch
+    P, Wt = B.points, B.weights
+    x = P.get(W.ARR_X).reshape(-1, 2)
+    c, k = _coef(x, 0.2)
+    Mb, Kb = W.assemble_mass_stiffness(P, Wt, c, k)
+    Mb, Kb = _np(Mb), _np(Kb)
+    wb = {f: _np(Wt.weights(b)) for f, b in (("mass", 1), ("x", 2), ("y", 4))}
+    qp = _np(P.get(W.ARR_QPTR))
+    for m in (1, 2):
+        F = pool[m]
+        o = B.info(m)
+        r0, z0, p0, n = o["row0"], o["nnz0"], o["pt0"], o["n_rows"]
+        print(f"[gpu] batch mesh {m} against the oracle ({n} rows)", flush=True)
+        R = O.setup(F, families=("mass", "x", "y"))
+        pat, data = R["pat"], R["data"]
+        cs = _np(c[p0:p0 + o["n_points"]])
+        ks = _np(k[p0:p0 + o["n_points"]])
+        Mref = O.wq_assemble(F, pat, data, R["W"], "mass", cs)
+        q0, q1 = qp[r0], qp[r0 + n]
+        Wm = {f: v[q0:q1] for f, v in wb.items()}
+        Kref = O.wq_assemble(F, pat, data, Wm, "stiffness", ks)
+        em = float(np.abs(Mb[z0:z0 + o["nnz"]] - Mref).max() / np.abs(Mref).max())
+        ek = float(np.abs(Kb[z0:z0 + o["nnz"]] - Kref).max() / np.abs(Kref).max())
+        print(f"[gpu] batch mesh {m}: mass (oracle weights) rel err {em:.2e}, "
+              f"stiffness (batch weights) rel err {ek:.2e}", flush=True)
+        assert em < 1e-12 and ek < 1e-12

@@ -145,3 +145,57 @@ def test_newton_cap_reports_no_convergence(grid8):
     with pytest.raises(W.WQError) as e:
         _run_steps(grid8, H.K_QUADRATIC, 1.0, 1.0, 0.5, 1, max_newton=0)
     assert e.value.status == -5
+
+
+@pytest.mark.parametrize("case", ["grid8", "hs"])
+@pytest.mark.parametrize("kind,a,b", [(H.K_QUADRATIC, 1.0, 1.0), (H.K_EXP, 1.0, -1.0), (H.K_SIN, 1.0, np.pi)])
+def test_exact_tangent_parity(case, kind, a, b, request):
+    """assemble_tangent_exact (Eq. 34 with the non-symmetric term k'(T) N_j grad T . grad N_i,
+    the reading the oracle's finite-difference test pins) against the oracle's exact
+    tangent with the GPU's own weights: 1e-12 normwise; the residual is unchanged."""
+    c = request.getfixturevalue(case)
+    F, R, W, pts, wts, Wg = c["F"], c["R"], c["W"], c["pts"], c["wts"], c["Wg"]
+    pat, data = R["pat"], R["data"]
+    n = F["n_fn"]
+    rng = np.random.default_rng(23)
+    T, Td = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    x = H.points_x(data)
+    f = 1.0 + np.sin(2 * x[:, 0]) * x[:, 1]
+    k, dk = H.conductivity(kind, a, b)
+    args = (torch.tensor(T, device="cuda"), torch.tensor(Td, device="cuda"), 7.0, (kind, a, b),
+            torch.tensor(f, device="cuda"))
+    Se, Re = W.assemble_tangent(pts, wts, *args, exact=True)
+    Ss, Rs = W.assemble_tangent(pts, wts, *args)
+    So, _ = H.tangent_residual(F, pat, data, Wg, T, Td, 7.0, k, f, dk)
+    es = np.abs(_np(Se) - So).max() / np.abs(So).max()
+    print(f"[gpu] {case} k={kind}: exact tangent rel err {es:.2e}")
+    assert es < 1e-12
+    assert torch.equal(Re, Rs)
+
+
+def test_exact_tangent_heat_steps(grid8):
+    """Newton with the exact tangent: the same states as the oracle's direct-solve Newton
+    with its exact tangent (1e-8), at most the paper's 7 corrector solves per step, and
+    fewer than the symmetric tangent needs."""
+    c = grid8
+    F, R, Wg, W = c["F"], c["R"], c["Wg"], c["W"]
+    pat, data = R["pat"], R["data"]
+    n = F["n_fn"]
+    x = H.points_x(data)
+    kind, a, b = H.K_QUADRATIC, 1.0, 1.0
+    k, dk = H.conductivity(kind, a, b)
+    _, f = H.manufactured(kind, a, b)
+    dirichlet = F["dir1"].astype(bool)
+    exact = _run_steps(c, kind, a, b, 0.5, 3, cg_rtol=1e-12, tangent=W.TANGENT_EXACT)
+    sym = _run_steps(c, kind, a, b, 0.5, 3, cg_rtol=1e-12)
+    T, Td = np.zeros(n), np.zeros(n)
+    for s in range(3):
+        T, Td, it, norms = H.heat_step(F, pat, data, Wg, T, Td, 0.5, 1.0, k, f(x, 0.5 * (s + 1)), dirichlet,
+                                       np.zeros(n), dkfun=dk)
+        Tg, _, rep = exact[s]
+        dT = np.abs(Tg - T).max() / np.abs(T).max()
+        print(f"[gpu] step {s}: exact-tangent newton gpu {rep['newton_iters']} oracle {it} "
+              f"(symmetric {sym[s][2]['newton_iters']}), |R| {rep['residual']:.2e}, T rel diff {dT:.2e}")
+        assert rep["residual"] <= 1e-10 and dT < 1e-8
+        assert abs(rep["newton_iters"] - it) <= 1 and rep["newton_iters"] <= 7
+        assert rep["newton_iters"] < sym[s][2]["newton_iters"]

@@ -1,13 +1,14 @@
 """Low-precision assembly on MFMA against the FP64 oracle evaluated with the GPU's weights.
 
 Target: normwise relative error <= 1e-6 per matrix (max |A - A*| / max |A*|).
+* Sliced FP16 (four 10-bit slices per operand on a shared grid, exact MFMA sums,
+  about 40 bits) meets 1e-6 on every matrix: test_sliced_fp16_within_1e6.
 * FP16 x 2 (22-bit operands, power-of-two scaling) and BF16 x 3 (24-bit operands) sum the
   products of a cell in FP32, so their error is about 2^-24 times the sum of |terms|;
-  it meets 1e-6 where the contraction does not cancel (mass, biharmonic here) and is
-  bounded by 8 * 2^-24 * (cancellation factor) otherwise (stiffness: the derivative-
-  family weights oscillate; the factor max_ij sum_q |terms| / max |K| is computed here).
-* Sliced FP16 (four 10-bit slices per operand on a shared grid, exact MFMA sums,
-  about 40 bits) meets 1e-6 on every matrix.
+  they meet 1e-6 where the contraction does not cancel (mass, biharmonic here) and
+  otherwise only the bound 8 * 2^-24 * (cancellation factor) (stiffness: the derivative-
+  family weights oscillate; the factor max_ij sum_q |terms| / max |K| is computed here):
+  test_split_hi_lo_within_fp32_cancellation_bound.
 """
 import numpy as np
 import pytest
@@ -86,10 +87,9 @@ def _cancellation(F, R, Wg, kind, coef):
     return tmax / vmax
 
 
-@pytest.mark.parametrize("case", ["grid12", "eps32", "hs"])
-@pytest.mark.parametrize("prec", [1, 2, 3])
-def test_split_precision_within_1e6(case, prec, request):
-    cs = request.getfixturevalue(case)
+def _errors(cs, prec):
+    """Normwise error of each low-precision matrix against the oracle's contraction with
+    the GPU's own weights, and the cancellation factor of each matrix."""
     F, R, W, pts, wts, Wg = cs["F"], cs["R"], cs["W"], cs["pts"], cs["wts"], cs["Wg"]
     pat, data = R["pat"], R["data"]
     c, k = cs["c"], cs["k"]
@@ -103,17 +103,45 @@ def test_split_precision_within_1e6(case, prec, request):
         ref["B"] = O.wq_assemble(F, pat, data, Wg, "biharmonic", k)
         got["B"] = _np(W.assemble_biharmonic(pts, wts, tk, prec=prec))
     errs = {key: _rel(got[key], ref[key]) for key in ref}
-    name = {1: "fp16x2", 2: "bf16x3", 3: "sliced"}[prec]
     canc = {"M": _cancellation(F, R, Wg, "mass", c), "K": _cancellation(F, R, Wg, "stiffness", k)}
     if cs["lap"]:
         canc["B"] = _cancellation(F, R, Wg, "biharmonic", k)
-    print(f"[gpu] {case} {name} rel err per matrix: " + ", ".join(f"{k_}={v:.2e}" for k_, v in errs.items())
-          + "; cancellation factors " + ", ".join(f"{k_}={v:.1f}" for k_, v in canc.items()))
-    for key, v in errs.items():
-        bound = 1e-6 if prec == 3 else max(1e-6, 8 * 2.0 ** -24 * canc[key[0]])
-        assert v <= bound, (key, v, bound)
     # fused and single-matrix kernels compute the same products in the same order
     assert np.array_equal(got["M"], got["M_fused"]) and np.array_equal(got["K"], got["K_fused"])
+    return errs, canc
+
+
+def _report(case, prec, errs, canc):
+    name = {1: "fp16x2", 2: "bf16x3", 3: "sliced"}[prec]
+    print(f"[gpu] {case} {name} rel err per matrix: " + ", ".join(f"{k_}={v:.2e}" for k_, v in errs.items())
+          + "; cancellation factors " + ", ".join(f"{k_}={v:.1f}" for k_, v in canc.items()))
+
+
+@pytest.mark.parametrize("case", ["grid12", "eps32", "hs"])
+def test_sliced_fp16_within_1e6(case, request):
+    """The sliced form (exact MFMA sums, about 40 bits) meets 1e-6 on every matrix."""
+    cs = request.getfixturevalue(case)
+    errs, canc = _errors(cs, 3)
+    _report(case, 3, errs, canc)
+    for key, v in errs.items():
+        assert v <= 1e-6, (key, v)
+
+
+@pytest.mark.parametrize("case", ["grid12", "eps32", "hs"])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_split_hi_lo_within_fp32_cancellation_bound(case, prec, request):
+    """FP16 x 2 and BF16 x 3 accumulate in FP32, so their error is about 2^-24 times the
+    sum of |terms|: the bound is 8 * 2^-24 * C per matrix, with C the cancellation factor
+    (max_ij sum_q |terms| / max |A|). This meets 1e-6 only where C is small (mass, and
+    biharmonic here); on stiffness rows C is in the hundreds to thousands and these two
+    forms miss 1e-6 (the sliced form is the one that meets it)."""
+    cs = request.getfixturevalue(case)
+    errs, canc = _errors(cs, prec)
+    _report(case, prec, errs, canc)
+    for key, v in errs.items():
+        bound = max(1e-6, 8 * 2.0 ** -24 * canc[key[0]])
+        assert v <= bound, (key, v, bound)
+    assert errs["M"] <= 1e-6
 
 
 def test_split_precision_deterministic(eps32):

@@ -66,15 +66,10 @@ def test_tangent_against_finite_differences(setup, kind, a, b):
     f = np.sin(3 * x[:, 0])
     Sv, _ = _residual_of_T(F, S, T, T_n, inv, k, f)
     Sm = O.csr(pat, Sv, n).toarray()
-    # non-symmetric term (Eq. 34, READING): N_AB = sum_q k'(T_q) N_B(x_q) (wx_Aq Tx_q + wy_Aq Ty_q)
-    Tq, Tx, Ty = H.point_field(data, T)
-    Nm = np.zeros((n, n))
-    for i in range(n):
-        q0, q1 = pat["qptr"][i], pat["qptr"][i + 1]
-        Q = pat["qidx"][q0:q1]
-        g = dk(Tq[Q]) * (W["x"][q0:q1] * Tx[Q] + W["y"][q0:q1] * Ty[Q])
-        A0 = O.local_matrix(F, pat, data, i, "N")
-        Nm[i, pat["S"][i]] = A0 @ g
+    # exact tangent of the oracle (Eq. 34, READING): S + the non-symmetric term
+    # sum_q k'(T_q) N_B(x_q) (wx_Aq Tx_q + wy_Aq Ty_q)
+    Se, _ = H.tangent_residual(F, pat, data, W, T, (T - T_n) * inv, inv, k, f, dk)
+    Nm = O.csr(pat, Se, n).toarray() - Sm
     h = 1e-6
     rng = np.random.default_rng(9)
     for B in rng.choice(n, 6, replace=False):
@@ -141,3 +136,36 @@ def test_nonlinear_newton_and_manufactured_solution():
         errs.append(np.sqrt(np.sum(wq * e * e)))
         assert abs(M.sum() - 1.0) < 1e-12
     assert errs[1] < 0.5 * errs[0], errs
+
+
+def test_exact_tangent_newton_converges_quadratically():
+    """With the exact tangent (Eq. 34, the non-symmetric term k'(T) N_B grad T . grad N_A
+    kept), Newton converges quadratically: each step needs at most the paper's 7
+    corrector solves (Section 6.3) where the symmetric tangent of Eq. (35) needs more,
+    and once the residual is small it is roughly squared per iteration."""
+    F = fxm.fixture_grid(8, displace=0.05, seed=11)
+    S = O.setup(F, families=("mass", "x", "y"))
+    pat, data, W = S["pat"], S["data"], S["W"]
+    n = F["n_fn"]
+    k, dk = H.conductivity(H.K_QUADRATIC, 1.0, 1.0)
+    _, f = H.manufactured(H.K_QUADRATIC, 1.0, 1.0)
+    x = H.points_x(data)
+    dirichlet = F["dir1"].astype(bool)
+    runs = {}
+    for name, d in (("symmetric", None), ("exact", dk)):
+        T, Td = np.zeros(n), np.zeros(n)
+        its, last = [], None
+        for step in range(3):
+            t1 = 0.5 * (step + 1)
+            T, Td, it, norms = H.heat_step(F, pat, data, W, T, Td, 0.5, 1.0, k, f(x, t1), dirichlet, np.zeros(n),
+                                           dkfun=d)
+            assert norms[-1] <= 1e-10, norms
+            its.append(it)
+            last = norms
+        runs[name] = (its, T, last)
+    assert max(runs["exact"][0]) <= 7 and sum(runs["exact"][0]) < sum(runs["symmetric"][0]), runs
+    # both iterations solve the same discrete problem
+    assert np.abs(runs["exact"][1] - runs["symmetric"][1]).max() < 1e-8
+    nm = runs["exact"][2]
+    small = [(a, b) for a, b in zip(nm, nm[1:]) if a < 1e-3]
+    assert small and all(b <= 10.0 * a * a + 1e-12 for a, b in small), nm
