@@ -221,6 +221,20 @@ wq_status assemble_tangent_exact(const wq_points* pts, const wq_weights* w, cons
                                  double inv_theta_dt, wq_conductivity k, const double* f_at_pts, void* S_vals,
                                  double* R, wq_precision prec, wq_stream stream);
 
+/* assemble_tangent_noalloc: assemble_tangent for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments, kernels and results (bit for bit) as assemble_tangent; the
+ * point fields live in a fixed array of the library, one per GPU (16 MiB: 4 doubles per
+ * point for at most 524288 points), instead of scratch owned by `pts`. It calls no
+ * hipMalloc, hipFree or other allocating routine. Errors: WQ_EINVAL if the handle has more
+ * than 524288 points, or if its device is not the current device. All calls on one GPU
+ * share the array and it keeps the last call's contents (each call overwrites all of the
+ * part it reads): calls that overlap on one GPU (other streams or threads) race, and the
+ * caller must serialise them. Asynchronous on `stream`. */
+wq_status assemble_tangent_noalloc(const wq_points* pts, const wq_weights* w, const double* T, const double* Tdot,
+                                   double inv_theta_dt, wq_conductivity k, const double* f_at_pts, void* S_vals,
+                                   double* R, wq_precision prec, wq_stream stream);
+
 /* wq_heat_step: one time step t_n -> t_{n+1} (Section 5.2). Predictor
  * T = T_n + (1 - theta) dt Tdot_n with T = g on prescribed DOFs; corrector iterations:
  * Tdot = (T - T_n - (1 - theta) dt Tdot_n) / (theta dt), S and R by assemble_tangent,

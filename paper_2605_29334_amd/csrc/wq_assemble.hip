@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 using namespace wq;
 
@@ -912,6 +913,12 @@ extern "C" wq_status assemble_mass_stiffness(const wq_points* P, const wq_weight
   return dispatch<3>(P, w, c, k, mv, kv, prec, (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------------ no-allocation scratch
+// Point fields of assemble_tangent_noalloc (4 x n_points doubles): a fixed array, one copy
+// per GPU, held until the process ends and shared by every call on that GPU.
+constexpr int64_t NOALLOC_MAX_POINTS = int64_t(1) << 19;
+static __device__ __align__(256) double scratch[4 * NOALLOC_MAX_POINTS];
+
 namespace {
 
 // Eq. (36) tangent and residual with the point fields (k_q and the three residual terms,
@@ -958,6 +965,32 @@ wq_status tangent_check(const wq_points* P, const wq_weights* w, const double* T
   return WQ_OK;
 }
 
+// ------------------------------------------------------------------ no-allocation tangent
+// Host code never passes `scratch` itself to a kernel (on the host the name stands for a
+// host-side stand-in, not device memory): its device address is looked up once per device
+// with hipGetSymbolAddress and kept.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call there).
+wq_status scratch_on_current_device(int want_device, double** out) {
+  int dev = -1;
+  WQ_HIP(hipGetDevice(&dev));
+  WQ_CHECK(dev == want_device, WQ_EINVAL,
+           "assemble_tangent_noalloc: the handle's device must be the current device");
+  WQ_CHECK(dev >= 0 && dev < MAX_DEVICES, WQ_EINVAL, "assemble_tangent_noalloc: device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    WQ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    WQ_CHECK(p != nullptr, WQ_EDEVICE, "assemble_tangent_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return WQ_OK;
+}
+
 }  // namespace
 
 extern "C" wq_status assemble_tangent(const wq_points* P, const wq_weights* w, const double* T, const double* Tdot,
@@ -981,4 +1014,16 @@ extern "C" wq_status assemble_tangent_exact(const wq_points* P, const wq_weights
     WQ_TRY(dalloc_n<double>(Pm->tangent_ws, 6 * (size_t)P->n_points));
   return tangent_impl(P, w, T, Tdot, inv_theta_dt, k, f_at_pts, S_vals, R, Pm->tangent_ws.as<double>(),
                       (hipStream_t)stream, true, true);
+}
+
+extern "C" wq_status assemble_tangent_noalloc(const wq_points* P, const wq_weights* w, const double* T,
+                                              const double* Tdot, double inv_theta_dt, wq_conductivity k,
+                                              const double* f_at_pts, void* S_vals, double* R, wq_precision prec,
+                                              wq_stream stream) {
+  WQ_TRY(tangent_check(P, w, T, Tdot, inv_theta_dt, k, S_vals, R, prec));
+  WQ_CHECK(P->n_points <= NOALLOC_MAX_POINTS, WQ_EINVAL,
+           "assemble_tangent_noalloc: more points than the fixed scratch holds (524288)");
+  double* ws = nullptr;
+  WQ_TRY(scratch_on_current_device(P->mesh->device, &ws));
+  return tangent_impl(P, w, T, Tdot, inv_theta_dt, k, f_at_pts, S_vals, R, ws, (hipStream_t)stream, false);
 }

@@ -103,6 +103,7 @@ def _lib():
             "assemble_biharmonic": ([P, P, P, P, C.c_int, P], C.c_int),
             "assemble_mass_stiffness": ([P, P, P, P, P, P, C.c_int, P], C.c_int),
             "assemble_tangent": ([P, P, P, P, D, Conductivity, P, P, P, C.c_int, P], C.c_int),
+            "assemble_tangent_noalloc": ([P, P, P, P, D, Conductivity, P, P, P, C.c_int, P], C.c_int),
             "assemble_tangent_exact": ([P, P, P, P, D, Conductivity, P, P, P, C.c_int, P], C.c_int),
             "wq_heat_step": ([P, P, C.POINTER(HeatParams), P, P, P, P, P, P, C.POINTER(HeatReport), P], C.c_int),
             "wq_server_start": ([C.c_size_t, C.c_int32, P], C.c_int),
@@ -136,7 +137,7 @@ def exported_symbols():
     return ["wq_mesh_create", "wq_mesh_destroy", "build_points", "build_points_with_s", "wq_points_destroy",
             "wq_points_size", "wq_points_info", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
             "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
-            "assemble_tangent", "assemble_tangent_exact", "wq_heat_step", "wq_server_start", "wq_server_submit", "wq_server_poll",
+            "assemble_tangent", "assemble_tangent_noalloc", "assemble_tangent_exact", "wq_heat_step", "wq_server_start", "wq_server_submit", "wq_server_poll",
             "wq_server_stop", "wq_batch_create", "wq_batch_build", "wq_batch_info", "wq_batch_points",
             "wq_batch_weights", "wq_batch_graph_assemble", "wq_batch_destroy", "wq_autotune_assembly",
             "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
@@ -334,6 +335,22 @@ def assemble_tangent(points, weights, T, Tdot, inv_theta_dt, k=(K_QUADRATIC, 1.0
     fn = _lib().assemble_tangent_exact if exact else _lib().assemble_tangent
     _check(fn(points.h, weights.h, _ptr(T), _ptr(Tdot), float(inv_theta_dt), Conductivity(*k), _ptr(f), _ptr(S_out),
               _ptr(R_out), WQ_FP64, _stream(stream)), "assemble_tangent")
+    return S_out, R_out
+
+
+def assemble_tangent_noalloc(points, weights, T, Tdot, inv_theta_dt, k=(K_QUADRATIC, 1.0, 1.0), f=None,
+                             S_out=None, R_out=None, stream=None):
+    """assemble_tangent through the entry point that allocates no device memory (its point
+    fields sit in the library's fixed per-GPU array). S_out and R_out must be given."""
+    n = points.n_rows
+    assert S_out is not None and R_out is not None, "the caller provides the outputs"
+    _vec(T, n), _vec(Tdot, n), _vec(R_out, n), _vec(S_out, points.nnz)
+    if f is not None:
+        _vec(f, points.n_points)
+    _check(_lib().assemble_tangent_noalloc(points.h, weights.h, _ptr(T), _ptr(Tdot), float(inv_theta_dt),
+                                           Conductivity(*k), _ptr(f), _ptr(S_out), _ptr(R_out), WQ_FP64,
+                                           _stream(stream)),
+           "assemble_tangent_noalloc")
     return S_out, R_out
 
 
