@@ -296,7 +296,8 @@ wq_status wq_heat_step(const wq_points* pts, const wq_weights* w, const wq_heat_
  * part computed once per fixed domain, Section 2) stay on the device, still charged to
  * the budget at the request's estimate. A later request whose mesh arrays are identical
  * takes an idle one over (one request at a time) and skips that work; a request that
- * needs room releases idle setups, least recently used first. */
+ * needs room releases idle setups, least recently used first. Requests with
+ * reuse_setup = 0 neither take over nor leave a setup. */
 typedef struct wq_server wq_server;
 typedef enum { WQ_SOURCE_NONE = 0, WQ_SOURCE_MANUFACTURED = 1 } wq_source;
 typedef struct {
@@ -306,6 +307,9 @@ typedef struct {
   int32_t n_steps;
   int32_t source;             /* wq_source                                               */
   double lambda;              /* manufactured source rate                                */
+  int32_t reuse_setup;        /* 1: may take over a held setup of an identical domain and
+                                 leave its own setup held; 0: set up from scratch and
+                                 release it at completion                                */
 } wq_request;
 typedef struct {
   int32_t status;             /* wq_status of the whole request                          */
@@ -366,7 +370,7 @@ wq_status wq_autotune_assembly(wq_points* pts, const wq_weights* w, wq_stream st
  * recorded events, copies up to `cap` records into `out` (host) and clears the list;
  * it returns the number of records written. `name` is the kernel (TSVD: its template
  * instance). `work` is the launch's algorithmic work: for TSVD the FLOPs
- * sum(6 r n^2 - 2 n^3) over its systems, for assembly the bytes 8 * (every basis value
+ * sum(9 r n^2 - n^3) over its systems, for assembly the bytes 8 * (every basis value
  * and weight read once + coefficients + outputs), otherwise the unit count (points,
  * rows). */
 typedef struct {

@@ -382,6 +382,45 @@ def gq_matrices(fx, cl, coef=None):
     return {k: sp.csr_matrix((np.concatenate(v), (R, Cc)), shape=(n, n)) for k, v in V.items()}
 
 
+def gauss_data(fx, cl):
+    """Basis at the 4x4 Gauss points of every Bezier cell, computed ahead (the paper times
+    formation and assembly with basis evaluation excluded, Section 6.1): per cell the
+    functions, N, dN/dx, dN/dy (16 x m), the points x and the weights g_a g_b |detJ|."""
+    gp, gw = gauss4()
+    out = []
+    for c in range(len(cl["elem"])):
+        f, k = int(cl["elem"][c]), int(cl["sub"][c])
+        rows = [eval_cell(fx, f, k, (gp[aq], gp[bq]), cl["funcs"][c]) for bq in range(4) for aq in range(4)]
+        wts = np.array([gw[aq] * gw[bq] for bq in range(4) for aq in range(4)])
+        out.append({"fn": cl["funcs"][c], "N": np.array([r[1] for r in rows]), "Nx": np.array([r[2] for r in rows]),
+                    "Ny": np.array([r[3] for r in rows]), "x": np.array([r[5] for r in rows]),
+                    "w": wts * np.abs(np.array([r[6] for r in rows]))})
+    return out
+
+
+def gq_assemble(fx, gdata, kind, coef=None):
+    """Element-wise Gauss formation and assembly with the basis given (gauss_data): per
+    cell and Gauss point the outer product of the basis values, weighted, added into the
+    global matrix; 'mass' (int c N_i N_j) or 'stiffness' (int k grad N_i . grad N_j).
+    coef(x) or None for 1. Returns a scipy CSR matrix."""
+    n = fx["n_fn"]
+    R, Cc, V = [], [], []
+    for d in gdata:
+        m = len(d["fn"])
+        wq = d["w"] if coef is None else d["w"] * coef(d["x"])
+        E = np.zeros((m, m))
+        for g in range(len(wq)):
+            if kind == "mass":
+                E += wq[g] * np.outer(d["N"][g], d["N"][g])
+            else:
+                E += wq[g] * (np.outer(d["Nx"][g], d["Nx"][g]) + np.outer(d["Ny"][g], d["Ny"][g]))
+        ii, jj = np.meshgrid(d["fn"], d["fn"], indexing="ij")
+        R.append(ii.reshape(-1))
+        Cc.append(jj.reshape(-1))
+        V.append(E.reshape(-1))
+    return sp.csr_matrix((np.concatenate(V), (np.concatenate(R), np.concatenate(Cc))), shape=(n, n))
+
+
 # ----------------------------------------------------------------------------------
 # O6  Weights by truncated SVD (Section 4.3, Eqs. (19)-(22); Section 2 Eqs. (5)-(6))
 # ----------------------------------------------------------------------------------
@@ -534,9 +573,9 @@ def row_gauss_rhs(fx, cl, supp_i, S_i, i, fam, cache):
 
 def sample_rows(fx, rows, families=("mass", "x", "y"), tau=1e-12, coef=None, glob=None):
     """Everything the method produces for the given rows: S_i, Q_i, the points' coordinates
-    x, the system of each family (A_fam, b_fam, z) with its weights, and mass / stiffness
-    rows (coef: dict
-    kind -> callable of x, or None for 1).
+    x, the system of each family (A_fam, b_fam, z) with its weights, and the mass,
+    stiffness and biharmonic rows of the families given (coef: dict kind -> callable of
+    x, or None for 1).
     glob: optional precomputed {"cls", "s", "cells"} of the whole mesh."""
     if glob is None:
         cls = classify(fx)
@@ -585,5 +624,8 @@ def sample_rows(fx, rows, families=("mass", "x", "y"), tau=1e-12, coef=None, glo
         if "x" in families and "y" in families:
             res["K"] = (local_matrix(fx, pat, data, i, "Nx") @ (ck * res["W"]["x"])
                         + local_matrix(fx, pat, data, i, "Ny") @ (ck * res["W"]["y"]))
+        if "lap" in families:
+            cb = np.ones(len(q)) if coef is None or "biharmonic" not in coef else coef["biharmonic"](x)
+            res["B"] = local_matrix(fx, pat, data, i, "Lap") @ (cb * res["W"]["lap"])
         out[i] = res
     return out, glob

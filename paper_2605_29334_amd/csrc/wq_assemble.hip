@@ -192,8 +192,8 @@ __device__ inline void fetch(const Step& s, uint32_t qoff, const Lane& L, const 
   const bool wv = mem && q < np;
   const uint32_t offW = wv ? (qoff + (uint32_t)q) * 8u : OOB;
   const uint32_t offC = wv ? (pt0 + (uint32_t)q) * 8u : OOB;
-  const int kb = 16 * s.cb + L.g, mpad = (m + 15) & ~15;
-  const uint32_t offS = (mem && kb < m) ? (uint32_t)(__popc(mask & L.lowmask) * mpad + 16 * s.cb + 4 * L.g) : OOB;
+  const int mpad = (m + 15) & ~15;
+  const uint32_t offS = mem ? (uint32_t)(__popc(mask & L.lowmask) * mpad + 16 * s.cb + 4 * L.g) : OOB;
 #pragma unroll
   for (int a = 0; a < N; ++a) o.d[a] = bload64s(B.D[a], offD, sD);
 #pragma unroll
@@ -228,10 +228,11 @@ __device__ inline void mfma_step(const double (&da)[Fam<K>::N], const double (&w
 }
 
 // Add the lane's four products (functions kb, kb + 4, kb + 8, kb + 12 of its row) to the
-// row's CSR slots (four slot bytes in sl).
+// row's CSR slots (four slot bytes in sl). Products of positions past the cell's functions
+// are exact zeros (their basis operand is zero) and their slot bytes name some slot of the
+// row, so member lanes add all four without a per-function test.
 template <int NACC>
-__device__ inline void scatter(const d4& c0, const d4& c1, uint32_t sl, bool mem, int kb, int m, int ro, double* acc,
-                               int nzcap) {
+__device__ inline void scatter(const d4& c0, const d4& c1, uint32_t sl, bool mem, int ro, double* acc, int nzcap) {
   // The products are moved to ordinary registers before the LDS adds read them: an LDS
   // instruction that read the MFMA's accumulation registers directly was scheduled too
   // soon after the FP64 MFMA on gfx950 and read unfinished sums (the register copies get
@@ -246,14 +247,12 @@ __device__ inline void scatter(const d4& c0, const d4& c1, uint32_t sl, bool mem
       asm volatile("" : "+v"(p1[v]));
     }
   }
-  if (mem && kb < m) {
+  if (mem) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      if (kb + 4 * v < m) {
-        const int at = ro + (int)((sl >> (8 * v)) & 0xffu);
-        __hip_atomic_fetch_add(acc + at, p0[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        if (NACC == 2) __hip_atomic_fetch_add(acc + nzcap + at, p1[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      }
+      const int at = ro + (int)((sl >> (8 * v)) & 0xffu);
+      __hip_atomic_fetch_add(acc + at, p0[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      if (NACC == 2) __hip_atomic_fetch_add(acc + nzcap + at, p1[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
   }
 }
@@ -277,8 +276,7 @@ __device__ inline void compute(const Step& s, const Ops<K>& o, const Lane& L, in
   mfma_step<K>(o.d, wb, c0, c1);
   const unsigned mask = (unsigned)s.E.z & 0xffffu;
   const bool mem = (mask >> L.r) & 1u;
-  if (s.fast) scatter<Fam<K>::NACC>(c0, c1, o.sl, mem, L.g, 16, L.ro, acc, nzcap);
-  else scatter<Fam<K>::NACC>(c0, c1, o.sl, mem, 16 * s.cb + L.g, st_m(s), L.ro, acc, nzcap);
+  scatter<Fam<K>::NACC>(c0, c1, o.sl, mem, L.ro, acc, nzcap);
 }
 
 template <int K>

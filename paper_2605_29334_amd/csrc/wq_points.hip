@@ -543,7 +543,8 @@ __global__ void k_tile_entries(int64_t n, const int64_t* sptr, const int32_t* sc
 // FILL == true: write one entry per cell and copy its member rows' slot maps behind the
 // tile's earlier ones (row order; each map padded to whole blocks of 16 functions and
 // stored in the order the assembly's lanes read it: byte 16 cb + 4 g + v of a map holds the
-// slot of function 16 cb + g + 4 v).
+// slot of function 16 cb + g + 4 v, and for positions past the cell's m functions some
+// slot of the row, where only zero products land).
 template <bool FILL>
 __global__ void k_tile2_entries(int64_t n_tiles, const int32_t* row0, const int64_t* sptr, const int32_t* scell,
                                 const int64_t* cfn_ptr, const int64_t* cell_pt_off, const int64_t* dptr,
@@ -578,7 +579,9 @@ __global__ void k_tile2_entries(int64_t n_tiles, const int32_t* row0, const int6
           const int64_t so = soff[pos[r]];
           for (int t = 0; t < mpad; ++t) {
             const int k = (t & ~15) + ((t >> 2) & 3) + 4 * (t & 3);
-            tslot[sb + t] = k < m ? slot[so + k] : (uint8_t)0;
+            // a position past the cell's functions gets some slot of the row: the kernel
+            // adds zero products there (no per-function predicate)
+            tslot[sb + t] = slot[so + (k < m ? k : k % m)];
           }
         }
         sb += mpad;

@@ -82,6 +82,7 @@ struct Request {
   wq_heat_params heat{};
   int32_t n_steps = 0, source = 0;
   double lambda = 0;
+  bool reuse = true;  // may take over a held setup of its domain and leave its own held
   double* T_out = nullptr;
   size_t est = 0;
   wq_result res{};
@@ -183,7 +184,7 @@ wq_status run_request(Request* r, hipStream_t st, Setup** built) {
   dfree(f);
   *built = nullptr;
   if (!r->setup) {
-    if (s == WQ_OK) {
+    if (s == WQ_OK && r->reuse) {
       Setup* h = new Setup();
       h->face_vtx = r->face_vtx;
       h->ext_fn = r->ext_fn;
@@ -220,6 +221,7 @@ void worker(wq_server* sv) {
       // is held, or its estimate fits once idle setups are released (least recently used
       // first)
       auto idle_match = [&](const Request& q) -> Setup* {
+        if (!q.reuse) return nullptr;
         for (Setup* h : sv->setups)
           if (!h->busy && same_domain(*h, q)) return h;
         return nullptr;
@@ -325,6 +327,7 @@ extern "C" wq_status wq_server_submit(wq_server* sv, const wq_request* q, double
   r->n_steps = q->n_steps;
   r->source = q->source;
   r->lambda = q->lambda;
+  r->reuse = q->reuse_setup != 0;
   r->T_out = T_out;
   r->est = hbm_estimate(d);
   r->res.hbm_estimate = r->est;

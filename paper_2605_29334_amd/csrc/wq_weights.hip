@@ -178,9 +178,12 @@ __constant__ int c_nb[6] = {32, 48, 56, 64, 96, 128};
 __constant__ int c_rb[7] = {64, 80, 96, 128, 160, 192, 256};
 constexpr int NB_N = 6, NB_R = 7, NBKT = NB_N * NB_R;
 
-// Also sums, per bucket, the algorithmic FLOPs of its systems, 6 r n^2 - 2 n^3: one
-// bidiagonalisation of the r x n matrix (4 r n^2 - 4 n^3 / 3) plus the QR of Z V_t at
-// full rank (2 r n^2 - 2 n^3 / 3); the measure of useful work for the roofline.
+// Also sums, per bucket, the algorithmic FLOPs of its systems, 9 r n^2 - n^3: the work of a
+// thin SVD of the n x r system by Golub-Kahan bidiagonalisation (4 r n^2 - 4 n^3 / 3), the
+// formation of its left and right singular vectors (4 n^3 / 3 and 4 r n^2 - 4 n^3 / 3), the
+// r x t Gram matrix of Z V_t (r t^2) and its Cholesky factor (t^3 / 3), at full rank
+// t = n: the method's lower bound, the measure of useful work for the roofline (about
+// 1.27 MFLOP for the 49 x 64 systems of regular rows).
 __global__ void k_sys_bucket(int64_t n, const int64_t* row_ptr, const int64_t* qptr, uint8_t* bkt, int* hist,
                              int* bad, unsigned long long* flops) {
   // per-workgroup tallies in LDS, then one global update per touched bucket
@@ -211,7 +214,7 @@ __global__ void k_sys_bucket(int64_t n, const int64_t* row_ptr, const int64_t* q
     atomicMax(&mxn[b], ni);  // per-bucket maxima (LDS sizing)
     atomicMax(&mxr[b], ri);
     const long long nn = ni, rr = ri;
-    atomicAdd(&fl[b], (unsigned long long)(6 * rr * nn * nn - 2 * nn * nn * nn));
+    atomicAdd(&fl[b], (unsigned long long)(9 * rr * nn * nn - nn * nn * nn));
   }
   __syncthreads();
   for (int b = threadIdx.x; b < NBKT; b += blockDim.x)

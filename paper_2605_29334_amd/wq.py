@@ -67,7 +67,7 @@ SOURCE_NONE, SOURCE_MANUFACTURED = 0, 1
 
 class Request(C.Structure):
     _fields_ = [("mesh", MeshDesc), ("dirichlet", C.c_void_p), ("heat", HeatParams), ("n_steps", C.c_int32),
-                ("source", C.c_int32), ("lam", C.c_double)]
+                ("source", C.c_int32), ("lam", C.c_double), ("reuse_setup", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -400,13 +400,15 @@ class Server:
         self._out = {}
 
     def submit(self, fx, dirichlet, dt, n_steps, theta=1.0, k=(K_QUADRATIC, 1.0, 1.0), source=SOURCE_MANUFACTURED,
-               lam=5.0, tol=1e-10, max_newton=50, cg_rtol=1e-6, max_cg=20000, tangent=TANGENT_SYMMETRIC):
+               lam=5.0, tol=1e-10, max_newton=50, cg_rtol=1e-6, max_cg=20000, tangent=TANGENT_SYMMETRIC,
+               reuse_setup=True):
         keep = {}
         desc = _mesh_desc(fx, keep)
         keep["dirichlet"] = np.ascontiguousarray(dirichlet, dtype=np.uint8)
         hp = HeatParams(float(dt), float(theta), Conductivity(*k), float(tol), int(max_newton), float(cg_rtol),
                         int(max_cg), int(tangent))
-        req = Request(desc, C.c_void_p(keep["dirichlet"].ctypes.data), hp, int(n_steps), int(source), float(lam))
+        req = Request(desc, C.c_void_p(keep["dirichlet"].ctypes.data), hp, int(n_steps), int(source), float(lam),
+                      1 if reuse_setup else 0)
         T = np.zeros(int(fx["n_fn"]), dtype=np.float64)
         ticket = C.c_int64()
         _check(_lib().wq_server_submit(self.h, C.byref(req), C.c_void_p(T.ctypes.data), C.byref(ticket)),

@@ -151,3 +151,22 @@ def test_idle_setup_is_released_when_room_is_needed(pool):
     assert [r["status"] for r in (r1, r2, r3)] == [0, 0, 0]
     assert [r["setup_reused"] for r in (r1, r2, r3)] == [0, 0, 0]
     assert np.array_equal(Ta1, Ta2)
+
+
+def test_requests_without_setup_reuse(pool):
+    """reuse_setup = 0: the same domain is set up again from scratch (nothing held,
+    nothing taken over) with bit-identical results; the exact tangent is served too and
+    takes fewer Newton iterations than the symmetric one on the same request."""
+    W = _wq()
+    F = pool[3]
+    S = W.Server(8 << 30, 1)
+    T1, r1 = S.poll(S.submit(F, F["dir1"], 0.3, 2, k=KINDS[0], reuse_setup=False))
+    T2, r2 = S.poll(S.submit(F, F["dir1"], 0.3, 2, k=KINDS[0], reuse_setup=False))
+    T3, r3 = S.poll(S.submit(F, F["dir1"], 0.3, 2, k=KINDS[0], reuse_setup=False, tangent=W.TANGENT_EXACT))
+    S.close()
+    assert [r["status"] for r in (r1, r2, r3)] == [0, 0, 0]
+    assert [r["setup_reused"] for r in (r1, r2, r3)] == [0, 0, 0]
+    assert np.array_equal(T1, T2)
+    print(f"[gpu] served Newton iterations: symmetric {r1['newton_iters']}, exact {r3['newton_iters']}")
+    assert r3["newton_iters"] < r1["newton_iters"]
+    assert np.abs(T3 - T1).max() <= 1e-8 * np.abs(T1).max()

@@ -382,3 +382,17 @@ def test_p11_poisson_l2_rate_four():
     hs_ = [1.0 / (N - 2) for N in Ns]
     rate = np.polyfit(np.log(hs_), np.log(errs), 1)[0]
     assert rate > 3.6, (errs, rate)
+
+
+def test_gq_assemble_with_given_basis_matches_gq_matrices(hs):
+    """The element-wise Gauss assembly with the basis computed ahead (used to time Gauss
+    formation against WQ formation, Section 6.1) equals gq_matrices term by term."""
+    F, R = hs
+    cl = R["cells"]
+    gd = O.gauss_data(F, cl)
+    coef = lambda x: 1.0 + 0.5 * np.sin(2 * np.pi * x[..., 0]) * np.sin(2 * np.pi * x[..., 1])  # noqa: E731
+    ref = O.gq_matrices(F, cl, coef=coef)
+    M = O.gq_assemble(F, gd, "mass", coef)
+    K = O.gq_assemble(F, gd, "stiffness", coef)
+    assert abs(M - ref["M"]).max() <= 1e-15 * abs(ref["M"]).max()
+    assert abs(K - (ref["Kx"] + ref["Ky"])).max() <= 1e-14 * abs(ref["Kx"] + ref["Ky"]).max()
