@@ -458,7 +458,7 @@ __device__ inline double qr_update(double* G, int ld, int r, int ncol, int j, in
 // zeroes the off-diagonal: |p'|^2 = |p|^2 - t g, |q'|^2 = |q|^2 + t g), so only the inner
 // product is reduced per rotation; where the update cancels (a norm drops below 1e-3 of
 // its old value) both are recomputed from the rotated columns. Returns whether the columns
-// met at |cos| above 1e-9 (cos^2 = g^2 / (|p|^2 |q|^2) > 1e-18, tested without a division).
+// met at |cos| above 3e-8 (cos^2 = g^2 / (|p|^2 |q|^2) > 1e-15, tested without a division).
 template <int LPP, int EPJ, bool GUARD>
 __device__ inline bool jacobi_pair(double* gp, double* gq, double* np, double* nq, int sub, int ne, double negl) {
   double u[EPJ], v[EPJ];
@@ -508,13 +508,13 @@ __device__ inline bool jacobi_pair(double* gp, double* gq, double* np, double* n
     *np = an;
     *nq = bn;
   }
-  return ga * ga > 1e-18 * (al * be);
+  return ga * ga > 1e-15 * (al * be);
 }
 
 // One rotation of the pair (s, t) where the lanes of the group hold column s in registers
 // (u, squared norm al, the same in every lane of the group) and column t sits in LDS at gq
 // (squared norm *nq). Only column t is read and written back. Returns whether the columns
-// met at |cos| above 1e-9, as jacobi_pair does.
+// met at |cos| above 3e-8, as jacobi_pair does.
 template <int LPP, int EPJ, bool GUARD>
 __device__ inline bool jacobi_held(double (&u)[EPJ], double& al, double* gq, double* nq, int sub, int ne,
                                      double negl) {
@@ -553,7 +553,7 @@ __device__ inline bool jacobi_held(double (&u)[EPJ], double& al, double* gq, dou
     an = group_sum<LPP>(an);
     bn = group_sum<LPP>(bn);
   }
-  const bool big = ga * ga > 1e-18 * (al * be);
+  const bool big = ga * ga > 1e-15 * (al * be);
   al = an;
   if (sub == 0) *nq = bn;
   return big;
@@ -779,7 +779,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     int nlev = 0;
     while (((n + (1 << nlev) - 1) >> nlev) >= 2) ++nlev;
     for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
-      bool big = false;  // a pair of this sweep met at |cos| above 1e-9
+      bool big = false;  // a pair of this sweep met at |cos| above 3e-8
       // fresh norms at each sweep bound the drift of the tracked updates
       for (int l = g; l < n; l += NG) {
         double s2 = 0.0;
@@ -838,7 +838,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       }
       __syncthreads();
       // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
-      // below 1e-9, the columns are orthogonal to |cos| ~ 1e-18, under the 1e-15 at which a
+      // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
       // pair is rotated at all, so the sweep that would only confirm it is skipped.
       converged = !__syncthreads_or(big);
     }
@@ -846,7 +846,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     const int nn = n + (n & 1);
     const int npair = nn / 2;
     for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
-      bool big = false;  // a pair of this sweep met at |cos| above 1e-9
+      bool big = false;  // a pair of this sweep met at |cos| above 3e-8
       // fresh norms at each sweep bound the drift of the tracked updates
       for (int l = g; l < n; l += NG) {
         double s2 = 0.0;
@@ -877,7 +877,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
         __syncthreads();
       }
       // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
-      // below 1e-9, the columns are orthogonal to |cos| ~ 1e-18, under the 1e-15 at which a
+      // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
       // pair is rotated at all, so the sweep that would only confirm it is skipped.
       converged = !__syncthreads_or(big);
     }
