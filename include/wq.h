@@ -134,8 +134,13 @@ wq_status wq_points_get(const wq_points* pts, wq_array what, void* dst_device, w
  * with the inverse applied through a QR factorisation of Z V_t (as Eq. (7) does for
  * A Z^2 A^T). The SVD in FP64: Householder QR of A^T with column pivoting, one-sided
  * Jacobi on the n x n triangular factor (left singular vectors directly), V_t formed as
- * A^T U_t S_t^{-1}. Weights are stored aligned with Q_i.
- * report (host, nullable): per family counts and worst cases, see wq_solve_report.
+ * A^T U_t S_t^{-1}. Where the pivoted QR alone proves how many singular values the
+ * cutoff keeps (sigma_{k+1} <= ||R22|| below cutoff * R_00 / 10, sigma_k >=
+ * 1 / ||R11^-1||_F - ||R22|| above 100 * cutoff * ||A||_F), the same solution is taken
+ * from the k pivot rows of A directly (Z A_k^T = Q R, w = Z Q R^-T b_k) without the SVD.
+ * Weights are stored aligned with Q_i.
+ * report (host, nullable): per family counts and worst cases, see wq_solve_report; for
+ * the systems solved without the SVD its ratios are the certified bounds.
  * Synchronises `stream`. Returns WQ_ESVD if a Jacobi SVD hit its sweep limit. */
 typedef struct {
   int64_t systems;          /* number of (row, family) systems solved                 */
@@ -143,6 +148,7 @@ typedef struct {
   int32_t max_sweeps;       /* largest number of Jacobi sweeps used                   */
   double min_kept_ratio;    /* smallest sigma_t / sigma_1 kept                        */
   double max_dropped_ratio; /* largest sigma_{t+1} / sigma_1 dropped                  */
+  int64_t certified;        /* systems whose kept count the pivoted QR proved (no SVD) */
 } wq_solve_report;
 
 wq_status solve_weights(wq_mesh* mesh, wq_points* pts, unsigned fam_mask, double tsvd_rel_cutoff,

@@ -313,6 +313,7 @@ struct TsvdArgs {
   unsigned long long* min_kept;     // bits of a double
   unsigned long long* max_dropped;  // bits of a double
   unsigned long long* truncated;
+  unsigned long long* certified;  // systems solved on the certified-rank path
   int* fail;
 };
 
@@ -604,6 +605,12 @@ __device__ inline HalvingSlot halving_slot(int n, int L, int g) {
 //  3. keep sigma_k > tau sigma_1; c_k = u_k^T b / sigma_k; V_t = A^T U_t Sigma_t^-1 (A
 //     re-read from the basis blocks), X = Z V_t;
 //  4. X = Q R (CGS2), y = R^-T c, w = Z Q y.
+// Where the pivoted QR already proves which singular values the cutoff keeps (a gap at
+// tau around its k-th step, certified by bounds on ||R22|| and ||R11^-1||), the QR stops
+// at step k and steps 2-3 are skipped: X = Z A_k^T over the k pivot rows of A and c =
+// their entries of b give the same solution (the kept span is that of those rows). The
+// derivative families always have such a gap (their rows sum to zero, and the geometry's
+// other coordinate is a second null direction), as do the mass rows of regular cells.
 // One workgroup per system; everything lives in LDS.
 template <int LPP, int EPR, int EPJ, int NT>
 __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
@@ -677,7 +684,8 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
     const double v = G[(size_t)l * ld + m];
     fro2 += v * v;
   }
-  const double negl = 1e-30 * block_sum(fro2, red);
+  const double fa2 = block_sum(fro2, red);
+  const double negl = 1e-30 * fa2;
   // ---- 2. Householder QR of A^T with column pivoting (largest trailing norm first).
   // Columns are addressed through a permutation (no data swaps); reflector j is kept
   // unscaled in its column (v_j = 1, v_m = x_m / (x_j - R_jj) below), R_jj in beta[j].
@@ -701,270 +709,354 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   }
   __syncthreads();
   const int kmax = min(n, r);
-  for (int j = 0; j < kmax; ++j) {
-    const double* cv = red + 32 + 32 * (j & 1);
-    const int* cur = (j & 1) ? cmap : piv;
-    int* nxt = (j & 1) ? piv : cmap;
-    double s2;
-    int bi;
-    if constexpr (NW >= 8) {  // one candidate per lane of each group of NW lanes
-      s2 = cv[tid & (NW - 1)];
-      bi = (int)cv[16 + (tid & (NW - 1))];
-      group_argmax<NW>(s2, bi);
-    } else {
-      s2 = cv[0];
-      bi = (int)cv[16];
-      for (int w = 1; w < NW; ++w) {
-        const double v = cv[w];
-        const int i2 = (int)cv[16 + w];
-        if (v > s2 || (v == s2 && i2 < bi)) {
-          s2 = v;
-          bi = i2;
-        }
-      }
-    }
-    const int cj = cur[j], pc = cur[bi];
-    double rjj, rv0, tj;
-    householder(G[(size_t)pc * ld + j], s2, &rjj, &rv0, &tj);
-    if (tid == 0) beta[j] = rjj;
-    for (int l = tid; l < n; l += NT) nxt[l] = l == j ? pc : (l == bi ? cj : cur[l]);
-    int bl;
-    const double best = qr_update<LPP, EPR, NG>(G, ld, r, n, j, pc, cur, bi, cj, tj, rv0, g, sub, &bl);
-    double* nv = red + 32 + 32 * ((j + 1) & 1);
-    wave_argmax<LPP>(best, bl, nv, nv + 16);
-    __syncthreads();
-  }
-  // the final permutation: logical column l of R is constraint perm[l]
-  const int* perm = (kmax & 1) ? cmap : piv;
-  // ---- M = R1^T: column k of M is row k of R1, M[k][i] = R1[k][i] = G[i][k] for i >= k.
-  // M sits at the end of the G area (X is later written from the start; see step 3).
-  double* M = G + (size_t)n * ld - (size_t)n * ldm;
-  {
-    constexpr int MS = (EPJ * LPP * EPJ * LPP + NT - 1) / NT;  // n^2 <= (EPJ LPP)^2
-    double val[MS];
-#pragma unroll
-    for (int s2 = 0; s2 < MS; ++s2) {
-      const int e = tid + NT * s2;
-      const int k = e / n, ii = e - k * n;
-      val[s2] = (e < n * n && ii >= k && k < kmax) ? (ii == k ? beta[k] : G[(size_t)perm[ii] * ld + k]) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s2 = 0; s2 < MS; ++s2) {
-      const int e = tid + NT * s2;
-      const int k = e / n, ii = e - k * n;
-      if (e < n * n) M[(size_t)k * ldm + ii] = val[s2];
-    }
-    for (int e = tid; e < n * (ldm - n); e += NT) M[(size_t)(e / (ldm - n)) * ldm + n + e % (ldm - n)] = 0.0;
-    for (int l = tid; l < n; l += NT) pinv[perm[l]] = l;
-  }
-  __syncthreads();
-  // ---- one-sided Jacobi on the columns of M. Rows [n, ldm) of every column are zero, and
-  // ne LPP <= ldm. Two pair orderings (each visits every pair once per sweep):
-  //  - recursive halving: each group holds the S column of its pairs in registers for a
-  //    whole level, so a rotation reads and writes only its T column in LDS (half the LDS
-  //    traffic) and sweeps are fewer; it costs registers and a few more rounds and barriers;
-  //  - the circle method: both columns of a pair through LDS in every round.
-  // Instances take the ordering that measured faster for their buckets: halving for
-  // 48 < n <= 56 (r <= 128), for 48 < n <= 64 with 80 < r <= 128 and for n <= 64 with
-  // r > 128; circle for the rest, where the held column cost occupancy or the extra rounds
-  // cost more than the LDS traffic saved.
-  constexpr bool HALVING = (NT == 256 && (EPJ == 7 || EPR == 32)) || (NT == 512 && LPP == 16);
-  const int ne = (n + LPP - 1) / LPP;
-  const bool full = ldm >= EPJ * LPP;  // all EPJ rows of a lane inside the column: no checks
-  int sweeps = 0;
-  bool converged = false;
-  double* cn = nrm;  // squared column norms of M (nrm is free after the QR)
-  if constexpr (HALVING) {
-    int nlev = 0;
-    while (((n + (1 << nlev) - 1) >> nlev) >= 2) ++nlev;
-    for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
-      bool big = false;  // a pair of this sweep met at |cos| above 3e-8
-      // fresh norms at each sweep bound the drift of the tracked updates
-      for (int l = g; l < n; l += NG) {
-        double s2 = 0.0;
-        for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
-        s2 = group_sum<LPP>(s2);
-        if (sub == 0) cn[l] = s2;
-      }
-      __syncthreads();
-      double u[EPJ];
-      double al = 0.0;
-      int held = -1;  // the column in u, or -1
-      for (int L = 0; L < nlev; ++L) {
-        const HalvingSlot sl = halving_slot(n, L, g);
-        const bool act = sl.j < sl.h;
-        const int want = act ? sl.s : -1;
-        if (L > 0) {
-          // a column no longer held goes back to LDS before anyone reads it
-          if (held >= 0 && held != want) {
-            double* gp = M + (size_t)held * ldm + sub;
-#pragma unroll
-            for (int e = 0; e < EPJ; ++e)
-              if (full || e < ne) gp[e * LPP] = u[e];
-            if (sub == 0) cn[held] = al;
-            held = -1;
+  // With early set, the factorisation stops before step j once the trailing block is
+  // negligible: ||R22||_F^2 <= (n - j) * (largest trailing column norm^2) below
+  // (tau / 10)^2 R_00^2 (R_00^2 = s20, the largest column norm^2 of A^T), a hundred times
+  // the rounding level of the factorisation for tau = 1e-12. Returns the
+  // step it stopped before (kmax when it ran to the end); s2stop is that step's pivot norm^2.
+  double s20 = 0.0, s2stop = 0.0;
+  auto qr_steps = [&](int j0, bool early) -> int {
+    for (int j = j0; j < kmax; ++j) {
+      const double* cv = red + 32 + 32 * (j & 1);
+      const int* cur = (j & 1) ? cmap : piv;
+      int* nxt = (j & 1) ? piv : cmap;
+      double s2;
+      int bi;
+      if constexpr (NW >= 8) {  // one candidate per lane of each group of NW lanes
+        s2 = cv[tid & (NW - 1)];
+        bi = (int)cv[16 + (tid & (NW - 1))];
+        group_argmax<NW>(s2, bi);
+      } else {
+        s2 = cv[0];
+        bi = (int)cv[16];
+        for (int w = 1; w < NW; ++w) {
+          const double v = cv[w];
+          const int i2 = (int)cv[16 + w];
+          if (v > s2 || (v == s2 && i2 < bi)) {
+            s2 = v;
+            bi = i2;
           }
-          __syncthreads();
-        }
-        if (act && held != want) {
-          const double* gp = M + (size_t)want * ldm + sub;
-#pragma unroll
-          for (int e = 0; e < EPJ; ++e) u[e] = (full || e < ne) ? gp[e * LPP] : 0.0;
-          al = cn[want];
-          held = want;
-        }
-        const int rounds = halving_groups((n + (1 << L) - 1) >> L);
-        for (int rd = 0; rd < rounds; ++rd) {
-          if (act && rd < sl.h) {
-            int k = sl.j + rd;
-            if (k >= sl.h) k -= sl.h;
-            if (k < sl.tcnt) {
-              const int cQ = sl.tlo + k;
-              double* gq = M + (size_t)cQ * ldm + sub;
-              big |= full ? jacobi_held<LPP, EPJ, false>(u, al, gq, cn + cQ, sub, ne, negl)
-                          : jacobi_held<LPP, EPJ, true>(u, al, gq, cn + cQ, sub, ne, negl);
-            }
-          }
-          __syncthreads();
         }
       }
-      if (held >= 0) {
-        double* gp = M + (size_t)held * ldm + sub;
-#pragma unroll
-        for (int e = 0; e < EPJ; ++e)
-          if (full || e < ne) gp[e * LPP] = u[e];
-        if (sub == 0) cn[held] = al;
+      if (j == 0) s20 = s2;
+      if (early && (double)(n - j) * s2 < 1e-2 * a.tau * a.tau * s20) {
+        s2stop = s2;
+        return j;
       }
+      const int cj = cur[j], pc = cur[bi];
+      double rjj, rv0, tj;
+      householder(G[(size_t)pc * ld + j], s2, &rjj, &rv0, &tj);
+      if (tid == 0) beta[j] = rjj;
+      for (int l = tid; l < n; l += NT) nxt[l] = l == j ? pc : (l == bi ? cj : cur[l]);
+      int bl;
+      const double best = qr_update<LPP, EPR, NG>(G, ld, r, n, j, pc, cur, bi, cj, tj, rv0, g, sub, &bl);
+      double* nv = red + 32 + 32 * ((j + 1) & 1);
+      wave_argmax<LPP>(best, bl, nv, nv + 16);
       __syncthreads();
-      // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
-      // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
-      // pair is rotated at all, so the sweep that would only confirm it is skipped.
-      converged = !__syncthreads_or(big);
     }
+    return kmax;
+  };
+  const int kq = qr_steps(0, true);
+  // ---- certified rank. The truncated-SVD solution only depends on the kept count t, the
+  // span of the kept right singular vectors and the kept part of b. sigma_{k+1} <= ||R22||
+  // and sigma_k >= sigma_min(R11) - ||R22|| >= 1 / ||R11^-1||_F - ||R22|| (R11: the
+  // leading k x k block, R22: the trailing block, k = kq), and tau sigma_1 lies between
+  // tau R_00 and tau ||A||_F. So when ||R22|| is below tau R_00 / 10 and the kept bound
+  // is above 100 tau ||A||_F, the cutoff keeps exactly k singular values, and their span is
+  // that of the k pivot rows of A up to O(eps / gap): the solution is then the weighted
+  // minimum-norm solution of those k equations, w = Z Q R^-T b_k for Z A_k^T = Q R (CGS2
+  // below), the same as the SVD's to rounding times the conditioning. Otherwise the
+  // factorisation runs to the end and the Jacobi SVD decides.
+  // R11^-1 by columns, one thread per column (back substitution); column c is kept in rows
+  // kq - c .. kq of the physical column of logical column kq - 1 - c, below its R entries
+  // (rows < kq - 1 - c), where no thread reads R.
+  const int* pk = (kq & 1) ? cmap : piv;  // logical column l of R is constraint pk[l]
+  const double r22 = kq < kmax ? sqrt((double)(n - kq) * s2stop) : 0.0;
+  double lo = 0.0;
+  bool fast = false;
+  if (s20 > 0.0 && kq > 0) {
+    double tn = 0.0;
+    for (int c = tid; c < kq; c += NT) {
+      double* Tc = G + (size_t)pk[kq - 1 - c] * ld + (kq - c);
+      double d = 1.0 / beta[c];
+      Tc[c] = d;
+      tn = d * d;
+      for (int ii = c - 1; ii >= 0; --ii) {
+        double s = 0.0;
+        for (int jj = ii + 1; jj <= c; ++jj) s += G[(size_t)pk[jj] * ld + ii] * Tc[jj];
+        d = -s / beta[ii];
+        Tc[ii] = d;
+        tn += d * d;
+      }
+    }
+    tn = block_sum(tn, red);  // the same bits in every thread: the branch is uniform
+    lo = 1.0 / sqrt(tn) - r22;
+    fast = lo > 100.0 * a.tau * sqrt(fa2);
+  }
+  int t;  // the kept count
+  if (fast) {
+    // X = Z A_k^T: the k pivot rows of A, re-read from the basis blocks, as the columns
+    for (int l = tid; l < n; l += NT) pinv[pk[l]] = l;
+    for (int c = tid; c < kq; c += NT) yv[c] = Rk[pk[c]];
+    if (tid == 0) {
+      atomicMin(a.min_kept, dbits(lo / sqrt(fa2)));       // a lower bound of sigma_k / sigma_1
+      atomicMax(a.max_dropped, dbits(r22 / sqrt(s20)));  // an upper bound of sigma_{k+1} / sigma_1
+      if (kq < n) atomicAdd(a.truncated, 1ULL);
+      atomicAdd(a.certified, 1ULL);
+    }
+    __syncthreads();
+    for (int e = tid; e < kq * ld; e += NT) G[e] = 0.0;
+    __syncthreads();
+    int moff = 0;
+    for (int64_t p = a.sptr[i]; p < a.sptr[i + 1]; ++p) {
+      const int32_t c = a.scell[p];
+      const int m = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
+      const int np = (int)(a.cell_pt_off[c + 1] - a.cell_pt_off[c]);
+      const double* Dc = AD + a.dptr[c];
+      const uint8_t* sl = a.slot + a.soff[p];
+      for (int e = tid; e < np * m; e += NT) {
+        const int q = e / m, k = e - q * m;
+        const int col = pinv[sl[k]];
+        if (col < kq) G[(size_t)col * ld + moff + q] = z[moff + q] * Dc[e];
+      }
+      moff += np;
+    }
+    __syncthreads();
+    t = kq;
   } else {
-    const int nn = n + (n & 1);
-    const int npair = nn / 2;
-    for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
-      bool big = false;  // a pair of this sweep met at |cos| above 3e-8
-      // fresh norms at each sweep bound the drift of the tracked updates
-      for (int l = g; l < n; l += NG) {
-        double s2 = 0.0;
-        for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
-        s2 = group_sum<LPP>(s2);
-        if (sub == 0) cn[l] = s2;
+    if (kq < kmax) qr_steps(kq, false);
+    // the final permutation: logical column l of R is constraint perm[l]
+    const int* perm = (kmax & 1) ? cmap : piv;
+    // ---- M = R1^T: column k of M is row k of R1, M[k][i] = R1[k][i] = G[i][k] for i >= k.
+    // M sits at the end of the G area (X is later written from the start; see step 3).
+    double* M = G + (size_t)n * ld - (size_t)n * ldm;
+    {
+      constexpr int MS = (EPJ * LPP * EPJ * LPP + NT - 1) / NT;  // n^2 <= (EPJ LPP)^2
+      double val[MS];
+  #pragma unroll
+      for (int s2 = 0; s2 < MS; ++s2) {
+        const int e = tid + NT * s2;
+        const int k = e / n, ii = e - k * n;
+        val[s2] = (e < n * n && ii >= k && k < kmax) ? (ii == k ? beta[k] : G[(size_t)perm[ii] * ld + k]) : 0.0;
       }
       __syncthreads();
-      // Circle method on positions 0..nn-1: pair p starts at positions (p, nn - 1 - p);
-      // position 0 stays, positions 1..nn-1 advance by one per round (cyclically), so every
-      // two positions meet once per sweep. Position 0 holds column nn - 1 (the padding
-      // column when n is odd), position c > 0 column c - 1; pair 0 (which holds the padding
-      // column in every round for odd n) runs on the last group, so for odd n the last pair
-      // group does no work and a wave whose groups are all past the real pairs skips the
-      // round entirely.
-      const int pp = (g + 1 == npair) ? 0 : g + 1;
-      int P = pp, Q = nn - 1 - pp;
-      for (int rd = 0; rd < nn - 1; ++rd) {
-        const int cP = P == 0 ? nn - 1 : P - 1, cQ = Q - 1;
-        if (g < npair && cP < n && cQ < n) {
-          double* gp = M + (size_t)cP * ldm + sub;
-          double* gq = M + (size_t)cQ * ldm + sub;
-          big |= full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + cP, cn + cQ, sub, ne, negl)
-                      : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + cP, cn + cQ, sub, ne, negl);
+  #pragma unroll
+      for (int s2 = 0; s2 < MS; ++s2) {
+        const int e = tid + NT * s2;
+        const int k = e / n, ii = e - k * n;
+        if (e < n * n) M[(size_t)k * ldm + ii] = val[s2];
+      }
+      for (int e = tid; e < n * (ldm - n); e += NT) M[(size_t)(e / (ldm - n)) * ldm + n + e % (ldm - n)] = 0.0;
+      for (int l = tid; l < n; l += NT) pinv[perm[l]] = l;
+    }
+    __syncthreads();
+    // ---- one-sided Jacobi on the columns of M. Rows [n, ldm) of every column are zero, and
+    // ne LPP <= ldm. Two pair orderings (each visits every pair once per sweep):
+    //  - recursive halving: each group holds the S column of its pairs in registers for a
+    //    whole level, so a rotation reads and writes only its T column in LDS (half the LDS
+    //    traffic) and sweeps are fewer; it costs registers and a few more rounds and barriers;
+    //  - the circle method: both columns of a pair through LDS in every round.
+    // Instances take the ordering that measured faster for their buckets: halving for
+    // 48 < n <= 56 (r <= 128), for 48 < n <= 64 with 80 < r <= 128 and for n <= 64 with
+    // r > 128; circle for the rest, where the held column cost occupancy or the extra rounds
+    // cost more than the LDS traffic saved.
+    constexpr bool HALVING = (NT == 256 && (EPJ == 7 || EPR == 32)) || (NT == 512 && LPP == 16);
+    const int ne = (n + LPP - 1) / LPP;
+    const bool full = ldm >= EPJ * LPP;  // all EPJ rows of a lane inside the column: no checks
+    int sweeps = 0;
+    bool converged = false;
+    double* cn = nrm;  // squared column norms of M (nrm is free after the QR)
+    if constexpr (HALVING) {
+      int nlev = 0;
+      while (((n + (1 << nlev) - 1) >> nlev) >= 2) ++nlev;
+      for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
+        bool big = false;  // a pair of this sweep met at |cos| above 3e-8
+        // fresh norms at each sweep bound the drift of the tracked updates
+        for (int l = g; l < n; l += NG) {
+          double s2 = 0.0;
+          for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+          s2 = group_sum<LPP>(s2);
+          if (sub == 0) cn[l] = s2;
         }
-        P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
-        Q = (Q == nn - 1) ? 1 : Q + 1;
+        __syncthreads();
+        double u[EPJ];
+        double al = 0.0;
+        int held = -1;  // the column in u, or -1
+        for (int L = 0; L < nlev; ++L) {
+          const HalvingSlot sl = halving_slot(n, L, g);
+          const bool act = sl.j < sl.h;
+          const int want = act ? sl.s : -1;
+          if (L > 0) {
+            // a column no longer held goes back to LDS before anyone reads it
+            if (held >= 0 && held != want) {
+              double* gp = M + (size_t)held * ldm + sub;
+  #pragma unroll
+              for (int e = 0; e < EPJ; ++e)
+                if (full || e < ne) gp[e * LPP] = u[e];
+              if (sub == 0) cn[held] = al;
+              held = -1;
+            }
+            __syncthreads();
+          }
+          if (act && held != want) {
+            const double* gp = M + (size_t)want * ldm + sub;
+  #pragma unroll
+            for (int e = 0; e < EPJ; ++e) u[e] = (full || e < ne) ? gp[e * LPP] : 0.0;
+            al = cn[want];
+            held = want;
+          }
+          const int rounds = halving_groups((n + (1 << L) - 1) >> L);
+          for (int rd = 0; rd < rounds; ++rd) {
+            if (act && rd < sl.h) {
+              int k = sl.j + rd;
+              if (k >= sl.h) k -= sl.h;
+              if (k < sl.tcnt) {
+                const int cQ = sl.tlo + k;
+                double* gq = M + (size_t)cQ * ldm + sub;
+                big |= full ? jacobi_held<LPP, EPJ, false>(u, al, gq, cn + cQ, sub, ne, negl)
+                            : jacobi_held<LPP, EPJ, true>(u, al, gq, cn + cQ, sub, ne, negl);
+              }
+            }
+            __syncthreads();
+          }
+        }
+        if (held >= 0) {
+          double* gp = M + (size_t)held * ldm + sub;
+  #pragma unroll
+          for (int e = 0; e < EPJ; ++e)
+            if (full || e < ne) gp[e * LPP] = u[e];
+          if (sub == 0) cn[held] = al;
+        }
+        __syncthreads();
+        // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
+        // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
+        // pair is rotated at all, so the sweep that would only confirm it is skipped.
+        converged = !__syncthreads_or(big);
+      }
+    } else {
+      const int nn = n + (n & 1);
+      const int npair = nn / 2;
+      for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
+        bool big = false;  // a pair of this sweep met at |cos| above 3e-8
+        // fresh norms at each sweep bound the drift of the tracked updates
+        for (int l = g; l < n; l += NG) {
+          double s2 = 0.0;
+          for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+          s2 = group_sum<LPP>(s2);
+          if (sub == 0) cn[l] = s2;
+        }
+        __syncthreads();
+        // Circle method on positions 0..nn-1: pair p starts at positions (p, nn - 1 - p);
+        // position 0 stays, positions 1..nn-1 advance by one per round (cyclically), so every
+        // two positions meet once per sweep. Position 0 holds column nn - 1 (the padding
+        // column when n is odd), position c > 0 column c - 1; pair 0 (which holds the padding
+        // column in every round for odd n) runs on the last group, so for odd n the last pair
+        // group does no work and a wave whose groups are all past the real pairs skips the
+        // round entirely.
+        const int pp = (g + 1 == npair) ? 0 : g + 1;
+        int P = pp, Q = nn - 1 - pp;
+        for (int rd = 0; rd < nn - 1; ++rd) {
+          const int cP = P == 0 ? nn - 1 : P - 1, cQ = Q - 1;
+          if (g < npair && cP < n && cQ < n) {
+            double* gp = M + (size_t)cP * ldm + sub;
+            double* gq = M + (size_t)cQ * ldm + sub;
+            big |= full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + cP, cn + cQ, sub, ne, negl)
+                        : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + cP, cn + cQ, sub, ne, negl);
+          }
+          P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
+          Q = (Q == nn - 1) ? 1 : Q + 1;
+          __syncthreads();
+        }
+        // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
+        // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
+        // pair is rotated at all, so the sweep that would only confirm it is skipped.
+        converged = !__syncthreads_or(big);
+      }
+    }
+    if (!converged && tid == 0) atomicOr(a.fail, 1);
+    if (tid == 0) atomicMax(a.max_sweeps, sweeps);
+    // ---- 3. singular values, truncation, c
+    double smax = 0.0;
+    for (int l = g; l < n; l += NG) {
+      double s2 = 0.0;
+      for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+      s2 = group_sum<LPP>(s2);
+      if (sub == 0) sig[l] = sqrt(s2);
+      smax = fmax(smax, sqrt(s2));
+    }
+    smax = block_max(smax, red);
+    if (tid == 0) {
+      int t = 0;
+      double kmin = INFINITY, dmax = 0.0;
+      for (int l = 0; l < n; ++l) {
+        if (sig[l] > a.tau * smax) {
+          keep[t++] = l;
+          kmin = fmin(kmin, sig[l] / smax);
+        } else {
+          dmax = fmax(dmax, sig[l] / smax);
+        }
+      }
+      keep[n] = t;
+      atomicMin(a.min_kept, dbits(kmin));
+      atomicMax(a.max_dropped, dbits(dmax));
+      if (t < n) atomicAdd(a.truncated, 1ULL);
+    }
+    __syncthreads();
+    t = keep[n];
+    // c_k = u_k^T b / sigma_k = (w_k . P^T b) / sigma_k^2
+    for (int k = g; k < t; k += NG) {
+      const double* wk = M + (size_t)keep[k] * ldm;
+      double s2 = 0.0;
+      for (int m = sub; m < n; m += LPP) s2 += wk[m] * Rk[perm[m]];
+      s2 = group_sum<LPP>(s2);
+      if (sub == 0) yv[k] = s2 / (sig[keep[k]] * sig[keep[k]]);
+    }
+    // X[m][k] = z_m sum_l A[l][m] U[l][k] / sigma_k with U[l][k] = M[pinv[l]][keep[k]] /
+    // sigma_k. The threads form NP parts of RW (r rounded up to whole waves) rows each; part
+    // g2 forms columns k0 + g2 KC + (0 .. KC-1) of a chunk of NP KC columns. Columns are
+    // written from the start of G, M's columns sit at the end: the writes of a chunk never
+    // reach a column of M still to be read (n ld >= k ld + n ldm - (n - k) ldm for k <= n,
+    // as ldm <= ld), and a chunk's own columns are read before the barrier.
+    constexpr int KC = 8;
+    {
+      const int RW = (r + 63) / 64 * 64;
+      const int NP = NT / RW;  // >= 1: r <= NT
+      const int g2 = tid / RW, m = tid - g2 * RW;
+      const bool row = g2 < NP && m < r;
+      const double* Dc = nullptr;
+      const uint8_t* sl = nullptr;
+      int mc = 0;
+      if (row) {
+        const int64_t p = a.sptr[i] + ptc[m];
+        const int32_t c = a.scell[p];
+        mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
+        Dc = AD + a.dptr[c] + (int64_t)ptq[m] * mc;
+        sl = a.slot + a.soff[p];
+      }
+      for (int k0 = 0; k0 < t; k0 += NP * KC) {
+        const int kb = k0 + g2 * KC;
+        double acc[KC];
+  #pragma unroll
+        for (int kq = 0; kq < KC; ++kq) acc[kq] = 0.0;
+        if (row)
+          for (int kk = 0; kk < mc; ++kk) {
+            const double av = Dc[kk];
+            const int ii = pinv[sl[kk]];
+  #pragma unroll
+            for (int kq = 0; kq < KC; ++kq)
+              if (kb + kq < t) acc[kq] += av * M[(size_t)keep[kb + kq] * ldm + ii];
+          }
+        __syncthreads();
+        if (row) {
+  #pragma unroll
+          for (int kq = 0; kq < KC; ++kq)
+            if (kb + kq < t) {
+              const double sk = sig[keep[kb + kq]];
+              G[(size_t)(kb + kq) * ld + m] = z[m] * acc[kq] / (sk * sk);
+            }
+        }
         __syncthreads();
       }
-      // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
-      // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
-      // pair is rotated at all, so the sweep that would only confirm it is skipped.
-      converged = !__syncthreads_or(big);
-    }
-  }
-  if (!converged && tid == 0) atomicOr(a.fail, 1);
-  if (tid == 0) atomicMax(a.max_sweeps, sweeps);
-  // ---- 3. singular values, truncation, c
-  double smax = 0.0;
-  for (int l = g; l < n; l += NG) {
-    double s2 = 0.0;
-    for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
-    s2 = group_sum<LPP>(s2);
-    if (sub == 0) sig[l] = sqrt(s2);
-    smax = fmax(smax, sqrt(s2));
-  }
-  smax = block_max(smax, red);
-  if (tid == 0) {
-    int t = 0;
-    double kmin = INFINITY, dmax = 0.0;
-    for (int l = 0; l < n; ++l) {
-      if (sig[l] > a.tau * smax) {
-        keep[t++] = l;
-        kmin = fmin(kmin, sig[l] / smax);
-      } else {
-        dmax = fmax(dmax, sig[l] / smax);
-      }
-    }
-    keep[n] = t;
-    atomicMin(a.min_kept, dbits(kmin));
-    atomicMax(a.max_dropped, dbits(dmax));
-    if (t < n) atomicAdd(a.truncated, 1ULL);
-  }
-  __syncthreads();
-  const int t = keep[n];
-  // c_k = u_k^T b / sigma_k = (w_k . P^T b) / sigma_k^2
-  for (int k = g; k < t; k += NG) {
-    const double* wk = M + (size_t)keep[k] * ldm;
-    double s2 = 0.0;
-    for (int m = sub; m < n; m += LPP) s2 += wk[m] * Rk[perm[m]];
-    s2 = group_sum<LPP>(s2);
-    if (sub == 0) yv[k] = s2 / (sig[keep[k]] * sig[keep[k]]);
-  }
-  // X[m][k] = z_m sum_l A[l][m] U[l][k] / sigma_k with U[l][k] = M[pinv[l]][keep[k]] /
-  // sigma_k. The threads form NP parts of RW (r rounded up to whole waves) rows each; part
-  // g2 forms columns k0 + g2 KC + (0 .. KC-1) of a chunk of NP KC columns. Columns are
-  // written from the start of G, M's columns sit at the end: the writes of a chunk never
-  // reach a column of M still to be read (n ld >= k ld + n ldm - (n - k) ldm for k <= n,
-  // as ldm <= ld), and a chunk's own columns are read before the barrier.
-  constexpr int KC = 8;
-  {
-    const int RW = (r + 63) / 64 * 64;
-    const int NP = NT / RW;  // >= 1: r <= NT
-    const int g2 = tid / RW, m = tid - g2 * RW;
-    const bool row = g2 < NP && m < r;
-    const double* Dc = nullptr;
-    const uint8_t* sl = nullptr;
-    int mc = 0;
-    if (row) {
-      const int64_t p = a.sptr[i] + ptc[m];
-      const int32_t c = a.scell[p];
-      mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
-      Dc = AD + a.dptr[c] + (int64_t)ptq[m] * mc;
-      sl = a.slot + a.soff[p];
-    }
-    for (int k0 = 0; k0 < t; k0 += NP * KC) {
-      const int kb = k0 + g2 * KC;
-      double acc[KC];
-#pragma unroll
-      for (int kq = 0; kq < KC; ++kq) acc[kq] = 0.0;
-      if (row)
-        for (int kk = 0; kk < mc; ++kk) {
-          const double av = Dc[kk];
-          const int ii = pinv[sl[kk]];
-#pragma unroll
-          for (int kq = 0; kq < KC; ++kq)
-            if (kb + kq < t) acc[kq] += av * M[(size_t)keep[kb + kq] * ldm + ii];
-        }
-      __syncthreads();
-      if (row) {
-#pragma unroll
-        for (int kq = 0; kq < KC; ++kq)
-          if (kb + kq < t) {
-            const double sk = sig[keep[kb + kq]];
-            G[(size_t)(kb + kq) * ld + m] = z[m] * acc[kq] / (sk * sk);
-          }
-      }
-      __syncthreads();
     }
   }
   // ---- 4. CGS2 on the columns of X; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk, w = Z Q y.
@@ -1195,12 +1287,12 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   // report accumulators
   struct Rep {
     int fail, max_sweeps;
-    unsigned long long min_kept, max_dropped, truncated;
+    unsigned long long min_kept, max_dropped, truncated, certified;
   };
   DBuf drep;
   if (s == WQ_OK) s = dalloc(drep, sizeof(Rep));
   if (s == WQ_OK) {
-    Rep init{0, 0, 0x7ff0000000000000ULL /* +inf */, 0ULL, 0ULL};
+    Rep init{0, 0, 0x7ff0000000000000ULL /* +inf */, 0ULL, 0ULL, 0ULL};
     if (hipMemcpyAsync(drep.p, &init, sizeof(Rep), hipMemcpyHostToDevice, st) != hipSuccess) s = WQ_EDEVICE;
   }
   // one launch per size bucket covers every family asked for (more workgroups per launch,
@@ -1300,6 +1392,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       ta.min_kept = &R->min_kept;
       ta.max_dropped = &R->max_dropped;
       ta.truncated = &R->truncated;
+      ta.certified = &R->certified;
       ta.fail = &R->fail;
       // 8 lanes per column pair; systems with more than 64 constraints (more than 32
       // pairs) take 1024 threads with 16 lanes per column pair (more waves per CU to hide
@@ -1373,6 +1466,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     for (int f = 0; f < 4; ++f) nf += (fam_mask >> f) & 1;
     rep->systems = n * nf;
     rep->truncated = (int64_t)hrep.truncated;
+    rep->certified = (int64_t)hrep.certified;
     rep->max_sweeps = hrep.max_sweeps;
     double v;
     std::memcpy(&v, &hrep.min_kept, 8);

@@ -41,7 +41,7 @@ class Timing(C.Structure):
 
 class SolveReport(C.Structure):
     _fields_ = [("systems", C.c_int64), ("truncated", C.c_int64), ("max_sweeps", C.c_int32),
-                ("min_kept_ratio", C.c_double), ("max_dropped_ratio", C.c_double)]
+                ("min_kept_ratio", C.c_double), ("max_dropped_ratio", C.c_double), ("certified", C.c_int64)]
 
 
 class Conductivity(C.Structure):
