@@ -315,6 +315,10 @@ struct TsvdArgs {
   unsigned long long* truncated;
   unsigned long long* certified;  // systems solved on the certified-rank path
   int* fail;
+  const int32_t* sel;  // nullable: workgroup b solves system sel[b] (family-major index) instead of b
+  int32_t* fb_list;    // one-wave solver: systems left to the SVD kernel (family-major index)
+  int rp_n;            // one-wave solver: the largest n its dynamic LDS holds R11 for
+  int* fb_count;
 };
 
 __device__ inline double block_sum(double v, double* red) {
@@ -616,8 +620,9 @@ template <int LPP, int EPR, int EPJ, int NT>
 __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   extern __shared__ double sh[];
   constexpr int NG = NT / LPP;  // lane groups
-  const int fs = (int)(blockIdx.x / a.nsys);
-  const int64_t sys = blockIdx.x - (int64_t)fs * a.nsys;
+  const int64_t wg = a.sel ? (int64_t)a.sel[blockIdx.x] : (int64_t)blockIdx.x;
+  const int fs = (int)(wg / a.nsys);
+  const int64_t sys = wg - (int64_t)fs * a.nsys;
   const double* AD = a.D[fs];
   const int tid = threadIdx.x;
   const int g = tid / LPP, sub = tid % LPP;
@@ -767,9 +772,11 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   // minimum-norm solution of those k equations, w = Z Q R^-T b_k for Z A_k^T = Q R (CGS2
   // below), the same as the SVD's to rounding times the conditioning. Otherwise the
   // factorisation runs to the end and the Jacobi SVD decides.
-  // R11^-1 by columns, one thread per column (back substitution); column c is kept in rows
-  // kq - c .. kq of the physical column of logical column kq - 1 - c, below its R entries
-  // (rows < kq - 1 - c), where no thread reads R.
+  // Column c of S = R11^-T (lower triangular), one thread per column: S[ii][c] = (delta -
+  // sum_{jj = c}^{ii - 1} R[jj][ii] S[jj][c]) / R[ii][ii], with R[.][ii] read down the
+  // physical column of logical column ii (rows < ii) and S[.][c] kept in rows c+1 .. kq of
+  // the physical column of logical column c (its reflector rows, no longer needed: no
+  // thread reads R there). Both are contiguous runs, summed in four chains.
   const int* pk = (kq & 1) ? cmap : piv;  // logical column l of R is constraint pk[l]
   const double r22 = kq < kmax ? sqrt((double)(n - kq) * s2stop) : 0.0;
   double lo = 0.0;
@@ -777,16 +784,21 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   if (s20 > 0.0 && kq > 0) {
     double tn = 0.0;
     for (int c = tid; c < kq; c += NT) {
-      double* Tc = G + (size_t)pk[kq - 1 - c] * ld + (kq - c);
-      double d = 1.0 / beta[c];
-      Tc[c] = d;
-      tn = d * d;
-      for (int ii = c - 1; ii >= 0; --ii) {
-        double s = 0.0;
-        for (int jj = ii + 1; jj <= c; ++jj) s += G[(size_t)pk[jj] * ld + ii] * Tc[jj];
-        d = -s / beta[ii];
-        Tc[ii] = d;
-        tn += d * d;
+      double* Sc = G + (size_t)pk[c] * ld + 1;  // S[jj][c] at Sc[jj]
+      for (int ii = c; ii < kq; ++ii) {
+        const double* Rc = G + (size_t)pk[ii] * ld;  // R[jj][ii] at Rc[jj], jj < ii
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int jj = c;
+        for (; jj + 4 <= ii; jj += 4) {
+          s0 = fma(Rc[jj], Sc[jj], s0);
+          s1 = fma(Rc[jj + 1], Sc[jj + 1], s1);
+          s2 = fma(Rc[jj + 2], Sc[jj + 2], s2);
+          s3 = fma(Rc[jj + 3], Sc[jj + 3], s3);
+        }
+        for (; jj < ii; ++jj) s0 = fma(Rc[jj], Sc[jj], s0);
+        const double v = ((ii == c ? 1.0 : 0.0) - ((s0 + s1) + (s2 + s3))) / beta[ii];
+        Sc[ii] = v;
+        tn = fma(v, v, tn);
       }
     }
     tn = block_sum(tn, red);  // the same bits in every thread: the branch is uniform
@@ -1187,6 +1199,323 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
 }
 
 
+// ---------------------------------------------------------------------------------
+// One wave per weight system, for systems of at most 64 constraints and 64 points (the
+// rows of regular cells and most of their neighbours). Lane l holds a column of the
+// factorised matrix in registers, one double per point, so the Householder steps need no
+// cross-lane reductions: the reflector's column is broadcast through LDS and every lane
+// forms its own dot product and update. The steps are those of the certified path of
+// k_tsvd2 (the kept count proved from the pivoted QR of A^T), with the second factorisation
+// by Householder instead of CGS2:
+//  1. pivoted Householder QR of A^T, stopped once the trailing block is negligible;
+//  2. the rank proof (||R11^-1||_F from R11^-T, one column per lane);
+//  3. Householder QR of X = Z A_k^T (the k pivot rows of A, re-read from the basis blocks);
+//  4. y = R^-T b_k, u = Q [y; 0] (the reflectors applied in reverse), w = Z u, and one
+//     step of iterative refinement on the residual of the k kept equations.
+// A system the proof does not cover is appended to a list for k_tsvd2 (the Jacobi SVD).
+constexpr int WR = 64;     // points (rows) held per lane
+constexpr int WMAXC = 40;  // support cells of a row in the gather tables
+
+
+// Largest (value, lane) of the wave, ties to the smaller lane: the same in every lane.
+__device__ inline void wave_argmax64(double v, int i, double& bv, int& bi) {
+  group_argmax<16>(v, i);
+  bv = readlane_f64(v, 0);
+  bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+  for (int row = 1; row < 4; ++row) {
+    const double rv = readlane_f64(v, 16 * row);
+    const int ri = __builtin_amdgcn_readlane(i, 16 * row);
+    if (rv > bv || (rv == bv && ri < bi)) {
+      bv = rv;
+      bi = ri;
+    }
+  }
+}
+
+// Sum over the wave in a fixed order, the same bits in every lane.
+__device__ inline double wave_sum64(double v) {
+  v = group_sum<16>(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_wsolve(TsvdArgs a) {
+  __shared__ double vb[WR + 4];  // the current reflector's column (4 zero pads past the rows)
+  __shared__ double zv[WR], bv[WR], beta[WR], ib[WR], tau2[WR], rv2[WR], uv2[WR];
+  extern __shared__ double rp[];  // R11 above the diagonal by columns: n_max (n_max - 1) / 2
+  __shared__ int64_t cbase[WMAXC];
+  __shared__ int cmc[WMAXC];
+  __shared__ uint8_t invk[WMAXC * WR];  // local index of row function l in support cell p, 255: none
+  __shared__ uint8_t ptp[WR + 4], ptq[WR + 4];  // support cell and local index of every point
+  __shared__ int pk[WR];                // position -> constraint of the pivoted QR
+  const int lane = threadIdx.x;
+  const int fs = (int)(blockIdx.x / a.nsys);
+  const int64_t sys = blockIdx.x - (int64_t)fs * a.nsys;
+  const double* AD = a.D[fs];
+  const int64_t i = a.rows[sys];
+  const int n = (int)(a.row_ptr[i + 1] - a.row_ptr[i]);
+  const int r = (int)(a.qptr[i + 1] - a.qptr[i]);
+  const int64_t s0 = a.sptr[i];
+  const int nc = (int)(a.sptr[i + 1] - s0);
+  auto to_svd = [&]() {
+    if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)blockIdx.x;
+  };
+  if (n > WR || n > a.rp_n || r > WR || nc < 1 || nc >= WMAXC) {
+    to_svd();
+    return;
+  }
+  // ---- gather tables (every point belongs to one support cell; np, m <= r, n <= 64).
+  // Rows past r point at a sentinel cell nc whose functions are all absent.
+  {
+    int moff = 0;
+    for (int p = 0; p < nc; ++p) {
+      const int32_t c = a.scell[s0 + p];
+      const int mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
+      const int np = (int)(a.cell_pt_off[c + 1] - a.cell_pt_off[c]);
+      const int64_t d0 = a.dptr[c];
+      invk[p * WR + lane] = 255;
+      __builtin_amdgcn_wave_barrier();
+      if (lane < mc) invk[p * WR + a.slot[a.soff[s0 + p] + lane]] = (uint8_t)lane;
+      if (lane < np) {
+        ptp[moff + lane] = (uint8_t)p;
+        ptq[moff + lane] = (uint8_t)lane;
+        zv[moff + lane] = a.DN[d0 + (int64_t)lane * mc + a.kself[s0 + p]];
+      }
+      if (lane == 0) {
+        cbase[p] = d0;
+        cmc[p] = mc;
+      }
+      moff += np;
+    }
+    invk[nc * WR + lane] = 255;
+    if (lane == 0) {
+      cbase[nc] = cbase[0];
+      cmc[nc] = 0;
+    }
+    if (lane >= r) {
+      ptp[lane] = (uint8_t)nc;
+      ptq[lane] = 0;
+      zv[lane] = 0.0;
+    }
+    if (lane < 4) {  // pads read by the residual loop (rows in fours)
+      ptp[WR + lane] = (uint8_t)nc;
+      ptq[WR + lane] = 0;
+      vb[WR + lane] = 0.0;
+    }
+    if (lane < n) bv[lane] = a.rhs[fs][a.row_ptr[i] + lane];
+  }
+  __syncthreads();
+  // Column of A^T for row function fl (every point), times z when zs; zero where !valid.
+  // Branch-free: every lane loads from a valid address and selects away what it does not
+  // have; the loads go out in batches of 16.
+  auto gather = [&](int fl, bool valid, bool zs, double(&x)[WR]) {
+    const int fq = valid ? fl : 0;
+#pragma unroll
+    for (int m = 0; m < WR; ++m) {
+      const int p = ptp[m];
+      const int kk = invk[p * WR + fq];
+      const bool has = valid && kk != 255;
+      const double v = AD[cbase[p] + (int64_t)ptq[m] * cmc[p] + (has ? kk : 0)];
+      x[m] = has ? (zs ? v * zv[m] : v) : 0.0;
+      if ((m & 15) == 15) asm volatile("" ::: "memory");
+    }
+  };
+  // The pivot column of step j into vb (rows below j zero); returns its row-j entry x0.
+  auto load_pivot = [&](const double(&x)[WR], int j, int p) -> double {
+    if (lane == p) {
+#pragma unroll
+      for (int m = 0; m < WR; ++m) vb[m] = x[m];
+    }
+    if (lane < j) vb[lane] = 0.0;
+    __syncthreads();
+    return vb[j];
+  };
+  // One Householder step on the lane's column: the reflector I - tj v v^T with v = rv0 vb,
+  // where vb holds the pivot column from row j on, vb[j] = x0 - R_jj = 1 / rv0 (so v_j = 1
+  // up to rounding) and zeros above, so rows above j are left exactly as they are (R
+  // entries). Every pass runs over all rows without a branch (branches around parts of
+  // the column make the compiler keep two versions of it); the new squared norm of the
+  // rows below j selects them.
+  auto reflect = [&](double(&x)[WR], int j, double rv0, double tj) -> double {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < WR; ++m) acc[m & 3] = fma(vb[m], x[m], acc[m & 3]);
+    const double sv = tj * rv0 * rv0 * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    asm volatile("" ::: "memory");  // re-read vb rather than hold 64 more doubles
+#pragma unroll
+    for (int m = 0; m < WR; ++m) x[m] = fma(-sv, vb[m], x[m]);
+    double ns[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < WR; ++m) ns[m & 3] = fma(x[m], m > j ? x[m] : 0.0, ns[m & 3]);
+    return (ns[0] + ns[1]) + (ns[2] + ns[3]);
+  };
+  double x[WR];
+  // ---- 1. pivoted Householder QR of A^T (lane l: column l), with the early stop of k_tsvd2
+  gather(lane, lane < n, false, x);
+  double fro = 0.0;
+#pragma unroll
+  for (int m = 0; m < WR; ++m) fro = fma(x[m], x[m], fro);
+  const double fa2 = wave_sum64(fro);
+  double nrm = fro;  // squared norm of the rows from the current step on
+  const int kmax = min(n, r);
+  int pos = lane < n ? -1 : WR;  // position once pivoted (lanes past n never are)
+  double s20 = 0.0, s2stop = 0.0;
+  int kq = kmax;
+  for (int j = 0; j < kmax; ++j) {
+    double s2;
+    int p;
+    wave_argmax64(pos < 0 ? nrm : -1.0, lane, s2, p);
+    if (j == 0) s20 = s2;
+    if ((double)(n - j) * s2 < 1e-2 * a.tau * a.tau * s20) {
+      kq = j;
+      s2stop = s2;
+      break;
+    }
+    const double x0 = load_pivot(x, j, p);
+    double rjj, rv0, tj;
+    householder(x0, s2, &rjj, &rv0, &tj);
+    if (lane == 0) vb[j] = x0 - rjj;
+    if (lane == p) {
+      pk[j] = p;
+      beta[j] = rjj;
+      pos = j;
+    }
+    __syncthreads();
+    if (pos < 0) nrm = reflect(x, j, rv0, tj);
+    __syncthreads();
+  }
+  // ---- 2. rank proof: sigma_{k+1} <= ||R22||_F <= sqrt((n - k) s2stop) and sigma_k >=
+  // 1 / ||R11^-1||_F - ||R22||_F (as in k_tsvd2)
+  const double r22 = kq < kmax ? sqrt((double)(n - kq) * s2stop) : 0.0;
+  if (pos >= 1 && pos < kq) {
+    const int base = pos * (pos - 1) / 2;
+#pragma unroll
+    for (int m = 0; m < WR - 1; ++m)
+      if (m < pos) rp[base + m] = x[m];
+  }
+  if (lane < kq) ib[lane] = 1.0 / beta[lane];
+  __syncthreads();
+  double lo = 0.0;
+  bool fast = false;
+  if (s20 > 0.0 && kq > 0) {
+    // column `lane` of S = R11^-T (lower triangular): S[ii][c] = (delta - sum_{jj < ii}
+    // R[jj][ii] S[jj][c]) / R[ii][ii]; the entries above the diagonal come out zero
+    double t[WR];
+    double tn = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < WR; ++ii) {
+      if (ii < kq) {  // a uniform branch, not an exit: the loop unrolls fully
+        double sa[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int jj = 0; jj < ii; ++jj) {
+          sa[jj & 3] = fma(rp[ii * (ii - 1) / 2 + jj], t[jj], sa[jj & 3]);
+          if ((jj & 15) == 15) asm volatile("" ::: "memory");  // at most 16 loads in flight
+        }
+        const double v = ((lane == ii ? 1.0 : 0.0) - ((sa[0] + sa[1]) + (sa[2] + sa[3]))) * ib[ii];
+        t[ii] = v;
+        tn = fma(v, v, tn);
+      }
+    }
+    lo = 1.0 / sqrt(wave_sum64(tn)) - r22;
+    fast = lo > 100.0 * a.tau * sqrt(fa2);
+  }
+  if (!fast) {
+    to_svd();
+    return;
+  }
+  // ---- 3. Householder QR of X = Z A_k^T (lane c: position c)
+  gather(lane < kq ? pk[lane] : 0, lane < kq, true, x);
+  nrm = 0.0;
+#pragma unroll
+  for (int m = 0; m < WR; ++m) nrm = fma(x[m], x[m], nrm);
+  for (int j = 0; j < kq; ++j) {
+    const double x0 = load_pivot(x, j, j);
+    double rjj, rv0, tj;
+    householder(x0, readlane_f64(nrm, j), &rjj, &rv0, &tj);
+    if (lane == 0) {
+      vb[j] = x0 - rjj;
+      beta[j] = rjj;
+      tau2[j] = tj;
+      rv2[j] = rv0;
+      uv2[j] = x0 - rjj;
+    }
+    __syncthreads();
+    if (lane > j && lane < kq) nrm = reflect(x, j, rv0, tj);
+    __syncthreads();
+  }
+  // X has full column rank (sigma_k(A) > 0 and z > 0 on the points); R_jj != 0 is checked
+  // anyway before dividing by it
+  if (__any(lane < kq && !(fabs(beta[lane]) > 0.0 && fabs(beta[lane]) < INFINITY))) {
+    to_svd();
+    return;
+  }
+  if (lane == 0) {
+    atomicMin(a.min_kept, dbits(lo / sqrt(fa2)));       // a lower bound of sigma_k / sigma_1
+    atomicMax(a.max_dropped, dbits(r22 / sqrt(s20)));  // an upper bound of sigma_{k+1} / sigma_1
+    if (kq < n) atomicAdd(a.truncated, 1ULL);
+    atomicAdd(a.certified, 1ULL);
+  }
+  // ---- 4. u = Q [R^-T c; 0] for the right-hand side c (lane c: c_c; result: lane m, row
+  // m). R^-T by columns of R (lane c holds R[0..c-1][c]); Q = H_0 ... H_{k-1} applied to
+  // [y; 0] in reverse, with the reflectors of step 3.
+  auto solve = [&](double cv) -> double {
+    const double id = lane < kq ? 1.0 / beta[lane] : 0.0;
+    double u = 0.0, acc = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < WR; ++ii) {
+      if (ii < kq) {
+        const double yi = readlane_f64((cv - acc) * id, ii);
+        if (lane == ii) u = yi;
+        acc = fma(x[ii], yi, acc);
+      }
+    }
+    for (int j = kq - 1; j >= 0; --j) {
+      if (lane == j) {
+#pragma unroll
+        for (int m = 0; m < WR; ++m) vb[m] = x[m];
+      }
+      if (lane < j) vb[lane] = 0.0;
+      if (lane == 0) vb[j] = uv2[j];
+      __syncthreads();
+      const double vm = lane < r ? vb[lane] * rv2[j] : 0.0;
+      const double d = wave_sum64(vm * u);
+      u = fma(-tau2[j] * d, vm, u);
+      __syncthreads();
+    }
+    return u;
+  };
+  // w = Z u, then one step of iterative refinement on the k kept equations: rho = b_k -
+  // A_k w (A_k re-read from the basis blocks, w broadcast through vb), w += Z solve(rho).
+  // It takes the residual of the kept equations from about eps kappa(X) to rounding level.
+  // (solve runs in every lane: it holds barriers and cross-lane sums)
+  const double u0 = solve(lane < kq ? bv[pk[lane]] : 0.0);
+  const double w = lane < r ? zv[lane] * u0 : 0.0;
+  vb[lane] = w;
+  __syncthreads();
+  double rho = 0.0;
+  {
+    const int fq = lane < kq ? pk[lane] : 0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int m0 = 0; m0 < r; m0 += 4) {  // a runtime loop (no register index depends on m); rows
+      // past r read the pads (sentinel cell, vb = 0)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + e;
+        const int p = ptp[m];
+        const int kk = invk[p * WR + fq];
+        const bool has = lane < kq && kk != 255;
+        const double v = AD[cbase[p] + (int64_t)ptq[m] * cmc[p] + (has ? kk : 0)];
+        acc[e] = fma(has ? v : 0.0, vb[m], acc[e]);
+      }
+    }
+    if (lane < kq) rho = bv[fq] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+  }
+  __syncthreads();
+  const double dw = solve(rho);
+  if (lane < r) a.W[fs][a.qptr[i] + lane] = fma(zv[lane], dw, w);
+}
+
+
 void release_weights(wq_weights* w) {
   for (int f = 0; f < 4; ++f) {
     dfree(w->W[f]);
@@ -1310,133 +1639,181 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     famW[nfam] = w->W[f].as<double>();
     ++nfam;
   }
-  {
-    for (int b = 0; b < NBKT && s == WQ_OK; ++b) {
-      const int64_t ns = hist[b];
-      if (ns == 0) continue;
-      const int mn = hist[2 * (NBKT + 1) + 2 * b];      // largest n in the bucket
-      const int mr = hist[2 * (NBKT + 1) + 2 * b + 1];  // largest r in the bucket
-      // column stride: 8 (mod 32) doubles (consecutive columns start 16 banks apart) unless
-      // a shorter stride fits more workgroups of the bucket on a CU (160 KiB of LDS,
-      // allocated in 512-byte granules); then the longest stride with the most workgroups
-      int ld = ((mr + 1 + 23) / 32) * 32 + 8;
-      if (ld < mr + 1) ld += 32;
-      auto lds_of = [&](int l) {
-        return ((size_t)mn * l + (size_t)mr + 5 * (size_t)mn + 96) * sizeof(double) +
-               (4 * (size_t)mn + 1 + 2 * (size_t)mr) * sizeof(int);
-      };
-      // (the kernels also hold 256 bytes of static LDS; the launch checks the exact figure)
-      auto per_cu = [&](int l) { return (int)((160 * 1024) / ((lds_of(l) + 256 + 511) / 512 * 512)); };
-      for (int l = ld - 1, best = per_cu(ld); l >= mr + 1; --l)
-        if (per_cu(l) > best) {
-          best = per_cu(l);
-          ld = l;
-        }
-      // M = R1^T columns: stride = 8 (mod 16) doubles, at most ld, at least mn rounded up
-      // to the 8 lanes of a Jacobi pair (those rows are zero-padded). For 48 < n <= 64 this
-      // covers all EPJ rows of a lane of the instance chosen below (no per-row checks).
-      // n > 64: a 512-thread instance (8 lanes per pair) where two workgroups fit on a CU
-      // (n <= 96, r <= 128), else the 1024-thread one (16 lanes per pair)
-      // The thread count and the lanes per pair or column set the summation orders, so they
-      // follow from the bucket's bounds alone: a system gets the same bits whatever else is
-      // in the bucket (a mesh alone or in a batch). Only strides and per-lane slot counts,
-      // which do not change the arithmetic, follow the bucket's actual maxima.
-      //  - 64 < n <= 96, r <= 128: 512 threads, 8 lanes per pair (two workgroups per CU fit
-      //    where the 1024-thread instance's registers allow one);
-      //  - 48 < n <= 64, 80 < r <= 128: 512 threads, 16 lanes per pair and per column (these
-      //    buckets hold two or three workgroups per CU by LDS: twice the resident waves);
-      //  - other n > 64: 1024 threads, 16 lanes (6 rows of M per lane up to n = 96, so that
-      //    no lane runs zero rows through the rotations, 8 above); other n <= 64: 256
-      //    threads, 8 lanes.
-      const int bn = b / NB_R, br = b % NB_R;
-      const bool w512 = bn == 4 && br <= 3;                          // 64 < n <= 96, r <= 128
-      const bool m512 = (bn == 2 || bn == 3) && br >= 2 && br <= 3;  // 48 < n <= 64, 80 < r <= 128
-      const bool wide = bn >= 4;                                     // n > 64
-      const int lpp = ((wide && !w512) || m512) ? 16 : 8;  // lanes per column pair of the instance
-      int ldm = ((mn + 8) / 16) * 16 + 8;
-      if (ldm < (mn + lpp - 1) / lpp * lpp) ldm += 16;
-      if (ldm > ld) ldm = (mn + lpp - 1) / lpp * lpp;
-      if (ldm > ld) ld = ldm;
-      const size_t lds = lds_of(ld);
-      if (lds + 256 > 160 * 1024) {
-        set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
-                  ") does not fit in LDS");
-        s = WQ_EINVAL;
-        break;
+  // common kernel arguments
+  TsvdArgs base{};
+  base.nfam = nfam;
+  base.tau = tau;
+  base.sptr = P->supp_ptr.as<int64_t>();
+  base.scell = P->supp_cell.as<int32_t>();
+  base.cfn_ptr = P->cfn_ptr.as<int64_t>();
+  base.cell_pt_off = P->cell_pt_off.as<int64_t>();
+  base.dptr = P->dptr.as<int64_t>();
+  base.soff = P->soff.as<int64_t>();
+  base.slot = P->slot.as<uint8_t>();
+  base.kself = P->kself.as<uint8_t>();
+  base.row_ptr = P->row_ptr.as<int64_t>();
+  base.qptr = P->qptr.as<int64_t>();
+  for (int q = 0; q < 4; ++q) {
+    base.D[q] = famD[q];
+    base.rhs[q] = famR[q];
+    base.W[q] = famW[q];
+  }
+  base.DN = P->DN.as<double>();
+  if (s == WQ_OK) {
+    Rep* R = drep.as<Rep>();
+    base.max_sweeps = &R->max_sweeps;
+    base.min_kept = &R->min_kept;
+    base.max_dropped = &R->max_dropped;
+    base.truncated = &R->truncated;
+    base.certified = &R->certified;
+    base.fail = &R->fail;
+  }
+  // The SVD kernel for the systems of bucket b (all of them, or the `grid` listed in sel).
+  auto svd_launch = [&](int b, const int32_t* sel, int64_t grid, int64_t flops) -> wq_status {
+    const int64_t ns = hist[b];
+    const int mn = hist[2 * (NBKT + 1) + 2 * b];      // largest n in the bucket
+    const int mr = hist[2 * (NBKT + 1) + 2 * b + 1];  // largest r in the bucket
+    // column stride: 8 (mod 32) doubles (consecutive columns start 16 banks apart) unless
+    // a shorter stride fits more workgroups of the bucket on a CU (160 KiB of LDS,
+    // allocated in 512-byte granules); then the longest stride with the most workgroups
+    int ld = ((mr + 1 + 23) / 32) * 32 + 8;
+    if (ld < mr + 1) ld += 32;
+    auto lds_of = [&](int l) {
+      return ((size_t)mn * l + (size_t)mr + 5 * (size_t)mn + 96) * sizeof(double) +
+             (4 * (size_t)mn + 1 + 2 * (size_t)mr) * sizeof(int);
+    };
+    // (the kernels also hold 256 bytes of static LDS; the launch checks the exact figure)
+    auto per_cu = [&](int l) { return (int)((160 * 1024) / ((lds_of(l) + 256 + 511) / 512 * 512)); };
+    for (int l = ld - 1, best = per_cu(ld); l >= mr + 1; --l)
+      if (per_cu(l) > best) {
+        best = per_cu(l);
+        ld = l;
       }
-      Rep* R = drep.as<Rep>();
-      TsvdArgs ta;
+    // M = R1^T columns: stride = 8 (mod 16) doubles, at most ld, at least mn rounded up
+    // to the 8 lanes of a Jacobi pair (those rows are zero-padded). For 48 < n <= 64 this
+    // covers all EPJ rows of a lane of the instance chosen below (no per-row checks).
+    // n > 64: a 512-thread instance (8 lanes per pair) where two workgroups fit on a CU
+    // (n <= 96, r <= 128), else the 1024-thread one (16 lanes per pair)
+    // The thread count and the lanes per pair or column set the summation orders, so they
+    // follow from the bucket's bounds alone: a system gets the same bits whatever else is
+    // in the bucket (a mesh alone or in a batch). Only strides and per-lane slot counts,
+    // which do not change the arithmetic, follow the bucket's actual maxima.
+    //  - 64 < n <= 96, r <= 128: 512 threads, 8 lanes per pair (two workgroups per CU fit
+    //    where the 1024-thread instance's registers allow one);
+    //  - 48 < n <= 64, 80 < r <= 128: 512 threads, 16 lanes per pair and per column (these
+    //    buckets hold two or three workgroups per CU by LDS: twice the resident waves);
+    //  - other n > 64: 1024 threads, 16 lanes (6 rows of M per lane up to n = 96, so that
+    //    no lane runs zero rows through the rotations, 8 above); other n <= 64: 256
+    //    threads, 8 lanes.
+    const int bn = b / NB_R, br = b % NB_R;
+    const bool w512 = bn == 4 && br <= 3;                          // 64 < n <= 96, r <= 128
+    const bool m512 = (bn == 2 || bn == 3) && br >= 2 && br <= 3;  // 48 < n <= 64, 80 < r <= 128
+    const bool wide = bn >= 4;                                     // n > 64
+    const int lpp = ((wide && !w512) || m512) ? 16 : 8;  // lanes per column pair of the instance
+    int ldm = ((mn + 8) / 16) * 16 + 8;
+    if (ldm < (mn + lpp - 1) / lpp * lpp) ldm += 16;
+    if (ldm > ld) ldm = (mn + lpp - 1) / lpp * lpp;
+    if (ldm > ld) ld = ldm;
+    const size_t lds = lds_of(ld);
+    if (lds + 256 > 160 * 1024) {
+      set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
+                ") does not fit in LDS");
+      return WQ_EINVAL;
+    }
+    TsvdArgs ta = base;
+    ta.rows = lists.as<int32_t>() + start[b];
+    ta.nsys = ns;
+    ta.ld = ld;
+    ta.ldm = ldm;
+    ta.sel = sel;
+    // 8 lanes per column pair; systems with more than 64 constraints (more than 32
+    // pairs) take 1024 threads with 16 lanes per column pair (more waves per CU to hide
+    // latency: such systems fill most of a CU's LDS on their own).
+    const void* fn = nullptr;
+    const char* kname = nullptr;  // timing record: the kernel instance
+    int nt = 0;
+    {
+      // EPR: register elements per lane of a column of A^T (r), EPJ: of M (n)
+      const int epr = (mr + 7) / 8;
+      nt = !wide ? (m512 ? 512 : 256) : w512 ? 512 : 1024;
+      const bool j7 = bn == 2;  // 48 < n <= 56: 7 rows of M per lane
+      if (m512) fn = (const void*)k_tsvd2<16, 8, 4, 512>, kname = "k_tsvd2<16,8,4,512>";
+      else if (!wide && epr <= 8 && j7) fn = (const void*)k_tsvd2<8, 8, 7, 256>, kname = "k_tsvd2<8,8,7,256>";
+      else if (!wide && epr <= 16 && j7) fn = (const void*)k_tsvd2<8, 16, 7, 256>, kname = "k_tsvd2<8,16,7,256>";
+      else if (!wide && epr <= 8) fn = (const void*)k_tsvd2<8, 8, 8, 256>, kname = "k_tsvd2<8,8,8,256>";
+      else if (!wide && epr <= 16) fn = (const void*)k_tsvd2<8, 16, 8, 256>, kname = "k_tsvd2<8,16,8,256>";
+      else if (!wide) fn = (const void*)k_tsvd2<8, 32, 8, 256>, kname = "k_tsvd2<8,32,8,256>";
+      else if (w512) fn = (const void*)k_tsvd2<8, 16, 12, 512>, kname = "k_tsvd2<8,16,12,512>";
+      else if (bn == 4) fn = (const void*)k_tsvd2<16, 16, 6, 1024>, kname = "k_tsvd2<16,16,6,1024>";
+      else fn = (const void*)k_tsvd2<16, 16, 8, 1024>, kname = "k_tsvd2<16,16,8,1024>";
+    }
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, fn) != hipSuccess || fa.sharedSizeBytes + lds > 160 * 1024) {
+      set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
+                ") does not fit in LDS");
+      return WQ_EINVAL;
+    }
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+      set_error("solve_weights: cannot raise the LDS limit of the TSVD kernel");
+      return WQ_EDEVICE;
+    }
+    KTimer tm(kname, flops, st);
+    void* args[] = {&ta};
+    wq_status ls = WQ_OK;
+    if (hipLaunchKernel(fn, dim3((unsigned)grid), dim3(nt), args, lds, st) != hipSuccess) {
+      set_error("solve_weights: TSVD launch failed");
+      ls = WQ_EDEVICE;
+    }
+    tm.stop();
+    return ls;
+  };
+  // Systems of at most 64 constraints and 64 points go to the one-wave solver first; the
+  // ones its rank proof does not cover are listed and solved by the SVD kernel of their
+  // bucket afterwards (one synchronisation to read the list lengths).
+  DBuf fbl, fbc;
+  int fbn[NBKT];
+  bool any_w = false;
+  if (s == WQ_OK) s = dalloc_n<int32_t>(fbl, (size_t)n * nfam);
+  if (s == WQ_OK) s = dalloc_n<int>(fbc, NBKT);
+  if (s == WQ_OK && hipMemsetAsync(fbc.p, 0, NBKT * sizeof(int), st) != hipSuccess) s = WQ_EDEVICE;
+  for (int b = 0; b < NBKT && s == WQ_OK; ++b) {
+    const int64_t ns = hist[b];
+    if (ns == 0) continue;
+    const int bn = b / NB_R, br = b % NB_R;
+    if (bn <= 3 && br == 0) {  // n <= 64, r <= 64
+      TsvdArgs ta = base;
       ta.rows = lists.as<int32_t>() + start[b];
       ta.nsys = ns;
-      ta.ld = ld;
-      ta.ldm = ldm;
-      ta.nfam = nfam;
-      ta.tau = tau;
-      ta.sptr = P->supp_ptr.as<int64_t>();
-      ta.scell = P->supp_cell.as<int32_t>();
-      ta.cfn_ptr = P->cfn_ptr.as<int64_t>();
-      ta.cell_pt_off = P->cell_pt_off.as<int64_t>();
-      ta.dptr = P->dptr.as<int64_t>();
-      ta.soff = P->soff.as<int64_t>();
-      ta.slot = P->slot.as<uint8_t>();
-      ta.kself = P->kself.as<uint8_t>();
-      ta.row_ptr = P->row_ptr.as<int64_t>();
-      ta.qptr = P->qptr.as<int64_t>();
-      for (int q = 0; q < 4; ++q) {
-        ta.D[q] = famD[q];
-        ta.rhs[q] = famR[q];
-        ta.W[q] = famW[q];
-      }
-      ta.DN = P->DN.as<double>();
-      ta.max_sweeps = &R->max_sweeps;
-      ta.min_kept = &R->min_kept;
-      ta.max_dropped = &R->max_dropped;
-      ta.truncated = &R->truncated;
-      ta.certified = &R->certified;
-      ta.fail = &R->fail;
-      // 8 lanes per column pair; systems with more than 64 constraints (more than 32
-      // pairs) take 1024 threads with 16 lanes per column pair (more waves per CU to hide
-      // latency: such systems fill most of a CU's LDS on their own).
-      const void* fn = nullptr;
-      const char* kname = nullptr;  // timing record: the kernel instance
-      int nt = 0;
-      {
-        // EPR: register elements per lane of a column of A^T (r), EPJ: of M (n)
-        const int epr = (mr + 7) / 8;
-        nt = !wide ? (m512 ? 512 : 256) : w512 ? 512 : 1024;
-        const bool j7 = bn == 2;  // 48 < n <= 56: 7 rows of M per lane
-        if (m512) fn = (const void*)k_tsvd2<16, 8, 4, 512>, kname = "k_tsvd2<16,8,4,512>";
-        else if (!wide && epr <= 8 && j7) fn = (const void*)k_tsvd2<8, 8, 7, 256>, kname = "k_tsvd2<8,8,7,256>";
-        else if (!wide && epr <= 16 && j7) fn = (const void*)k_tsvd2<8, 16, 7, 256>, kname = "k_tsvd2<8,16,7,256>";
-        else if (!wide && epr <= 8) fn = (const void*)k_tsvd2<8, 8, 8, 256>, kname = "k_tsvd2<8,8,8,256>";
-        else if (!wide && epr <= 16) fn = (const void*)k_tsvd2<8, 16, 8, 256>, kname = "k_tsvd2<8,16,8,256>";
-        else if (!wide) fn = (const void*)k_tsvd2<8, 32, 8, 256>, kname = "k_tsvd2<8,32,8,256>";
-        else if (w512) fn = (const void*)k_tsvd2<8, 16, 12, 512>, kname = "k_tsvd2<8,16,12,512>";
-        else if (bn == 4) fn = (const void*)k_tsvd2<16, 16, 6, 1024>, kname = "k_tsvd2<16,16,6,1024>";
-        else fn = (const void*)k_tsvd2<16, 16, 8, 1024>, kname = "k_tsvd2<16,16,8,1024>";
-      }
-      hipFuncAttributes fa{};
-      if (hipFuncGetAttributes(&fa, fn) != hipSuccess || fa.sharedSizeBytes + lds > 160 * 1024) {
-        set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ", r=" + std::to_string(mr) +
-                  ") does not fit in LDS");
-        s = WQ_EINVAL;
-        break;
-      }
-      if (lds > 64 * 1024 &&
-          hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
-        set_error("solve_weights: cannot raise the LDS limit of the TSVD kernel");
-        s = WQ_EDEVICE;
-        break;
-      }
-      KTimer tm(kname, (int64_t)bflops[b] * nfam, st);
-      void* args[] = {&ta};
-      if (hipLaunchKernel(fn, dim3((unsigned)(ns * nfam)), dim3(nt), args, lds, st) != hipSuccess) {
-        set_error("solve_weights: TSVD launch failed");
-        s = WQ_EDEVICE;
-      }
+      ta.fb_list = fbl.as<int32_t>() + start[b] * nfam;
+      ta.fb_count = fbc.as<int>() + b;
+      // dynamic LDS: R11 of the bucket's largest system (more workgroups per CU for the
+      // smaller buckets; the layout, and so the arithmetic, does not depend on it)
+      const int mn = hist[2 * (NBKT + 1) + 2 * b];
+      ta.rp_n = mn;
+      const size_t lds = (size_t)mn * (mn - 1) / 2 * sizeof(double);
+      KTimer tm("k_wsolve", (int64_t)bflops[b] * nfam, st);
+      k_wsolve<<<dim3((unsigned)(ns * nfam)), dim3(64), lds, st>>>(ta);
       tm.stop();
+      if (hipGetLastError() != hipSuccess) {
+        set_error("solve_weights: one-wave solver launch failed");
+        s = WQ_EDEVICE;
+      }
+      any_w = true;
+    } else {
+      s = svd_launch(b, nullptr, ns * nfam, (int64_t)bflops[b] * nfam);
     }
   }
+  if (s == WQ_OK && any_w) {
+    if (hipMemcpyAsync(fbn, fbc.p, NBKT * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      s = WQ_EDEVICE;
+    for (int b = 0; b < NBKT && s == WQ_OK; ++b)
+      if (hist[b] && b / NB_R <= 3 && b % NB_R == 0 && fbn[b] > 0)
+        s = svd_launch(b, fbl.as<int32_t>() + start[b] * nfam, fbn[b], 0);
+  }
+  dfree(fbl);
+  dfree(fbc);
   Rep hrep{};
   if (s == WQ_OK && hipMemcpyAsync(&hrep, drep.p, sizeof(Rep), hipMemcpyDeviceToHost, st) != hipSuccess)
     s = WQ_EDEVICE;
