@@ -191,6 +191,34 @@ wq_status assemble_mass_stiffness(const wq_points* pts, const wq_weights* w, con
                                   const double* k_at_points, void* mass_vals, void* stiff_vals,
                                   wq_precision prec, wq_stream stream);
 
+/* ------------------------------------------------------------------ Gauss comparison
+ * Element-wise Gauss quadrature, the system WQ is compared against (Section 1: the
+ * standard loop over elements with 4 x 4 Gauss points per Bezier cell; Section 6.1 times
+ * it against row-wise WQ with the basis at the quadrature points computed ahead and
+ * excluded), on the same CSR pattern as the WQ matrices.
+ * gauss_setup: the basis at the 16 Gauss points of every cell (values, physical
+ *   gradients, Laplacians when want_laplacian, which needs build_points(want_laplacian=1)),
+ *   the weights w_g |det J| and the physical points; synchronises `stream`.
+ * wq_gauss_size: the number of Gauss points (16 per cell); wq_gauss_get_x copies their
+ *   coordinates (device double[2 * size], x then y per point, cell-major, 4 x 4 points
+ *   per cell with the first cell coordinate fastest).
+ * assemble_gauss: vals (device double[nnz], aligned with COL) :=
+ *   WQ_GQ_MASS:       sum_cells sum_g w_g |det J| c_g N_i N_j
+ *   WQ_GQ_STIFFNESS:  sum_cells sum_g w_g |det J| c_g grad N_i . grad N_j
+ *   WQ_GQ_BIHARMONIC: sum_cells sum_g w_g |det J| c_g Lap N_i Lap N_j
+ *   with coef_at_gauss (device double[size] in the order of wq_gauss_get_x, or NULL for
+ *   1). Each cell's local matrix on FP64 MFMA, added into vals by FP64 atomics: the
+ *   order of the additions, and so the last bits, can differ between runs. Asynchronous
+ *   on `stream`; the handle must outlive the work queued on it. */
+typedef struct wq_gauss wq_gauss;
+typedef enum { WQ_GQ_MASS = 0, WQ_GQ_STIFFNESS = 1, WQ_GQ_BIHARMONIC = 2 } wq_gauss_kind;
+wq_status gauss_setup(wq_mesh* mesh, wq_points* pts, int want_laplacian, wq_stream stream, wq_gauss** out);
+void wq_gauss_destroy(wq_gauss* g);
+int64_t wq_gauss_size(const wq_gauss* g);
+wq_status wq_gauss_get_x(const wq_gauss* g, double* dst_device, wq_stream stream);
+wq_status assemble_gauss(const wq_gauss* g, wq_gauss_kind kind, const double* coef_at_gauss, double* vals,
+                         wq_stream stream);
+
 /* ------------------------------------------------------------------ nonlinear heat
  * Section 5: Tdot N_A + k(T) grad T . grad N_A - f N_A = 0 (weak residual), time by the
  * generalised trapezoidal rule, Newton with the symmetric tangent of Eq. (35).

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwq.so")
 ARCH = os.environ.get("WQ_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["wq_common.hip", "wq_points.hip", "wq_weights.hip", "wq_assemble.hip", "wq_heat.hip", "wq_server.hip", "wq_batch.hip"]
+SOURCES = ["wq_common.hip", "wq_points.hip", "wq_weights.hip", "wq_assemble.hip", "wq_heat.hip", "wq_server.hip", "wq_batch.hip", "wq_gauss.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          # packed FP32 instructions are disabled for all device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

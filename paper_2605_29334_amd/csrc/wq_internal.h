@@ -169,4 +169,10 @@ constexpr int T2_NZCAP = 416;  // CSR entries per cell-major tile (8 rows of 52;
 // 64-bit index launch helper
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Basis data at the 4 x 4 Gauss points of every cell (values, physical gradients, Laplacians
+// when GL is given; point-major per cell like the WQ data), gw = Gauss weight * |det J|, and
+// the physical points when gx is given. Asynchronous on st.
+wq_status gauss_basis(wq_mesh* M, wq_points* P, double* GN, double* GX, double* GY, double* GL, double* gw,
+                      double* gx, hipStream_t st);
+
 }  // namespace wq

@@ -41,11 +41,12 @@ __device__ inline void eval_fn(const double* C, const double b1[4], const double
 }
 
 // Basis data at the 16 Gauss points of every cell: G?[c*16*? ...] laid out like the WQ
-// data (point-major, cell functions contiguous), plus gw = weight * |det J|.
+// data (point-major, cell functions contiguous), plus gw = weight * |det J| and, when gx is
+// given, the physical points (x, y) at gx[2 (16 c + g)].
 __global__ void k_gauss_basis(int32_t ncell, const int32_t* cell_face, const uint8_t* cell_sub,
                               const int64_t* ext_ptr, const int64_t* coef_ptr, const double* coef,
                               const double* ctrl, const int64_t* cfn_ptr, const int32_t* cfn, const uint8_t* cfn_loc,
-                              double* GN, double* GX, double* GY, double* GL, double* gw) {
+                              double* GN, double* GX, double* GY, double* GL, double* gw, double* gx) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= 16LL * ncell) return;
   const int64_t c = t / 16;
@@ -59,13 +60,14 @@ __global__ void k_gauss_basis(int32_t ncell, const int32_t* cell_face, const uin
   const double* Cf = coef + coef_ptr[f] + (int64_t)sub * mf * 16;
   const int64_t f0 = cfn_ptr[c];
   const int m = (int)(cfn_ptr[c + 1] - f0);
-  double J[2][2] = {{0, 0}, {0, 0}}, H[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  double J[2][2] = {{0, 0}, {0, 0}}, H[2][3] = {{0, 0, 0}, {0, 0, 0}}, X[2] = {0, 0};
   for (int k = 0; k < m; ++k) {
     double v[6];
     eval_fn(Cf + 16 * (int)cfn_loc[f0 + k], b1, d1, s1, b2, d2, s2, v);
     const int32_t j = cfn[f0 + k];
     for (int a = 0; a < 2; ++a) {
       const double P = ctrl[2 * (int64_t)j + a];
+      X[a] += P * v[0];
       J[a][0] += P * v[1];
       J[a][1] += P * v[2];
       H[a][0] += P * v[3];
@@ -80,6 +82,10 @@ __global__ void k_gauss_basis(int32_t ncell, const int32_t* cell_face, const uin
   const double G01 = Ji[0][0] * Ji[1][0] + Ji[0][1] * Ji[1][1];
   const double G11 = Ji[1][0] * Ji[1][0] + Ji[1][1] * Ji[1][1];
   gw[16 * c + g] = c_gw[g % 4] * c_gw[g / 4] * fabs(det);
+  if (gx) {
+    gx[2 * (16 * c + g)] = X[0];
+    gx[2 * (16 * c + g) + 1] = X[1];
+  }
   const int64_t o = 16 * f0 + (int64_t)g * m;
   for (int k = 0; k < m; ++k) {
     double v[6];
@@ -1525,6 +1531,17 @@ void release_weights(wq_weights* w) {
 
 }  // namespace
 
+wq_status wq::gauss_basis(wq_mesh* M, wq_points* P, double* GN, double* GX, double* GY, double* GL, double* gw,
+                          double* gx, hipStream_t st) {
+  KTimer tm("k_gauss_basis", 16LL * P->ncell, st);
+  k_gauss_basis<<<nblocks(16LL * P->ncell, BS), BS, 0, st>>>(
+      P->ncell, P->cell_face.as<int32_t>(), P->cell_sub.as<uint8_t>(), M->ext_ptr.as<int64_t>(),
+      M->coef_ptr.as<int64_t>(), M->coef.as<double>(), M->ctrl.as<double>(), P->cfn_ptr.as<int64_t>(),
+      P->cfn.as<int32_t>(), P->cfn_loc.as<uint8_t>(), GN, GX, GY, GL, gw, gx);
+  tm.stop();
+  return hipGetLastError() == hipSuccess ? WQ_OK : WQ_EDEVICE;
+}
+
 extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, double tau, wq_stream stream,
                                    wq_weights** out, wq_solve_report* rep) {
   WQ_CHECK(M && P && out && P->mesh == M, WQ_EINVAL, "solve_weights: bad arguments");
@@ -1544,16 +1561,9 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   for (int f = 0; f < 4 && s == WQ_OK; ++f)
     if (f < 3 || (fam_mask & WQ_FAM_LAP)) s = dalloc_n<double>(G[f], ng);
   if (s == WQ_OK) s = dalloc_n<double>(gw, 16 * (size_t)P->ncell);
-  if (s == WQ_OK) {
-    KTimer tm("k_gauss_basis", 16LL * P->ncell, st);
-    k_gauss_basis<<<nblocks(16LL * P->ncell, BS), BS, 0, st>>>(
-        P->ncell, P->cell_face.as<int32_t>(), P->cell_sub.as<uint8_t>(), M->ext_ptr.as<int64_t>(),
-        M->coef_ptr.as<int64_t>(), M->coef.as<double>(), M->ctrl.as<double>(), P->cfn_ptr.as<int64_t>(),
-        P->cfn.as<int32_t>(), P->cfn_loc.as<uint8_t>(), G[0].as<double>(), G[1].as<double>(), G[2].as<double>(),
-        (fam_mask & WQ_FAM_LAP) ? G[3].as<double>() : nullptr, gw.as<double>());
-    tm.stop();
-    if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
-  }
+  if (s == WQ_OK)
+    s = gauss_basis(M, P, G[0].as<double>(), G[1].as<double>(), G[2].as<double>(),
+                    (fam_mask & WQ_FAM_LAP) ? G[3].as<double>() : nullptr, gw.as<double>(), nullptr, st);
   for (int f = 0; f < 4 && s == WQ_OK; ++f)
     if (fam_mask & (1u << f)) s = dalloc_n<double>(w->rhs[f], P->nnz);
   if (s == WQ_OK) {

@@ -118,6 +118,11 @@ def _lib():
             "wq_batch_graph_assemble": ([P, P, P, P, P, C.c_int, P], C.c_int),
             "wq_batch_destroy": ([P], None),
             "wq_autotune_assembly": ([P, P, P, P, P], C.c_int),
+            "gauss_setup": ([P, P, C.c_int, P, P], C.c_int),
+            "wq_gauss_destroy": ([P], None),
+            "wq_gauss_size": ([P], I64),
+            "wq_gauss_get_x": ([P, P, P], C.c_int),
+            "assemble_gauss": ([P, C.c_int, P, P, P], C.c_int),
             "wq_timing_enable": ([C.c_int], None),
             "wq_timings": ([P, C.c_int], C.c_int),
             "wq_strerror": ([C.c_int], C.c_char_p),
@@ -140,6 +145,7 @@ def exported_symbols():
             "assemble_tangent", "assemble_tangent_noalloc", "assemble_tangent_exact", "wq_heat_step", "wq_server_start", "wq_server_submit", "wq_server_poll",
             "wq_server_stop", "wq_batch_create", "wq_batch_build", "wq_batch_info", "wq_batch_points",
             "wq_batch_weights", "wq_batch_graph_assemble", "wq_batch_destroy", "wq_autotune_assembly",
+            "gauss_setup", "wq_gauss_destroy", "wq_gauss_size", "wq_gauss_get_x", "assemble_gauss",
             "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
 
 
@@ -261,6 +267,44 @@ class Weights:
     def close(self):
         if self.h:
             _lib().wq_weights_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+GQ_MASS, GQ_STIFFNESS, GQ_BIHARMONIC = 0, 1, 2
+
+
+class Gauss:
+    """gauss_setup / assemble_gauss: element-wise 4 x 4 Gauss assembly on the WQ pattern."""
+
+    def __init__(self, mesh, points, want_laplacian=False, stream=None):
+        h = C.c_void_p()
+        _check(_lib().gauss_setup(mesh.h, points.h, int(bool(want_laplacian)), _stream(stream), C.byref(h)),
+               "gauss_setup")
+        self.h = h
+        self.points = points
+        self.size = int(_lib().wq_gauss_size(h))
+
+    def x(self, stream=None):
+        out = torch.empty(2 * self.size, dtype=torch.float64, device="cuda")
+        _check(_lib().wq_gauss_get_x(self.h, _ptr(out), _stream(stream)), "wq_gauss_get_x")
+        return out
+
+    def assemble(self, kind, coef=None, out=None, stream=None):
+        out = _out(self.points, out, WQ_FP64)
+        if coef is not None:
+            assert coef.dtype == torch.float64 and coef.numel() == self.size and coef.is_cuda and coef.is_contiguous()
+        _check(_lib().assemble_gauss(self.h, int(kind), _ptr(coef), _ptr(out), _stream(stream)), "assemble_gauss")
+        return out
+
+    def close(self):
+        if self.h:
+            _lib().wq_gauss_destroy(self.h)
             self.h = None
 
     def __del__(self):
