@@ -183,3 +183,36 @@ def fixture_eps(N, density=0.01, valences=(3, 5, 6), displace=0.05, seed=2000):
     """N x N faces with seeded EPs (density = fraction of interior vertices)."""
     mesh, P = ep_mesh(N, density, valences, seed)
     return build_fixture(mesh, P, displace, seed)
+
+
+# ---------------------------------------------------------------- surfaces (2-manifolds in 3-D)
+# The spline space is the planar one; only the control points gain a third coordinate, so
+# the surface is x(eta) = sum_j ctrl_j N_j in R^3 (Section 4.1 treats such surfaces).
+
+def rotate_to_3d(F, angles=(0.3, -0.5, 0.7)):
+    """The planar domain placed in 3-D by a rotation (about z, y, x in turn): a plane
+    whose geometry is the planar one, for invariance checks."""
+    az, ay, ax = angles
+    Rz = np.array([[np.cos(az), -np.sin(az), 0], [np.sin(az), np.cos(az), 0], [0, 0, 1]])
+    Ry = np.array([[np.cos(ay), 0, np.sin(ay)], [0, 1, 0], [-np.sin(ay), 0, np.cos(ay)]])
+    Rx = np.array([[1, 0, 0], [0, np.cos(ax), -np.sin(ax)], [0, np.sin(ax), np.cos(ax)]])
+    Rot = Rx @ Ry @ Rz
+    G = dict(F)
+    c = np.asarray(F["ctrl"], dtype=np.float64)
+    G["ctrl"] = np.ascontiguousarray(np.hstack([c, np.zeros((len(c), 1))]) @ Rot.T)
+    G["rotation"] = Rot
+    return G
+
+
+def fixture_dome(F, radius=1.5):
+    """The planar domain lifted onto a sphere of the given radius centred above the
+    domain's centre: control point (x, y) -> (x, y, sqrt(radius^2 - |(x, y) - centre|^2)),
+    a spherical cap (the spline surface through those control points is close to it).
+    With fixture_half_strip as the base: a curved 2-EP surface patch."""
+    G = dict(F)
+    c = np.asarray(F["ctrl"], dtype=np.float64)
+    ctr = 0.5 * (c.min(axis=0) + c.max(axis=0))
+    r2 = np.sum((c - ctr) ** 2, axis=1)
+    assert np.all(r2 < radius * radius), "radius too small for the domain"
+    G["ctrl"] = np.ascontiguousarray(np.hstack([c, np.sqrt(radius * radius - r2)[:, None]]))
+    return G

@@ -281,7 +281,13 @@ def eval_cell(fx, f, k, eta, fn_subset=None):
     N11 = Ce @ T(s1, b2)
     N12 = Ce @ T(d1, d2)
     N22 = Ce @ T(b1, s2)
-    P = fx["ctrl"][fn]  # (m, 2)
+    P = fx["ctrl"][fn]  # (m, 2), or (m, 3) for a surface
+    if P.shape[1] == 3:
+        out = _eval_surface(fn, P, N, N1, N2, N11, N12, N22)
+        if fn_subset is None:
+            return out
+        sel = np.array([int(np.nonzero(fn == j)[0][0]) for j in fn_subset], dtype=np.int64)
+        return (fn[sel], out[1][sel], out[2][sel], out[3][sel], out[4][sel], out[5], out[6], out[7][sel])
     x = P.T @ N
     J = np.stack([P.T @ N1, P.T @ N2], axis=1)  # J[a, b] = d x_a / d eta_b
     detJ = np.linalg.det(J)
@@ -300,14 +306,46 @@ def eval_cell(fx, f, k, eta, fn_subset=None):
     return (fn[sel], N[sel], grad[0][sel], grad[1][sel], lap[sel], x, detJ)
 
 
+def is_surface(fx):
+    """A 2-manifold in 3-D: control points with three coordinates (Section 4.1)."""
+    return np.asarray(fx["ctrl"]).shape[1] == 3
+
+
+def _eval_surface(fn, P, N, N1, N2, N11, N12, N22):
+    """Eqs. (13)-(17) on a parametric surface x(eta) = sum_j P_j N_j in R^3: tangent
+    vectors a_a = dx/deta_a, metric g_ab = a_a . a_b, area element sqrt(det g); the
+    surface gradient grad_s N = g^{ab} (dN/deta_b) a_a (three components) and the
+    Laplace-Beltrami operator Delta_s N = g^{ab} (d2N/deta_a deta_b - Gamma^c_ab dN/deta_c)
+    with Gamma^c_ab = g^{cd} a_d . d2x/deta_a deta_b. For a plane they reduce to the
+    planar gradient and Laplacian. Returns (fn, N, Nx, Ny, LB, x, sqrt(det g), Nz)."""
+    x = P.T @ N
+    A = np.stack([P.T @ N1, P.T @ N2], axis=1)  # (3, 2): columns a_1, a_2
+    g = A.T @ A
+    gi = np.linalg.inv(g)
+    sg = math.sqrt(np.linalg.det(g))
+    dN = np.stack([N1, N2])  # (2, m)
+    grad = A @ (gi @ dN)  # (3, m)
+    Xh = {(0, 0): P.T @ N11, (0, 1): P.T @ N12, (1, 1): P.T @ N22}
+    Xh[(1, 0)] = Xh[(0, 1)]
+    Hn = {(0, 0): N11, (0, 1): N12, (1, 0): N12, (1, 1): N22}
+    lb = np.zeros(len(fn))
+    for a in range(2):
+        for b in range(2):
+            gam = gi @ (A.T @ Xh[(a, b)])  # Gamma^c_ab, c = 0, 1
+            lb += gi[a, b] * (Hn[(a, b)] - gam[0] * N1 - gam[1] * N2)
+    return (fn, N, grad[0], grad[1], lb, x, sg, grad[2])
+
+
 def wq_points(fx, cl):
     """Basis/geometry at every WQ point, per cell: dict with fn (the cell's nonzero
-    functions), N, Nx, Ny, Lap (npts x m), x (npts x 2), detJ (npts)."""
+    functions), N, Nx, Ny (and Nz on a surface: the surface gradient), Lap (the
+    Laplacian, or the Laplace-Beltrami operator on a surface) (npts x m), x (npts x 2 or
+    3), detJ (npts; sqrt(det g) on a surface)."""
     data = []
     for c in range(len(cl["elem"])):
         f, k = int(cl["elem"][c]), int(cl["sub"][c])
         rows = [eval_cell(fx, f, k, eta, cl["funcs"][c]) for eta in cl["eta"][c]]
-        data.append({
+        d = {
             "fn": cl["funcs"][c],
             "N": np.array([r[1] for r in rows]),
             "Nx": np.array([r[2] for r in rows]),
@@ -315,7 +353,10 @@ def wq_points(fx, cl):
             "Lap": np.array([r[4] for r in rows]),
             "x": np.array([r[5] for r in rows]),
             "detJ": np.array([r[6] for r in rows]),
-        })
+        }
+        if len(rows[0]) > 7:
+            d["Nz"] = np.array([r[7] for r in rows])
+        data.append(d)
     return data
 
 
@@ -354,19 +395,22 @@ def gauss4():
 def gq_matrices(fx, cl, coef=None):
     """Element-wise Gauss assembly (4x4 points per Bezier cell, i.e. 4x4x4 for a split
     element) of M = int N_i N_j, Kx = int dxN_i dxN_j, Ky = int dyN_i dyN_j and
-    B = int Lap N_i Lap N_j (scipy CSR, n x n). coef(x) optionally multiplies every
+    B = int Lap N_i Lap N_j (scipy CSR, n x n); on a surface also Kz, with the surface
+    gradient and the Laplace-Beltrami operator. coef(x) optionally multiplies every
     integrand."""
     gp, gw = gauss4()
     n = fx["n_fn"]
     R, Cc = [], []
-    V = {k: [] for k in ("M", "Kx", "Ky", "B")}
+    surf = is_surface(fx)
+    V = {k: [] for k in (("M", "Kx", "Ky", "Kz", "B") if surf else ("M", "Kx", "Ky", "B"))}
     for c in range(len(cl["elem"])):
         f, k = int(cl["elem"][c]), int(cl["sub"][c])
         for bq in range(4):
             for aq in range(4):
-                fn, N, Nx, Ny, Lap, x, detJ = eval_cell(fx, f, k, (gp[aq], gp[bq]), cl["funcs"][c])
+                ev = eval_cell(fx, f, k, (gp[aq], gp[bq]), cl["funcs"][c])
+                fn, N, Nx, Ny, Lap, x, detJ = ev[:7]
                 # derivatives are w.r.t. the cell coordinate eta: |detJ| d eta is the
-                # area element on the cell
+                # area element on the cell (sqrt(det g) on a surface)
                 wq = gw[aq] * gw[bq] * abs(detJ)
                 if coef is not None:
                     wq *= coef(x)
@@ -377,6 +421,8 @@ def gq_matrices(fx, cl, coef=None):
                 V["Kx"].append((wq * np.outer(Nx, Nx)).reshape(-1))
                 V["Ky"].append((wq * np.outer(Ny, Ny)).reshape(-1))
                 V["B"].append((wq * np.outer(Lap, Lap)).reshape(-1))
+                if surf:
+                    V["Kz"].append((wq * np.outer(ev[7], ev[7])).reshape(-1))
     R = np.concatenate(R)
     Cc = np.concatenate(Cc)
     return {k: sp.csr_matrix((np.concatenate(v), (R, Cc)), shape=(n, n)) for k, v in V.items()}
@@ -392,9 +438,12 @@ def gauss_data(fx, cl):
         f, k = int(cl["elem"][c]), int(cl["sub"][c])
         rows = [eval_cell(fx, f, k, (gp[aq], gp[bq]), cl["funcs"][c]) for bq in range(4) for aq in range(4)]
         wts = np.array([gw[aq] * gw[bq] for bq in range(4) for aq in range(4)])
-        out.append({"fn": cl["funcs"][c], "N": np.array([r[1] for r in rows]), "Nx": np.array([r[2] for r in rows]),
-                    "Ny": np.array([r[3] for r in rows]), "x": np.array([r[5] for r in rows]),
-                    "w": wts * np.abs(np.array([r[6] for r in rows]))})
+        d = {"fn": cl["funcs"][c], "N": np.array([r[1] for r in rows]), "Nx": np.array([r[2] for r in rows]),
+             "Ny": np.array([r[3] for r in rows]), "x": np.array([r[5] for r in rows]),
+             "w": wts * np.abs(np.array([r[6] for r in rows]))}
+        if len(rows[0]) > 7:
+            d["Nz"] = np.array([r[7] for r in rows])
+        out.append(d)
     return out
 
 
@@ -414,6 +463,8 @@ def gq_assemble(fx, gdata, kind, coef=None):
                 E += wq[g] * np.outer(d["N"][g], d["N"][g])
             else:
                 E += wq[g] * (np.outer(d["Nx"][g], d["Nx"][g]) + np.outer(d["Ny"][g], d["Ny"][g]))
+                if "Nz" in d:
+                    E += wq[g] * np.outer(d["Nz"][g], d["Nz"][g])
         ii, jj = np.meshgrid(d["fn"], d["fn"], indexing="ij")
         R.append(ii.reshape(-1))
         Cc.append(jj.reshape(-1))
@@ -425,9 +476,9 @@ def gq_assemble(fx, gdata, kind, coef=None):
 # O6  Weights by truncated SVD (Section 4.3, Eqs. (19)-(22); Section 2 Eqs. (5)-(6))
 # ----------------------------------------------------------------------------------
 
-FAMILIES = ("mass", "x", "y", "lap")
-_FAM_KEY = {"mass": "N", "x": "Nx", "y": "Ny", "lap": "Lap"}
-_FAM_GQ = {"mass": "M", "x": "Kx", "y": "Ky", "lap": "B"}
+FAMILIES = ("mass", "x", "y", "lap", "z")
+_FAM_KEY = {"mass": "N", "x": "Nx", "y": "Ny", "lap": "Lap", "z": "Nz"}
+_FAM_GQ = {"mass": "M", "x": "Kx", "y": "Ky", "lap": "B", "z": "Kz"}
 
 
 def local_matrix(fx, pat, data, i, key):
@@ -511,6 +562,8 @@ def wq_assemble(fx, pat, data, W, kind, coef_pts=None, rows=None):
     vals = np.zeros(len(pat["col"]))
     terms = {"mass": [("mass", "N")], "stiffness": [("x", "Nx"), ("y", "Ny")],
              "biharmonic": [("lap", "Lap")]}[kind]
+    if kind == "stiffness" and is_surface(fx):  # the third surface-gradient component
+        terms = terms + [("z", "Nz")]
     for i in rows:
         q0, q1 = pat["qptr"][i], pat["qptr"][i + 1]
         c = np.ones(q1 - q0) if coef_pts is None else coef_pts[pat["qidx"][q0:q1]]
