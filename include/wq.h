@@ -46,7 +46,7 @@ typedef enum {
 
 /* Weight families (bit mask): exactness for N_j, dN_j/dx, dN_j/dy, Lap N_j
  * (Eq. (9), the two planar terms of Eq. (11), Eq. (12)). */
-typedef enum { WQ_FAM_MASS = 1, WQ_FAM_DX = 2, WQ_FAM_DY = 4, WQ_FAM_LAP = 8 } wq_family;
+typedef enum { WQ_FAM_MASS = 1, WQ_FAM_DX = 2, WQ_FAM_DY = 4, WQ_FAM_LAP = 8, WQ_FAM_DZ = 16 } wq_family;
 
 /* Arithmetic of the row contraction. FP64 everywhere else, always. */
 typedef enum { WQ_FP64 = 0, WQ_SPLIT_FP16 = 1, WQ_SPLIT_BF16 = 2, WQ_SLICED_FP16 = 3 } wq_precision;
@@ -62,7 +62,11 @@ typedef enum { WQ_FP64 = 0, WQ_SPLIT_FP16 = 1, WQ_SPLIT_BF16 = 2, WQ_SLICED_FP16
  *   coef      [.]     per face nsub x m_f x 16 Bernstein coefficients, index k + 4 l
  *                     (k along corner0->corner1); nsub = 4 if split (sub-element
  *                     sx + 2 sy covers [sx/2,(sx+1)/2] x [sy/2,(sy+1)/2]), else 1
- *   ctrl      [n_fn*2] control points; the geometry map is x = sum_j ctrl_j N_j
+ *   ctrl      [n_fn*dim] control points; the geometry map is x = sum_j ctrl_j N_j
+ *   dim       2: a planar domain; 3: a 2-manifold in 3-D (Section 4.1): gradients are
+ *             surface gradients with a third component (family WQ_FAM_DZ), the
+ *             Laplacian is the Laplace-Beltrami operator and det J is sqrt(det g).
+ *             0 is read as 2.
  * Faces touching the boundary are passive (zero parametric area) and carry m_f = 0. */
 typedef struct {
   int32_t nv, nf, n_fn;
@@ -73,6 +77,7 @@ typedef struct {
   const int64_t* coef_ptr;
   const double* coef;
   const double* ctrl;
+  int32_t dim;
 } wq_mesh_desc;
 
 wq_status wq_mesh_create(const wq_mesh_desc* desc, wq_mesh** out);
@@ -108,7 +113,7 @@ wq_status build_points_with_s(wq_mesh* mesh, const uint8_t* s_host, int want_lap
  *   WQ_ARR_QPTR     int64[n+1]   WQ_ARR_QIDX  int32[sum r_i]
  *   WQ_ARR_ETYPE    uint8[nf]  (0 passive, 1 regular, 2 boundary, 3 irregular, 4 transition)
  *   WQ_ARR_S        uint8[nf]    points per direction (0: passive)
- *   WQ_ARR_X        double[2*np] WQ_ARR_DETJ double[np]
+ *   WQ_ARR_X        double[dim*np] WQ_ARR_DETJ double[np] (sqrt(det g) on a surface)
  * wq_points_size() returns the element count of each array. */
 typedef enum {
   WQ_ARR_ROW_PTR = 0, WQ_ARR_COL = 1, WQ_ARR_QPTR = 2, WQ_ARR_QIDX = 3,
@@ -200,8 +205,10 @@ wq_status assemble_mass_stiffness(const wq_points* pts, const wq_weights* w, con
  *   gradients, Laplacians when want_laplacian, which needs build_points(want_laplacian=1)),
  *   the weights w_g |det J| and the physical points; synchronises `stream`.
  * wq_gauss_size: the number of Gauss points (16 per cell); wq_gauss_get_x copies their
- *   coordinates (device double[2 * size], x then y per point, cell-major, 4 x 4 points
- *   per cell with the first cell coordinate fastest).
+ *   coordinates (device double[dim * size], the mesh's dim coordinates per point,
+ *   cell-major, 4 x 4 points per cell with the first cell coordinate fastest).
+ *   On a surface (dim 3) the stiffness sums the three surface-gradient components and
+ *   the biharmonic kind uses the Laplace-Beltrami operator.
  * assemble_gauss: vals (device double[nnz], aligned with COL) :=
  *   WQ_GQ_MASS:       sum_cells sum_g w_g |det J| c_g N_i N_j
  *   WQ_GQ_STIFFNESS:  sum_cells sum_g w_g |det J| c_g grad N_i . grad N_j

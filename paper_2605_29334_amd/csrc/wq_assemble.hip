@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(WAVE)
 
 template <int K>
 wq_status launch(const wq_points* P, const wq_weights* w, Src S, double* o0, double* o1, hipStream_t st,
-                 bool timed = true) {
+                 bool timed = true, bool zterm = false) {
   constexpr int N = Fam<K>::N;
   constexpr int NACC = Fam<K>::NACC;
   const int nzcap = (P->t2_maxnz + 1) & ~1;
@@ -391,7 +391,10 @@ wq_status launch(const wq_points* P, const wq_weights* w, Src S, double* o0, dou
   const int64_t lim = (int64_t)OOB;
   WQ_CHECK(P->n_basis * 8 < lim && sum_r * 8 < lim && P->n_points * 8 < lim && (int64_t)P->t2_slot.bytes < lim,
            WQ_EINVAL, "assemble: mesh too large for one launch (2 GiB per array); split it");
-  if (K == 0) {
+  if (K == 0 && zterm) {  // the third surface-gradient term of a surface stiffness
+    S.D[0] = P->DZ.as<double>();
+    S.W[0] = w->W[4].as<double>();
+  } else if (K == 0) {
     S.D[0] = P->DN.as<double>();
     S.W[0] = w->W[0].as<double>();
   } else if (K == 1) {
@@ -419,7 +422,8 @@ wq_status launch(const wq_points* P, const wq_weights* w, Src S, double* o0, dou
   for (int a = 0; a < 2; ++a) nc += S.C[a] ? 1 : 0;
   if (K >= 4) nc = 1 + Fam<K>::NPF;  // k and the point fields
   const int64_t outb = K >= 4 ? P->nnz + P->n_rows : NACC * P->nnz;
-  KTimer tm(timed ? names[K] : nullptr, 8 * (2 * N * sum_r + nc * P->n_points + outb), timed ? st : nullptr);
+  KTimer tm(timed ? (zterm ? "k_assemble_stiffness_z" : names[K]) : nullptr,
+            8 * (2 * N * sum_r + nc * P->n_points + outb), timed ? st : nullptr);
   if (P->n_t2 > 0)
     k_asm_mfma<K><<<(unsigned)(per_xcd * NXCD), WAVE, lds, st>>>(
         P->n_t2, chunk, nzcap, entcap, P->t2_row0.as<int32_t>(), P->t2_eptr.as<int64_t>(), P->t2_ent.as<int4>(),
@@ -882,6 +886,35 @@ wq_status dispatch(const wq_points* P, const wq_weights* w, const double* c0, co
   return launch_split<K, WQ_SLICED_FP16>(P, w, c0, c1, (float*)o0, (float*)o1, st);
 }
 
+__global__ void k_add(double* v, const double* z, int64_t n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) v[t] += z[t];
+}
+
+// On a surface the stiffness has a third gradient family: its weights are needed, and the
+// low-precision contractions, which carry two derivative families, do not apply.
+wq_status surface_check(const wq_points* P, const wq_weights* w, wq_precision prec) {
+  if (P->mesh->dim != 3) return WQ_OK;
+  WQ_CHECK(w->fam_mask & WQ_FAM_DZ, WQ_EINVAL, "assemble: a surface stiffness needs the d/dz weights (WQ_FAM_DZ)");
+  WQ_CHECK(prec == WQ_FP64, WQ_EINVAL, "assemble: surface stiffness is FP64 only");
+  return WQ_OK;
+}
+
+// Surface stiffness: K += sum_q k_q w^z_iq dN_j/dz (the same kernel as the mass matrix,
+// on the third gradient family), into scratch held by the points handle, then added.
+wq_status add_zterm(const wq_points* P, const wq_weights* w, const double* k, double* kv, hipStream_t st) {
+  if (P->mesh->dim != 3) return WQ_OK;
+  wq_points* Pm = const_cast<wq_points*>(P);
+  if (Pm->zterm_ws.bytes < (size_t)P->nnz * sizeof(double)) {
+    dfree(Pm->zterm_ws);
+    WQ_TRY(dalloc_n<double>(Pm->zterm_ws, (size_t)P->nnz));
+  }
+  WQ_TRY(launch<0>(P, w, src_coef(k, nullptr), Pm->zterm_ws.as<double>(), nullptr, st, true, true));
+  if (P->nnz > 0) k_add<<<nblocks(P->nnz, 256), 256, 0, st>>>(kv, Pm->zterm_ws.as<double>(), P->nnz);
+  WQ_HIP(hipGetLastError());
+  return WQ_OK;
+}
+
 }  // namespace
 
 extern "C" wq_status assemble_mass(const wq_points* P, const wq_weights* w, const double* c, void* vals,
@@ -893,7 +926,9 @@ extern "C" wq_status assemble_mass(const wq_points* P, const wq_weights* w, cons
 extern "C" wq_status assemble_stiffness(const wq_points* P, const wq_weights* w, const double* k, void* vals,
                                         wq_precision prec, wq_stream stream) {
   WQ_TRY(check(P, w, WQ_FAM_DX | WQ_FAM_DY, vals, prec));
-  return dispatch<1>(P, w, k, nullptr, vals, nullptr, prec, (hipStream_t)stream);
+  WQ_TRY(surface_check(P, w, prec));
+  WQ_TRY(dispatch<1>(P, w, k, nullptr, vals, nullptr, prec, (hipStream_t)stream));
+  return add_zterm(P, w, k, (double*)vals, (hipStream_t)stream);
 }
 
 extern "C" wq_status assemble_biharmonic(const wq_points* P, const wq_weights* w, const double* d, void* vals,
@@ -908,7 +943,9 @@ extern "C" wq_status assemble_mass_stiffness(const wq_points* P, const wq_weight
                                              wq_stream stream) {
   WQ_TRY(check(P, w, WQ_FAM_MASS | WQ_FAM_DX | WQ_FAM_DY, mv, prec));
   WQ_CHECK(kv, WQ_EINVAL, "assemble_mass_stiffness: null stiffness output");
-  return dispatch<3>(P, w, c, k, mv, kv, prec, (hipStream_t)stream);
+  WQ_TRY(surface_check(P, w, prec));
+  WQ_TRY(dispatch<3>(P, w, c, k, mv, kv, prec, (hipStream_t)stream));
+  return add_zterm(P, w, k, (double*)kv, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------------ no-allocation scratch
@@ -956,6 +993,7 @@ wq_status tangent_impl(const wq_points* P, const wq_weights* w, const double* T,
 wq_status tangent_check(const wq_points* P, const wq_weights* w, const double* T, const double* Tdot,
                         double inv_theta_dt, wq_conductivity k, void* S_vals, double* R, wq_precision prec) {
   WQ_TRY(check(P, w, WQ_FAM_MASS | WQ_FAM_DX | WQ_FAM_DY, S_vals, prec));
+  WQ_CHECK(P->mesh->dim == 2, WQ_EINVAL, "assemble_tangent: the heat tangent is planar (dim 2)");
   WQ_CHECK(prec == WQ_FP64, WQ_EINVAL, "assemble_tangent: the Newton tangent and residual are FP64 only");
   WQ_CHECK(T && Tdot && R, WQ_EINVAL, "assemble_tangent: null T, Tdot or R");
   WQ_CHECK(k.kind >= WQ_K_LINEAR && k.kind <= WQ_K_SIN, WQ_EINVAL, "assemble_tangent: unknown conductivity kind");

@@ -42,6 +42,7 @@ extern "C" wq_status wq_batch_create(const wq_mesh_desc* meshes, int32_t n_meshe
     WQ_CHECK(d.nv > 0 && d.nf > 0 && d.n_fn > 0 && d.face_vtx && d.split && d.ext_ptr && d.ext_fn && d.coef_ptr &&
                  d.coef && d.ctrl,
              WQ_EINVAL, "wq_batch_create: incomplete mesh " + std::to_string(k));
+    WQ_CHECK(d.dim == 0 || d.dim == 2, WQ_EINVAL, "wq_batch_create: planar meshes only (mesh " + std::to_string(k) + ")");
     nv += d.nv;
     nf += d.nf;
     nfn += d.n_fn;

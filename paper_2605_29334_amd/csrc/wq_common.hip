@@ -202,6 +202,8 @@ extern "C" wq_status wq_mesh_create(const wq_mesh_desc* d, wq_mesh** out) {
   WQ_CHECK(d->nv > 0 && d->nf > 0 && d->n_fn > 0, WQ_EINVAL, "wq_mesh_create: empty mesh");
   WQ_CHECK(d->face_vtx && d->split && d->ext_ptr && d->ext_fn && d->coef_ptr && d->coef && d->ctrl,
            WQ_EINVAL, "wq_mesh_create: null array");
+  const int dim = d->dim == 0 ? 2 : d->dim;
+  WQ_CHECK(dim == 2 || dim == 3, WQ_EINVAL, "wq_mesh_create: dim must be 2 or 3");
   // host-side validation of the descriptor (cheap, O(size))
   for (int64_t i = 0; i < 4LL * d->nf; ++i)
     WQ_CHECK(d->face_vtx[i] >= 0 && d->face_vtx[i] < d->nv, WQ_EINVAL, "face_vtx out of range");
@@ -222,6 +224,7 @@ extern "C" wq_status wq_mesh_create(const wq_mesh_desc* d, wq_mesh** out) {
   m->nv = d->nv;
   m->nf = d->nf;
   m->n_fn = d->n_fn;
+  m->dim = dim;
   m->n_ext = d->ext_ptr[d->nf];
   m->n_coef = d->coef_ptr[d->nf];
   m->h_ext_ptr.assign(d->ext_ptr, d->ext_ptr + d->nf + 1);
@@ -232,7 +235,7 @@ extern "C" wq_status wq_mesh_create(const wq_mesh_desc* d, wq_mesh** out) {
   if (s == WQ_OK) s = upload(m->ext_fn, d->ext_fn, (size_t)m->n_ext);
   if (s == WQ_OK) s = upload(m->coef_ptr, d->coef_ptr, (size_t)d->nf + 1);
   if (s == WQ_OK) s = upload(m->coef, d->coef, (size_t)m->n_coef);
-  if (s == WQ_OK) s = upload(m->ctrl, d->ctrl, 2 * (size_t)d->n_fn);
+  if (s == WQ_OK) s = upload(m->ctrl, d->ctrl, (size_t)dim * d->n_fn);
   if (s != WQ_OK) {
     release_mesh(m);
     delete m;

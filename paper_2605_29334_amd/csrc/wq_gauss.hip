@@ -11,7 +11,8 @@ struct wq_gauss {
   wq_points* pts = nullptr;
   int has_lap = 0;
   // basis at the 16 Gauss points of every cell, point-major per cell like the WQ data
-  DBuf GN, GX, GY, GL, gw /*[16 ncell]*/, gx /*[2 x 16 ncell]*/;
+  DBuf GN, GX, GY, GZ /*surfaces*/, GL, gw /*[16 ncell]*/, gx /*[dim x 16 ncell]*/;
+  int dim = 2;
   // per (cell, cell function a): the CSR offset of the row of function a and the offset of
   // the slot map of the (row, cell) pair, so that entry (a, b) of the cell's local matrix
   // goes to vals[pbase + slot[pslot + b]]
@@ -59,9 +60,9 @@ __global__ void k_zero(double* v, int64_t n) {
 // B[l / 16][l % 16]: the same basis entry, once weighted), D[4 v + l / 16][l % 16] in
 // result register v. Every entry is added into the CSR values with an FP64 atomic, so
 // the order of the additions, and with it the last bits, varies between runs.
-template <int NT>  // terms of the integrand: 1 or 2
+template <int NT>  // terms of the integrand: 1, 2 or 3 (the gradient components)
 __global__ void __launch_bounds__(64) k_gq_assemble(const int64_t* cfn_ptr, const double* G0, const double* G1,
-                                                    const double* gw, const double* coef, const int64_t* pbase,
+                                                    const double* G2, const double* gw, const double* coef, const int64_t* pbase,
                                                     const int64_t* pslot, const uint8_t* slot, double* vals) {
   const int32_t c = blockIdx.x;
   const int lane = threadIdx.x;
@@ -74,7 +75,7 @@ __global__ void __launch_bounds__(64) k_gq_assemble(const int64_t* cfn_ptr, cons
     const int g = 4 * s + gq;
     W[s] = gw[16 * (int64_t)c + g] * (coef ? coef[16 * (int64_t)c + g] : 1.0);
   }
-  const double* Gt[2] = {G0 + 16 * f0, G1 ? G1 + 16 * f0 : nullptr};
+  const double* Gt[3] = {G0 + 16 * f0, G1 ? G1 + 16 * f0 : nullptr, G2 ? G2 + 16 * f0 : nullptr};
   const int nt = (m + 15) / 16;
   for (int ta = 0; ta < nt; ++ta) {
     const int a = 16 * ta + col;
@@ -112,20 +113,22 @@ extern "C" wq_status gauss_setup(wq_mesh* M, wq_points* P, int want_laplacian, w
   wq_gauss* g = new wq_gauss();
   g->pts = P;
   g->has_lap = want_laplacian != 0;
+  g->dim = M->dim;
   const size_t ng = 16 * (size_t)P->n_cfn;
   wq_status s = dalloc_n<double>(g->GN, ng);
   if (s == WQ_OK) s = dalloc_n<double>(g->GX, ng);
   if (s == WQ_OK) s = dalloc_n<double>(g->GY, ng);
+  if (s == WQ_OK && g->dim == 3) s = dalloc_n<double>(g->GZ, ng);
   if (s == WQ_OK && g->has_lap) s = dalloc_n<double>(g->GL, ng);
   if (s == WQ_OK) s = dalloc_n<double>(g->gw, 16 * (size_t)P->ncell);
-  if (s == WQ_OK) s = dalloc_n<double>(g->gx, 32 * (size_t)P->ncell);
+  if (s == WQ_OK) s = dalloc_n<double>(g->gx, 16 * (size_t)g->dim * P->ncell);
   if (s == WQ_OK) s = dalloc_n<int64_t>(g->pbase, (size_t)P->n_cfn);
   if (s == WQ_OK) s = dalloc_n<int64_t>(g->pslot, (size_t)P->n_cfn);
   DBuf bad;
   if (s == WQ_OK) s = dalloc_n<int>(bad, 1);
   if (s == WQ_OK && hipMemsetAsync(bad.p, 0, sizeof(int), st) != hipSuccess) s = WQ_EDEVICE;
   if (s == WQ_OK)
-    s = gauss_basis(M, P, g->GN.as<double>(), g->GX.as<double>(), g->GY.as<double>(),
+    s = gauss_basis(M, P, g->GN.as<double>(), g->GX.as<double>(), g->GY.as<double>(), g->GZ.as<double>(),
                     g->has_lap ? g->GL.as<double>() : nullptr, g->gw.as<double>(), g->gx.as<double>(), st);
   if (s == WQ_OK && P->ncell > 0) {
     k_gq_pairs<<<P->ncell, 64, 0, st>>>(P->ncell, P->cfn_ptr.as<int64_t>(), P->cfn.as<int32_t>(),
@@ -153,7 +156,7 @@ extern "C" wq_status gauss_setup(wq_mesh* M, wq_points* P, int want_laplacian, w
 
 extern "C" void wq_gauss_destroy(wq_gauss* g) {
   if (!g) return;
-  for (DBuf* b : {&g->GN, &g->GX, &g->GY, &g->GL, &g->gw, &g->gx, &g->pbase, &g->pslot}) dfree(*b);
+  for (DBuf* b : {&g->GN, &g->GX, &g->GY, &g->GZ, &g->GL, &g->gw, &g->gx, &g->pbase, &g->pslot}) dfree(*b);
   delete g;
 }
 
@@ -187,12 +190,15 @@ extern "C" wq_status assemble_gauss(const wq_gauss* g, wq_gauss_kind kind, const
   const int64_t* pb = g->pbase.as<int64_t>();
   const int64_t* ps = g->pslot.as<int64_t>();
   const uint8_t* sl = P->slot.as<uint8_t>();
-  if (kind == WQ_GQ_STIFFNESS)
-    k_gq_assemble<2><<<P->ncell, 64, 0, st>>>(cp, g->GX.as<double>(), g->GY.as<double>(), g->gw.as<double>(),
-                                              coef_at_gauss, pb, ps, sl, vals);
+  if (kind == WQ_GQ_STIFFNESS && g->dim == 3)
+    k_gq_assemble<3><<<P->ncell, 64, 0, st>>>(cp, g->GX.as<double>(), g->GY.as<double>(), g->GZ.as<double>(),
+                                              g->gw.as<double>(), coef_at_gauss, pb, ps, sl, vals);
+  else if (kind == WQ_GQ_STIFFNESS)
+    k_gq_assemble<2><<<P->ncell, 64, 0, st>>>(cp, g->GX.as<double>(), g->GY.as<double>(), nullptr,
+                                              g->gw.as<double>(), coef_at_gauss, pb, ps, sl, vals);
   else
     k_gq_assemble<1><<<P->ncell, 64, 0, st>>>(
-        cp, kind == WQ_GQ_MASS ? g->GN.as<double>() : g->GL.as<double>(), nullptr, g->gw.as<double>(),
+        cp, kind == WQ_GQ_MASS ? g->GN.as<double>() : g->GL.as<double>(), nullptr, nullptr, g->gw.as<double>(),
         coef_at_gauss, pb, ps, sl, vals);
   tm.stop();
   WQ_HIP(hipGetLastError());

@@ -227,6 +227,7 @@ extern "C" wq_status wq_heat_step(const wq_points* P, const wq_weights* w, const
                                   const uint8_t* dirichlet, const double* g_next, const double* f_at_pts, double* T,
                                   double* Tdot, double* S_vals, wq_heat_report* rep, wq_stream stream) {
   WQ_CHECK(P && w && hp && dirichlet && T && Tdot && S_vals, WQ_EINVAL, "wq_heat_step: null argument");
+  WQ_CHECK(P->mesh->dim == 2, WQ_EINVAL, "wq_heat_step: the heat solve is planar (dim 2)");
   WQ_CHECK(hp->dt > 0 && hp->theta > 0 && hp->theta <= 1 && hp->tol > 0 && hp->max_newton >= 0 && hp->max_cg > 0 &&
                (hp->tangent == WQ_TANGENT_SYMMETRIC || hp->tangent == WQ_TANGENT_EXACT),
            WQ_EINVAL, "wq_heat_step: bad parameters");

@@ -59,6 +59,7 @@ enum : uint8_t { ET_PASSIVE = 0, ET_REGULAR = 1, ET_BOUNDARY = 2, ET_IRREGULAR =
 struct wq_mesh {
   int device = 0;
   int32_t nv = 0, nf = 0, n_fn = 0;
+  int32_t dim = 2;  // coordinates per control point: 2 (planar) or 3 (surface)
   int64_t n_ext = 0, n_coef = 0;
   wq::DBuf face_vtx, split, ext_ptr, ext_fn, coef_ptr, coef, ctrl;
   // host copies needed by the (rare) min-max fallback of Eq. (18)
@@ -101,11 +102,14 @@ struct wq_points {
   wq::DBuf t2_row0 /*int32 [n_t2+1]*/, t2_eptr /*int64 [n_t2+1]*/, t2_ent /*int4*/, t2_slot /*uint8*/;
   // per point
   wq::DBuf x /*double [2 np]*/, detJ /*double [np]*/;
-  // per (cell, point, cell function)
-  wq::DBuf DN, DX, DY, DL;
+  // per (cell, point, cell function); DZ only on a surface (third gradient component),
+  // where DL holds the Laplace-Beltrami operator
+  wq::DBuf DN, DX, DY, DZ, DL;
   // scratch owned by the handle, allocated on first use: tangent point fields
   // (4 x n_points doubles) and the Newton / PCG vectors of wq_heat_step
   wq::DBuf tangent_ws, newton_ws;
+  // scratch for the third gradient term of a surface stiffness (nnz doubles, first use)
+  wq::DBuf zterm_ws;
   // basis data split for the low-precision contraction (built on first use):
   // FP16 x 2: uint32 per value (hi | lo << 16) of D * 2^-ds_exp[f];
   // BF16 x 3: uint2 per value (hi | mid << 16, lo)
@@ -117,15 +121,15 @@ struct wq_points {
 struct wq_weights {
   wq_points* pts = nullptr;
   unsigned fam_mask = 0;
-  wq::DBuf W[4];    // weights per family, aligned with qidx
-  wq::DBuf rhs[4];  // Gauss right-hand sides per family, aligned with col
+  wq::DBuf W[5];    // weights per family (mass, dx, dy, lap, dz), aligned with qidx
+  wq::DBuf rhs[5];  // Gauss right-hand sides per family, aligned with col
 };
 
 // ------------------------------------------------------------------ device helpers
 namespace wq {
 
 __host__ __device__ inline int fam_index(unsigned fam) {
-  return fam == WQ_FAM_MASS ? 0 : fam == WQ_FAM_DX ? 1 : fam == WQ_FAM_DY ? 2 : 3;
+  return fam == WQ_FAM_MASS ? 0 : fam == WQ_FAM_DX ? 1 : fam == WQ_FAM_DY ? 2 : fam == WQ_FAM_LAP ? 3 : 4;
 }
 
 // cubic Bernstein values and derivatives
@@ -169,10 +173,58 @@ constexpr int T2_NZCAP = 416;  // CSR entries per cell-major tile (8 rows of 52;
 // 64-bit index launch helper
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Geometry of a 2-manifold in 3-D at one point (Section 4.1, Eqs. (13)-(17) on a surface):
+// from the tangent vectors a_1, a_2 (columns of A) and the second derivatives x_11, x_12,
+// x_22 (columns of X2), the area element sqrt(det g), the inverse metric and the
+// Christoffel coefficients Gamma^c_ab = g^{cd} a_d . x_ab.
+struct SurfGeom {
+  double A[3][2];
+  double gi00, gi01, gi11;
+  double sg;
+  double gam[2][3];  // [c][ab], ab = 11, 12, 22
+};
+__device__ inline SurfGeom surf_geom(const double A[3][2], const double X2[3][3]) {
+  SurfGeom G;
+  for (int a = 0; a < 3; ++a) {
+    G.A[a][0] = A[a][0];
+    G.A[a][1] = A[a][1];
+  }
+  const double g00 = A[0][0] * A[0][0] + A[1][0] * A[1][0] + A[2][0] * A[2][0];
+  const double g01 = A[0][0] * A[0][1] + A[1][0] * A[1][1] + A[2][0] * A[2][1];
+  const double g11 = A[0][1] * A[0][1] + A[1][1] * A[1][1] + A[2][1] * A[2][1];
+  const double det = g00 * g11 - g01 * g01;
+  G.sg = sqrt(det);
+  const double id = 1.0 / det;
+  G.gi00 = g11 * id;
+  G.gi01 = -g01 * id;
+  G.gi11 = g00 * id;
+  for (int ab = 0; ab < 3; ++ab) {
+    const double t0 = A[0][0] * X2[0][ab] + A[1][0] * X2[1][ab] + A[2][0] * X2[2][ab];
+    const double t1 = A[0][1] * X2[0][ab] + A[1][1] * X2[1][ab] + A[2][1] * X2[2][ab];
+    G.gam[0][ab] = G.gi00 * t0 + G.gi01 * t1;
+    G.gam[1][ab] = G.gi01 * t0 + G.gi11 * t1;
+  }
+  return G;
+}
+// Surface gradient g^{ab} N_b a_a (three components) and Laplace-Beltrami operator
+// g^{ab} (N_ab - Gamma^c_ab N_c) of a function with parametric derivatives v = (N, N_1,
+// N_2, N_11, N_12, N_22).
+__device__ inline void surf_basis(const SurfGeom& G, const double v[6], double* gr, double* lb) {
+  const double c0 = G.gi00 * v[1] + G.gi01 * v[2];
+  const double c1 = G.gi01 * v[1] + G.gi11 * v[2];
+  for (int a = 0; a < 3; ++a) gr[a] = G.A[a][0] * c0 + G.A[a][1] * c1;
+  const double h00 = v[3] - G.gam[0][0] * v[1] - G.gam[1][0] * v[2];
+  const double h01 = v[4] - G.gam[0][1] * v[1] - G.gam[1][1] * v[2];
+  const double h11 = v[5] - G.gam[0][2] * v[1] - G.gam[1][2] * v[2];
+  *lb = G.gi00 * h00 + 2.0 * G.gi01 * h01 + G.gi11 * h11;
+}
+
 // Basis data at the 4 x 4 Gauss points of every cell (values, physical gradients, Laplacians
 // when GL is given; point-major per cell like the WQ data), gw = Gauss weight * |det J|, and
-// the physical points when gx is given. Asynchronous on st.
-wq_status gauss_basis(wq_mesh* M, wq_points* P, double* GN, double* GX, double* GY, double* GL, double* gw,
-                      double* gx, hipStream_t st);
+// the physical points when gx is given (dim coordinates per point). On a surface also GZ
+// (the third surface-gradient component) and GL holds the Laplace-Beltrami operator.
+// Asynchronous on st.
+wq_status gauss_basis(wq_mesh* M, wq_points* P, double* GN, double* GX, double* GY, double* GZ, double* GL,
+                      double* gw, double* gx, hipStream_t st);
 
 }  // namespace wq

@@ -388,7 +388,7 @@ __global__ void k_basis(int64_t npts_total, int32_t ncell, const int64_t* cell_p
                         const uint8_t* cell_sub, const uint8_t* s, const uint8_t* split, const int64_t* ext_ptr,
                         const int64_t* coef_ptr, const double* coef, const double* ctrl, const int64_t* cfn_ptr,
                         const int32_t* cfn, const uint8_t* cfn_loc, const int64_t* dptr, double* X, double* DJ,
-                        double* DN, double* DX, double* DY, double* DL, int* bad_jac) {
+                        double* DN, double* DX, double* DY, double* DZ, double* DL, int dim, int* bad_jac) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= npts_total) return;
   int lo = 0, hi = ncell - 1;  // cell holding point p
@@ -410,6 +410,39 @@ __global__ void k_basis(int64_t npts_total, int32_t ncell, const int64_t* cell_p
   const double* Cf = coef + coef_ptr[f] + (int64_t)sub * mf * 16;
   const int64_t f0 = cfn_ptr[c];
   const int m = (int)(cfn_ptr[c + 1] - f0);
+  if (dim == 3) {  // a surface: tangent vectors, metric, surface gradient, Laplace-Beltrami
+    double x3[3] = {0, 0, 0}, A[3][2] = {{0, 0}, {0, 0}, {0, 0}}, X2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int k = 0; k < m; ++k) {
+      double v[6];
+      eval_fn(Cf + 16 * (int)cfn_loc[f0 + k], b1, d1, s1, b2, d2, s2, v);
+      const int32_t j = cfn[f0 + k];
+      for (int a = 0; a < 3; ++a) {
+        const double P = ctrl[3 * (int64_t)j + a];
+        x3[a] += P * v[0];
+        A[a][0] += P * v[1];
+        A[a][1] += P * v[2];
+        X2[a][0] += P * v[3];
+        X2[a][1] += P * v[4];
+        X2[a][2] += P * v[5];
+      }
+    }
+    const SurfGeom G = surf_geom(A, X2);
+    for (int a = 0; a < 3; ++a) X[3 * p + a] = x3[a];
+    DJ[p] = G.sg;
+    if (!(G.sg > 0.0)) atomicOr(bad_jac, 1);
+    const int64_t o = dptr[c] + (int64_t)lp * m;
+    for (int k = 0; k < m; ++k) {
+      double v[6], gr[3], lb;
+      eval_fn(Cf + 16 * (int)cfn_loc[f0 + k], b1, d1, s1, b2, d2, s2, v);
+      surf_basis(G, v, gr, &lb);
+      DN[o + k] = v[0];
+      DX[o + k] = gr[0];
+      DY[o + k] = gr[1];
+      DZ[o + k] = gr[2];
+      if (DL) DL[o + k] = lb;
+    }
+    return;
+  }
   // geometry: x = sum P_j N_j, J = dx/deta, H_eta x
   double x[2] = {0, 0}, J[2][2] = {{0, 0}, {0, 0}}, H[2][3] = {{0, 0, 0}, {0, 0, 0}};
   for (int k = 0; k < m; ++k) {
@@ -617,7 +650,8 @@ void release_points(wq_points* P) {
   dfree(P->cfn_ptr); dfree(P->cfn); dfree(P->cfn_loc); dfree(P->dptr); dfree(P->supp_ptr);
   dfree(P->supp_cell); dfree(P->row_ptr); dfree(P->col); dfree(P->qptr); dfree(P->qidx);
   dfree(P->soff); dfree(P->slot); dfree(P->kself); dfree(P->x); dfree(P->detJ);
-  dfree(P->DN); dfree(P->DX); dfree(P->DY); dfree(P->DL);
+  dfree(P->DN); dfree(P->DX); dfree(P->DY); dfree(P->DZ); dfree(P->DL);
+  dfree(P->zterm_ws);
   dfree(P->tile_eptr); dfree(P->tile_ent); dfree(P->tile_mem);
   dfree(P->t2_row0); dfree(P->t2_eptr); dfree(P->t2_ent); dfree(P->t2_slot);
   dfree(P->tangent_ws); dfree(P->newton_ws);
@@ -988,11 +1022,12 @@ wq_status build_points_impl(wq_mesh* M, int want_lap, const uint8_t* s_host, hip
       P->max_cell_m = hf[1];
       P->max_cell_np = hf[2];
     }
-    if (s == WQ_OK) s = dalloc_n<double>(P->x, 2 * P->n_points);
+    if (s == WQ_OK) s = dalloc_n<double>(P->x, (size_t)M->dim * P->n_points);
     if (s == WQ_OK) s = dalloc_n<double>(P->detJ, P->n_points);
     if (s == WQ_OK) s = dalloc_n<double>(P->DN, P->n_basis);
     if (s == WQ_OK) s = dalloc_n<double>(P->DX, P->n_basis);
     if (s == WQ_OK) s = dalloc_n<double>(P->DY, P->n_basis);
+    if (s == WQ_OK && M->dim == 3) s = dalloc_n<double>(P->DZ, P->n_basis);
     if (s == WQ_OK && want_lap) s = dalloc_n<double>(P->DL, P->n_basis);
     if (s == WQ_OK && hipMemsetAsync(flags.p, 0, 8 * sizeof(int), st) != hipSuccess) s = WQ_EDEVICE;
     if (s == WQ_OK) {
@@ -1002,14 +1037,15 @@ wq_status build_points_impl(wq_mesh* M, int want_lap, const uint8_t* s_host, hip
           P->s.as<uint8_t>(), M->split.as<uint8_t>(), M->ext_ptr.as<int64_t>(), M->coef_ptr.as<int64_t>(),
           M->coef.as<double>(), M->ctrl.as<double>(), P->cfn_ptr.as<int64_t>(), P->cfn.as<int32_t>(),
           P->cfn_loc.as<uint8_t>(), P->dptr.as<int64_t>(), P->x.as<double>(), P->detJ.as<double>(),
-          P->DN.as<double>(), P->DX.as<double>(), P->DY.as<double>(), want_lap ? P->DL.as<double>() : nullptr,
-          flags.as<int>());
+          P->DN.as<double>(), P->DX.as<double>(), P->DY.as<double>(), P->DZ.as<double>(),
+          want_lap ? P->DL.as<double>() : nullptr, M->dim, flags.as<int>());
       tm.stop();
       if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
     }
     if (s == WQ_OK) s = sync_flags(flags, hf, 1, st);
     if (s == WQ_OK && hf[0]) {
-      set_error("build_points: det J <= 0 at some point (geometry map not orientation-preserving)");
+      set_error(M->dim == 3 ? "build_points: a degenerate surface point (det g <= 0)"
+                            : "build_points: det J <= 0 at some point (geometry map not orientation-preserving)");
       s = WQ_EINVAL;
     }
     dfree(npm);
@@ -1063,7 +1099,7 @@ extern "C" int64_t wq_points_size(const wq_points* P, wq_array what) {
     case WQ_ARR_COL: return P->nnz;
     case WQ_ARR_QIDX: return (int64_t)(P->qidx.bytes / sizeof(int32_t));
     case WQ_ARR_ETYPE: case WQ_ARR_S: return P->mesh->nf;
-    case WQ_ARR_X: return 2 * P->n_points;
+    case WQ_ARR_X: return (int64_t)P->mesh->dim * P->n_points;
     case WQ_ARR_DETJ: return P->n_points;
   }
   return -1;

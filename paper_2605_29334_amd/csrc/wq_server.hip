@@ -304,6 +304,7 @@ extern "C" wq_status wq_server_submit(wq_server* sv, const wq_request* q, double
   WQ_CHECK(d.nf > 0 && d.n_fn > 0 && d.face_vtx && d.split && d.ext_ptr && d.ext_fn && d.coef_ptr && d.coef && d.ctrl &&
                q->dirichlet,
            WQ_EINVAL, "wq_server_submit: incomplete request");
+  WQ_CHECK(d.dim == 0 || d.dim == 2, WQ_EINVAL, "wq_server_submit: the heat solve is planar (dim 2)");
   WQ_CHECK(q->n_steps >= 0 && q->heat.dt > 0 && q->heat.theta > 0 && q->heat.theta <= 1, WQ_EINVAL,
            "wq_server_submit: bad time stepping");
   Request* r = new Request();

@@ -11,6 +11,7 @@ namespace {
 
 constexpr int BS = 256;
 constexpr int GQ_GROUP = 16;   // lanes per row in the Gauss row kernel
+constexpr int NFAM = 5;        // weight families: mass, d/dx, d/dy, Laplacian, d/dz (bit f of a mask)
 constexpr int MAX_SWEEPS = 40;
 
 // 4-point Gauss-Legendre on [0, 1]
@@ -42,11 +43,13 @@ __device__ inline void eval_fn(const double* C, const double b1[4], const double
 
 // Basis data at the 16 Gauss points of every cell: G?[c*16*? ...] laid out like the WQ
 // data (point-major, cell functions contiguous), plus gw = weight * |det J| and, when gx is
-// given, the physical points (x, y) at gx[2 (16 c + g)].
+// given, the physical points at gx[dim (16 c + g) ..]. On a surface (dim 3) GX, GY, GZ hold
+// the surface gradient and GL the Laplace-Beltrami operator.
 __global__ void k_gauss_basis(int32_t ncell, const int32_t* cell_face, const uint8_t* cell_sub,
                               const int64_t* ext_ptr, const int64_t* coef_ptr, const double* coef,
                               const double* ctrl, const int64_t* cfn_ptr, const int32_t* cfn, const uint8_t* cfn_loc,
-                              double* GN, double* GX, double* GY, double* GL, double* gw, double* gx) {
+                              double* GN, double* GX, double* GY, double* GZ, double* GL, double* gw, double* gx,
+                              int dim) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= 16LL * ncell) return;
   const int64_t c = t / 16;
@@ -60,6 +63,39 @@ __global__ void k_gauss_basis(int32_t ncell, const int32_t* cell_face, const uin
   const double* Cf = coef + coef_ptr[f] + (int64_t)sub * mf * 16;
   const int64_t f0 = cfn_ptr[c];
   const int m = (int)(cfn_ptr[c + 1] - f0);
+  if (dim == 3) {  // a surface
+    double x3[3] = {0, 0, 0}, A[3][2] = {{0, 0}, {0, 0}, {0, 0}}, X2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int k = 0; k < m; ++k) {
+      double v[6];
+      eval_fn(Cf + 16 * (int)cfn_loc[f0 + k], b1, d1, s1, b2, d2, s2, v);
+      const int32_t j = cfn[f0 + k];
+      for (int a = 0; a < 3; ++a) {
+        const double P = ctrl[3 * (int64_t)j + a];
+        x3[a] += P * v[0];
+        A[a][0] += P * v[1];
+        A[a][1] += P * v[2];
+        X2[a][0] += P * v[3];
+        X2[a][1] += P * v[4];
+        X2[a][2] += P * v[5];
+      }
+    }
+    const SurfGeom SG = surf_geom(A, X2);
+    gw[16 * c + g] = c_gw[g % 4] * c_gw[g / 4] * SG.sg;
+    if (gx)
+      for (int a = 0; a < 3; ++a) gx[3 * (16 * c + g) + a] = x3[a];
+    const int64_t o = 16 * f0 + (int64_t)g * m;
+    for (int k = 0; k < m; ++k) {
+      double v[6], gr[3], lb;
+      eval_fn(Cf + 16 * (int)cfn_loc[f0 + k], b1, d1, s1, b2, d2, s2, v);
+      surf_basis(SG, v, gr, &lb);
+      GN[o + k] = v[0];
+      GX[o + k] = gr[0];
+      GY[o + k] = gr[1];
+      GZ[o + k] = gr[2];
+      if (GL) GL[o + k] = lb;
+    }
+    return;
+  }
   double J[2][2] = {{0, 0}, {0, 0}}, H[2][3] = {{0, 0, 0}, {0, 0, 0}}, X[2] = {0, 0};
   for (int k = 0; k < m; ++k) {
     double v[6];
@@ -114,17 +150,17 @@ __global__ void k_gauss_basis(int32_t ncell, const int32_t* cell_face, const uin
 __global__ void k_gauss_rows(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cfn_ptr,
                              const int64_t* soff, const uint8_t* slot, const uint8_t* kself, const int64_t* row_ptr,
                              const double* G0, const double* G1, const double* G2, const double* G3,
-                             const double* gw, unsigned mask, int max_row, double* R0, double* R1, double* R2,
-                             double* R3) {
+                             const double* G4, const double* gw, unsigned mask, int max_row, double* R0, double* R1,
+                             double* R2, double* R3, double* R4) {
   extern __shared__ double sh_acc[];
   const int grp = threadIdx.x / GQ_GROUP;
   const int lane = threadIdx.x % GQ_GROUP;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / GQ_GROUP) + grp;
   const int nfam = __popc(mask);
   double* acc = sh_acc + (size_t)grp * nfam * max_row;
-  double* su = sh_acc + (size_t)(blockDim.x / GQ_GROUP) * nfam * max_row + grp * 4 * GQ_GROUP;
-  const double* Gs[4] = {G0, G1, G2, G3};
-  double* Rs[4] = {R0, R1, R2, R3};
+  double* su = sh_acc + (size_t)(blockDim.x / GQ_GROUP) * nfam * max_row + grp * NFAM * GQ_GROUP;
+  const double* Gs[NFAM] = {G0, G1, G2, G3, G4};
+  double* Rs[NFAM] = {R0, R1, R2, R3, R4};
   const bool active = i < n;
   for (int t = lane; t < nfam * max_row; t += GQ_GROUP) acc[t] = 0.0;
   __syncthreads();
@@ -135,7 +171,7 @@ __global__ void k_gauss_rows(int64_t n, const int64_t* sptr, const int32_t* scel
       const int m = (int)(cfn_ptr[c + 1] - f0);
       const int ks = kself[p];
       const uint8_t* sl = slot + soff[p];
-      for (int fam = 0, a = 0; fam < 4; ++fam) {
+      for (int fam = 0, a = 0; fam < NFAM; ++fam) {
         if (!(mask & (1u << fam))) continue;
         su[a * GQ_GROUP + lane] = gw[16 * (int64_t)c + lane] * Gs[fam][16 * f0 + lane * m + ks];
         ++a;
@@ -145,7 +181,7 @@ __global__ void k_gauss_rows(int64_t n, const int64_t* sptr, const int32_t* scel
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int k = lane; k < m; k += GQ_GROUP) {
         const int sk = sl[k];
-        for (int fam = 0, a = 0; fam < 4; ++fam) {
+        for (int fam = 0, a = 0; fam < NFAM; ++fam) {
           if (!(mask & (1u << fam))) continue;
           const double* G = Gs[fam] + 16 * f0;
           const double* u = su + a * GQ_GROUP;
@@ -163,7 +199,7 @@ __global__ void k_gauss_rows(int64_t n, const int64_t* sptr, const int32_t* scel
   __syncthreads();
   if (active) {
     const int ni = (int)(row_ptr[i + 1] - row_ptr[i]);
-    for (int fam = 0, a = 0; fam < 4; ++fam) {
+    for (int fam = 0, a = 0; fam < NFAM; ++fam) {
       if (!(mask & (1u << fam))) continue;
       for (int t = lane; t < ni; t += GQ_GROUP) Rs[fam][row_ptr[i] + t] = acc[a * max_row + t];
       ++a;
@@ -311,10 +347,10 @@ struct TsvdArgs {
   const uint8_t* kself;
   const int64_t* row_ptr;
   const int64_t* qptr;
-  const double* D[4];    // basis data of each family of the launch
-  const double* DN;      // values (for Z)
-  const double* rhs[4];  // Gauss right-hand side of each family, aligned with col
-  double* W[4];          // output weights of each family, aligned with qidx
+  const double* D[NFAM];    // basis data of each family of the launch
+  const double* DN;         // values (for Z)
+  const double* rhs[NFAM];  // Gauss right-hand side of each family, aligned with col
+  double* W[NFAM];          // output weights of each family, aligned with qidx
   int* max_sweeps;
   unsigned long long* min_kept;     // bits of a double
   unsigned long long* max_dropped;  // bits of a double
@@ -1523,7 +1559,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
 
 
 void release_weights(wq_weights* w) {
-  for (int f = 0; f < 4; ++f) {
+  for (int f = 0; f < NFAM; ++f) {
     dfree(w->W[f]);
     dfree(w->rhs[f]);
   }
@@ -1531,13 +1567,13 @@ void release_weights(wq_weights* w) {
 
 }  // namespace
 
-wq_status wq::gauss_basis(wq_mesh* M, wq_points* P, double* GN, double* GX, double* GY, double* GL, double* gw,
-                          double* gx, hipStream_t st) {
+wq_status wq::gauss_basis(wq_mesh* M, wq_points* P, double* GN, double* GX, double* GY, double* GZ, double* GL,
+                          double* gw, double* gx, hipStream_t st) {
   KTimer tm("k_gauss_basis", 16LL * P->ncell, st);
   k_gauss_basis<<<nblocks(16LL * P->ncell, BS), BS, 0, st>>>(
       P->ncell, P->cell_face.as<int32_t>(), P->cell_sub.as<uint8_t>(), M->ext_ptr.as<int64_t>(),
       M->coef_ptr.as<int64_t>(), M->coef.as<double>(), M->ctrl.as<double>(), P->cfn_ptr.as<int64_t>(),
-      P->cfn.as<int32_t>(), P->cfn_loc.as<uint8_t>(), GN, GX, GY, GL, gw, gx);
+      P->cfn.as<int32_t>(), P->cfn_loc.as<uint8_t>(), GN, GX, GY, GZ, GL, gw, gx, M->dim);
   tm.stop();
   return hipGetLastError() == hipSuccess ? WQ_OK : WQ_EDEVICE;
 }
@@ -1545,7 +1581,9 @@ wq_status wq::gauss_basis(wq_mesh* M, wq_points* P, double* GN, double* GX, doub
 extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, double tau, wq_stream stream,
                                    wq_weights** out, wq_solve_report* rep) {
   WQ_CHECK(M && P && out && P->mesh == M, WQ_EINVAL, "solve_weights: bad arguments");
-  WQ_CHECK(fam_mask && !(fam_mask & ~15u), WQ_EINVAL, "solve_weights: bad family mask");
+  WQ_CHECK(fam_mask && !(fam_mask & ~31u), WQ_EINVAL, "solve_weights: bad family mask");
+  WQ_CHECK(!(fam_mask & WQ_FAM_DZ) || M->dim == 3, WQ_EINVAL,
+           "solve_weights: the d/dz family exists on surfaces (dim 3) only");
   WQ_CHECK(!(fam_mask & WQ_FAM_LAP) || P->has_lap, WQ_EINVAL,
            "solve_weights: Laplacian weights need build_points(want_laplacian=1)");
   WQ_CHECK(tau > 0.0 && tau < 1.0, WQ_EINVAL, "solve_weights: cutoff must be in (0,1)");
@@ -1556,21 +1594,21 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   w->fam_mask = fam_mask;
   wq_status s = WQ_OK;
   // Gauss data
-  DBuf G[4], gw;
+  DBuf G[NFAM], gw;
   const int64_t ng = 16 * P->n_cfn;
-  for (int f = 0; f < 4 && s == WQ_OK; ++f)
-    if (f < 3 || (fam_mask & WQ_FAM_LAP)) s = dalloc_n<double>(G[f], ng);
+  for (int f = 0; f < NFAM && s == WQ_OK; ++f)
+    if (f < 3 || (fam_mask & (1u << f)) || (f == 4 && M->dim == 3)) s = dalloc_n<double>(G[f], ng);
   if (s == WQ_OK) s = dalloc_n<double>(gw, 16 * (size_t)P->ncell);
   if (s == WQ_OK)
-    s = gauss_basis(M, P, G[0].as<double>(), G[1].as<double>(), G[2].as<double>(),
+    s = gauss_basis(M, P, G[0].as<double>(), G[1].as<double>(), G[2].as<double>(), G[4].as<double>(),
                     (fam_mask & WQ_FAM_LAP) ? G[3].as<double>() : nullptr, gw.as<double>(), nullptr, st);
-  for (int f = 0; f < 4 && s == WQ_OK; ++f)
+  for (int f = 0; f < NFAM && s == WQ_OK; ++f)
     if (fam_mask & (1u << f)) s = dalloc_n<double>(w->rhs[f], P->nnz);
   if (s == WQ_OK) {
     const int rows_per_block = BS / GQ_GROUP;
     int nfam = 0;
-    for (int f = 0; f < 4; ++f) nfam += (fam_mask >> f) & 1;
-    const size_t lds = (size_t)rows_per_block * (nfam * P->max_row + 4 * GQ_GROUP) * sizeof(double);
+    for (int f = 0; f < NFAM; ++f) nfam += (fam_mask >> f) & 1;
+    const size_t lds = (size_t)rows_per_block * (nfam * P->max_row + NFAM * GQ_GROUP) * sizeof(double);
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute((const void*)k_gauss_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
             hipSuccess)
@@ -1579,8 +1617,9 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     if (s == WQ_OK) k_gauss_rows<<<nblocks(n, rows_per_block), BS, lds, st>>>(
         n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(), P->cfn_ptr.as<int64_t>(), P->soff.as<int64_t>(),
         P->slot.as<uint8_t>(), P->kself.as<uint8_t>(), P->row_ptr.as<int64_t>(), G[0].as<double>(),
-        G[1].as<double>(), G[2].as<double>(), G[3].as<double>(), gw.as<double>(), fam_mask, P->max_row,
-        w->rhs[0].as<double>(), w->rhs[1].as<double>(), w->rhs[2].as<double>(), w->rhs[3].as<double>());
+        G[1].as<double>(), G[2].as<double>(), G[3].as<double>(), G[4].as<double>(), gw.as<double>(), fam_mask,
+        P->max_row, w->rhs[0].as<double>(), w->rhs[1].as<double>(), w->rhs[2].as<double>(), w->rhs[3].as<double>(),
+        w->rhs[4].as<double>());
     tm.stop();
     if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
   }
@@ -1637,14 +1676,14 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   // one launch per size bucket covers every family asked for (more workgroups per launch,
   // fewer partly idle tails)
   int nfam = 0;
-  const double* famD[4] = {nullptr, nullptr, nullptr, nullptr};
-  const double* famR[4] = {nullptr, nullptr, nullptr, nullptr};
-  double* famW[4] = {nullptr, nullptr, nullptr, nullptr};
-  for (int f = 0; f < 4 && s == WQ_OK; ++f) {
+  const double* famD[NFAM] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const double* famR[NFAM] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* famW[NFAM] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int f = 0; f < NFAM && s == WQ_OK; ++f) {
     if (!(fam_mask & (1u << f))) continue;
     s = dalloc_n<double>(w->W[f], (size_t)(P->qidx.bytes / sizeof(int32_t)));
     famD[nfam] = f == 0 ? P->DN.as<double>() : f == 1 ? P->DX.as<double>() : f == 2 ? P->DY.as<double>()
-                                                                                  : P->DL.as<double>();
+                 : f == 3 ? P->DL.as<double>() : P->DZ.as<double>();
     famR[nfam] = w->rhs[f].as<double>();
     famW[nfam] = w->W[f].as<double>();
     ++nfam;
@@ -1663,7 +1702,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   base.kself = P->kself.as<uint8_t>();
   base.row_ptr = P->row_ptr.as<int64_t>();
   base.qptr = P->qptr.as<int64_t>();
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NFAM; ++q) {
     base.D[q] = famD[q];
     base.rhs[q] = famR[q];
     base.W[q] = famW[q];
@@ -1828,7 +1867,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   if (s == WQ_OK && hipMemcpyAsync(&hrep, drep.p, sizeof(Rep), hipMemcpyDeviceToHost, st) != hipSuccess)
     s = WQ_EDEVICE;
   if (s == WQ_OK && hipStreamSynchronize(st) != hipSuccess) s = WQ_EDEVICE;
-  for (int f = 0; f < 4; ++f) dfree(G[f]);
+  for (int f = 0; f < NFAM; ++f) dfree(G[f]);
   dfree(gw);
   dfree(bkt);
   dfree(lists);
@@ -1850,7 +1889,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   }
   if (rep) {
     int nf = 0;
-    for (int f = 0; f < 4; ++f) nf += (fam_mask >> f) & 1;
+    for (int f = 0; f < NFAM; ++f) nf += (fam_mask >> f) & 1;
     rep->systems = n * nf;
     rep->truncated = (int64_t)hrep.truncated;
     rep->certified = (int64_t)hrep.certified;

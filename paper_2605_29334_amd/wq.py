@@ -15,7 +15,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwq.so")
 
-WQ_FAM_MASS, WQ_FAM_DX, WQ_FAM_DY, WQ_FAM_LAP = 1, 2, 4, 8
+WQ_FAM_MASS, WQ_FAM_DX, WQ_FAM_DY, WQ_FAM_LAP, WQ_FAM_DZ = 1, 2, 4, 8, 16
 WQ_FP64, WQ_SPLIT_FP16, WQ_SPLIT_BF16, WQ_SLICED_FP16 = 0, 1, 2, 3
 ARR_ROW_PTR, ARR_COL, ARR_QPTR, ARR_QIDX, ARR_ETYPE, ARR_S, ARR_X, ARR_DETJ = range(8)
 _ARR_DTYPE = {ARR_ROW_PTR: torch.int64, ARR_COL: torch.int32, ARR_QPTR: torch.int64, ARR_QIDX: torch.int32,
@@ -32,7 +32,8 @@ class WQError(RuntimeError):
 class MeshDesc(C.Structure):
     _fields_ = [("nv", C.c_int32), ("nf", C.c_int32), ("n_fn", C.c_int32),
                 ("face_vtx", C.c_void_p), ("split", C.c_void_p), ("ext_ptr", C.c_void_p),
-                ("ext_fn", C.c_void_p), ("coef_ptr", C.c_void_p), ("coef", C.c_void_p), ("ctrl", C.c_void_p)]
+                ("ext_fn", C.c_void_p), ("coef_ptr", C.c_void_p), ("coef", C.c_void_p), ("ctrl", C.c_void_p),
+                ("dim", C.c_int32)]
 
 
 class Timing(C.Structure):
@@ -180,12 +181,13 @@ class Mesh:
         k = self._keep
         d = MeshDesc(int(fx["nv"]), int(len(k["face_vtx"])), int(fx["n_fn"]),
                      *[C.c_void_p(k[n].ctypes.data) for n in ("face_vtx", "split", "ext_ptr", "ext_fn",
-                                                              "coef_ptr", "coef", "ctrl")])
+                                                              "coef_ptr", "coef", "ctrl")], int(k["ctrl"].shape[1]))
         h = C.c_void_p()
         _check(_lib().wq_mesh_create(C.byref(d), C.byref(h)), "wq_mesh_create")
         self.h = h
         self.nf = len(k["face_vtx"])
         self.n_fn = int(fx["n_fn"])
+        self.dim = int(k["ctrl"].shape[1])
 
     def close(self):
         if self.h:
@@ -288,10 +290,11 @@ class Gauss:
                "gauss_setup")
         self.h = h
         self.points = points
+        self.dim = mesh.dim
         self.size = int(_lib().wq_gauss_size(h))
 
     def x(self, stream=None):
-        out = torch.empty(2 * self.size, dtype=torch.float64, device="cuda")
+        out = torch.empty(self.dim * self.size, dtype=torch.float64, device="cuda")
         _check(_lib().wq_gauss_get_x(self.h, _ptr(out), _stream(stream)), "wq_gauss_get_x")
         return out
 
@@ -430,7 +433,7 @@ def _mesh_desc(fx, keep):
     })
     return MeshDesc(int(fx["nv"]), int(len(keep["face_vtx"])), int(fx["n_fn"]),
                     *[C.c_void_p(keep[n].ctypes.data) for n in ("face_vtx", "split", "ext_ptr", "ext_fn", "coef_ptr",
-                                                                "coef", "ctrl")])
+                                                                "coef", "ctrl")], int(keep["ctrl"].shape[1]))
 
 
 class Server:
