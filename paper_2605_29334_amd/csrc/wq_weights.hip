@@ -1242,22 +1242,25 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
 
 
 // ---------------------------------------------------------------------------------
-// One wave per weight system, for systems of at most 64 constraints and 64 points (the
-// rows of regular cells and most of their neighbours). Lane l holds a column of the
-// factorised matrix in registers, one double per point, so the Householder steps need no
-// cross-lane reductions: the reflector's column is broadcast through LDS and every lane
-// forms its own dot product and update. The steps are those of the certified path of
-// k_tsvd2 (the kept count proved from the pivoted QR of A^T), with the second factorisation
-// by Householder instead of CGS2:
+// Register-resident solver for systems of at most 64 constraints and 64 RW points: RW
+// waves per system, wave v holding points [64 v, 64 v + 64) of every column of the
+// factorised matrix (lane l: column l), one double per point in registers. The
+// Householder steps broadcast the reflector's column through LDS and every lane forms its
+// own partial dot product and update; with RW > 1 the partial dot products and squared
+// norms of the waves are summed through LDS in wave order (the same bits in every wave).
+// The steps are those of the certified path of k_tsvd2 (the kept count proved from the
+// pivoted QR of A^T), with the second factorisation by Householder instead of CGS2:
 //  1. pivoted Householder QR of A^T, stopped once the trailing block is negligible;
 //  2. the rank proof (||R11^-1||_F from R11^-T, one column per lane);
 //  3. Householder QR of X = Z A_k^T (the k pivot rows of A, re-read from the basis blocks);
 //  4. y = R^-T b_k, u = Q [y; 0] (the reflectors applied in reverse), w = Z u, and one
 //     step of iterative refinement on the residual of the k kept equations.
+// Rows above the current step are zero in the broadcast column, so the passes skip the
+// blocks of 16 rows that lie wholly above it (a uniform branch; the sums are unchanged,
+// the skipped terms being exact zeros).
 // A system the proof does not cover is appended to a list for k_tsvd2 (the Jacobi SVD).
-constexpr int WR = 64;     // points (rows) held per lane
-constexpr int WMAXC = 40;  // support cells of a row in the gather tables
-
+constexpr int WR = 64;  // points (rows) held per lane and wave
+constexpr int WB = 16;  // rows per skipped block
 
 // Largest (value, lane) of the wave, ties to the smaller lane: the same in every lane.
 __device__ inline void wave_argmax64(double v, int i, double& bv, int& bi) {
@@ -1281,16 +1284,24 @@ __device__ inline double wave_sum64(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_wsolve(TsvdArgs a) {
-  __shared__ double vb[WR + 4];  // the current reflector's column (4 zero pads past the rows)
-  __shared__ double zv[WR], bv[WR], beta[WR], ib[WR], tau2[WR], rv2[WR], uv2[WR];
+template <int RW>
+__global__ void __launch_bounds__(64 * RW) __attribute__((amdgpu_waves_per_eu(3))) k_wsolve(TsvdArgs a) {
+  constexpr int NR = RW * WR;                  // points of the workgroup
+  constexpr int WMAXC = RW == 1 ? 40 : 64;     // support cells of a row in the gather tables
+  __shared__ double vb[NR + 4];  // the current reflector's column (4 zero pads past the rows)
+  __shared__ double zv[NR], bv[WR], beta[WR], ib[WR], tau2[WR], rv2[WR], uv2[WR];
+  __shared__ double xpart[RW > 1 ? 2 * NR : 1];  // per-wave partial sums (dot, norm)
+  __shared__ double hx0;                         // row-j entry of the pivot column
+  __shared__ int flag;
   extern __shared__ double rp[];  // R11 above the diagonal by columns: n_max (n_max - 1) / 2
   __shared__ int64_t cbase[WMAXC];
   __shared__ int cmc[WMAXC];
   __shared__ uint8_t invk[WMAXC * WR];  // local index of row function l in support cell p, 255: none
-  __shared__ uint8_t ptp[WR + 4], ptq[WR + 4];  // support cell and local index of every point
-  __shared__ int pk[WR];                // position -> constraint of the pivoted QR
-  const int lane = threadIdx.x;
+  __shared__ uint8_t ptp[NR + 4], ptq[NR + 4];  // support cell and local index of every point
+  __shared__ int pk[WR];                        // position -> constraint of the pivoted QR
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform in the wave
+  const int r0 = WR * wv;  // first point of this wave
   const int fs = (int)(blockIdx.x / a.nsys);
   const int64_t sys = blockIdx.x - (int64_t)fs * a.nsys;
   const double* AD = a.D[fs];
@@ -1300,15 +1311,29 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
   const int64_t s0 = a.sptr[i];
   const int nc = (int)(a.sptr[i + 1] - s0);
   auto to_svd = [&]() {
-    if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)blockIdx.x;
+    if (threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)blockIdx.x;
   };
-  if (n > WR || n > a.rp_n || r > WR || nc < 1 || nc >= WMAXC) {
+  if (n > WR || n > a.rp_n || r > NR || nc < 1 || nc >= WMAXC) {
     to_svd();
     return;
   }
-  // ---- gather tables (every point belongs to one support cell; np, m <= r, n <= 64).
-  // Rows past r point at a sentinel cell nc whose functions are all absent.
-  {
+  // Sum over the waves of a per-lane partial, in wave order (slot 0: dot products, 1:
+  // norms; a slot is rewritten only after a barrier that follows every read of it).
+  auto xsum = [&](double v, int slot) -> double {
+    if constexpr (RW == 1) {
+      return v;
+    } else {
+      xpart[slot * NR + threadIdx.x] = v;
+      __syncthreads();
+      double s = xpart[slot * NR + lane];
+#pragma unroll
+      for (int w = 1; w < RW; ++w) s += xpart[slot * NR + w * WR + lane];
+      return s;
+    }
+  };
+  // ---- gather tables (every point belongs to one support cell; m <= n <= 64). Points past
+  // r point at a sentinel cell nc whose functions are all absent.
+  if (wv == 0) {
     int moff = 0;
     for (int p = 0; p < nc; ++p) {
       const int32_t c = a.scell[s0 + p];
@@ -1318,10 +1343,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
       invk[p * WR + lane] = 255;
       __builtin_amdgcn_wave_barrier();
       if (lane < mc) invk[p * WR + a.slot[a.soff[s0 + p] + lane]] = (uint8_t)lane;
-      if (lane < np) {
-        ptp[moff + lane] = (uint8_t)p;
-        ptq[moff + lane] = (uint8_t)lane;
-        zv[moff + lane] = a.DN[d0 + (int64_t)lane * mc + a.kself[s0 + p]];
+      for (int q = lane; q < np; q += 64) {
+        ptp[moff + q] = (uint8_t)p;
+        ptq[moff + q] = (uint8_t)q;
+        zv[moff + q] = a.DN[d0 + (int64_t)q * mc + a.kself[s0 + p]];
       }
       if (lane == 0) {
         cbase[p] = d0;
@@ -1334,61 +1359,92 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
       cbase[nc] = cbase[0];
       cmc[nc] = 0;
     }
-    if (lane >= r) {
-      ptp[lane] = (uint8_t)nc;
-      ptq[lane] = 0;
-      zv[lane] = 0.0;
-    }
     if (lane < 4) {  // pads read by the residual loop (rows in fours)
-      ptp[WR + lane] = (uint8_t)nc;
-      ptq[WR + lane] = 0;
-      vb[WR + lane] = 0.0;
+      ptp[NR + lane] = (uint8_t)nc;
+      ptq[NR + lane] = 0;
+      vb[NR + lane] = 0.0;
     }
     if (lane < n) bv[lane] = a.rhs[fs][a.row_ptr[i] + lane];
   }
+  if (r0 + lane >= r) {
+    ptp[r0 + lane] = (uint8_t)nc;
+    ptq[r0 + lane] = 0;
+    zv[r0 + lane] = 0.0;
+  }
   __syncthreads();
-  // Column of A^T for row function fl (every point), times z when zs; zero where !valid.
-  // Branch-free: every lane loads from a valid address and selects away what it does not
-  // have; the loads go out in batches of 16.
+  // This wave's points of the column of A^T for row function fl, times z when zs; zero
+  // where !valid. Branch-free: every lane loads from a valid address and selects away what
+  // it does not have; the loads go out in batches of 16.
   auto gather = [&](int fl, bool valid, bool zs, double(&x)[WR]) {
     const int fq = valid ? fl : 0;
 #pragma unroll
     for (int m = 0; m < WR; ++m) {
-      const int p = ptp[m];
+      const int p = ptp[r0 + m];
       const int kk = invk[p * WR + fq];
       const bool has = valid && kk != 255;
-      const double v = AD[cbase[p] + (int64_t)ptq[m] * cmc[p] + (has ? kk : 0)];
-      x[m] = has ? (zs ? v * zv[m] : v) : 0.0;
+      const double v = AD[cbase[p] + (int64_t)ptq[r0 + m] * cmc[p] + (has ? kk : 0)];
+      x[m] = has ? (zs ? v * zv[r0 + m] : v) : 0.0;
       if ((m & 15) == 15) asm volatile("" ::: "memory");
     }
   };
-  // The pivot column of step j into vb (rows below j zero); returns its row-j entry x0.
-  auto load_pivot = [&](const double(&x)[WR], int j, int p) -> double {
+  // The pivot column (lane p) of step j into vb, rows above j zero. The wave holding row j
+  // keeps its entry x0 in hx0 and sets vb[j] = x0 - R_jj = 1 / rv0 (so v_j = 1 up to
+  // rounding); its own LDS accesses are ordered, the other waves read vb after the barrier.
+  // Blocks wholly above row j are neither written nor read.
+  auto load_pivot = [&](const double(&x)[WR], int j, int p, double s2, double& rjj, double& rv0, double& tj) {
     if (lane == p) {
 #pragma unroll
-      for (int m = 0; m < WR; ++m) vb[m] = x[m];
+      for (int b = 0; b < WR / WB; ++b)
+        if (j < r0 + WB * b + WB) {
+#pragma unroll
+          for (int m = WB * b; m < WB * b + WB; ++m) vb[r0 + m] = x[m];
+        }
     }
-    if (lane < j) vb[lane] = 0.0;
+    if (r0 + lane < j) vb[r0 + lane] = 0.0;
+    if (j >= r0 && j < r0 + WR) {
+      asm volatile("" ::: "memory");
+      const double x0 = vb[j];
+      householder(x0, s2, &rjj, &rv0, &tj);
+      if (lane == 0) {
+        hx0 = x0;
+        vb[j] = x0 - rjj;
+      }
+    }
     __syncthreads();
-    return vb[j];
+    if (j < r0 || j >= r0 + WR) householder(hx0, s2, &rjj, &rv0, &tj);
   };
-  // One Householder step on the lane's column: the reflector I - tj v v^T with v = rv0 vb,
-  // where vb holds the pivot column from row j on, vb[j] = x0 - R_jj = 1 / rv0 (so v_j = 1
-  // up to rounding) and zeros above, so rows above j are left exactly as they are (R
-  // entries). Every pass runs over all rows without a branch (branches around parts of
-  // the column make the compiler keep two versions of it); the new squared norm of the
-  // rows below j selects them.
-  auto reflect = [&](double(&x)[WR], int j, double rv0, double tj) -> double {
+  // This wave's part of v^T x (v = vb, zero above row j).
+  auto dot_part = [&](const double(&x)[WR], int j) -> double {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < WR; ++m) acc[m & 3] = fma(vb[m], x[m], acc[m & 3]);
-    const double sv = tj * rv0 * rv0 * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    for (int b = 0; b < WR / WB; ++b)
+      if (j < r0 + WB * b + WB) {
+#pragma unroll
+        for (int m = WB * b; m < WB * b + WB; ++m) acc[m & 3] = fma(vb[r0 + m], x[m], acc[m & 3]);
+      }
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  };
+  // x -= sv v on this wave's points; returns its part of the squared norm of the rows
+  // below j. Every lane runs it (sv = 0 leaves a column as it is).
+  auto update = [&](double(&x)[WR], int j, double sv) -> double {
     asm volatile("" ::: "memory");  // re-read vb rather than hold 64 more doubles
 #pragma unroll
-    for (int m = 0; m < WR; ++m) x[m] = fma(-sv, vb[m], x[m]);
+    for (int b = 0; b < WR / WB; ++b)
+      if (j < r0 + WB * b + WB) {
+#pragma unroll
+        for (int m = WB * b; m < WB * b + WB; ++m) x[m] = fma(-sv, vb[r0 + m], x[m]);
+      }
     double ns[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < WR; ++m) ns[m & 3] = fma(x[m], m > j ? x[m] : 0.0, ns[m & 3]);
+    for (int b = 0; b < WR / WB; ++b) {
+      if (j < r0 + WB * b) {
+#pragma unroll
+        for (int m = WB * b; m < WB * b + WB; ++m) ns[m & 3] = fma(x[m], x[m], ns[m & 3]);
+      } else if (j < r0 + WB * b + WB) {
+#pragma unroll
+        for (int m = WB * b; m < WB * b + WB; ++m) ns[m & 3] = fma(x[m], r0 + m > j ? x[m] : 0.0, ns[m & 3]);
+      }
+    }
     return (ns[0] + ns[1]) + (ns[2] + ns[3]);
   };
   double x[WR];
@@ -1397,8 +1453,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
   double fro = 0.0;
 #pragma unroll
   for (int m = 0; m < WR; ++m) fro = fma(x[m], x[m], fro);
-  const double fa2 = wave_sum64(fro);
-  double nrm = fro;  // squared norm of the rows from the current step on
+  double nrm = xsum(fro, 1);  // squared norm of the rows from the current step on
+  const double fa2 = wave_sum64(nrm);
   const int kmax = min(n, r);
   int pos = lane < n ? -1 : WR;  // position once pivoted (lanes past n never are)
   double s20 = 0.0, s2stop = 0.0;
@@ -1413,116 +1469,137 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
       s2stop = s2;
       break;
     }
-    const double x0 = load_pivot(x, j, p);
     double rjj, rv0, tj;
-    householder(x0, s2, &rjj, &rv0, &tj);
-    if (lane == 0) vb[j] = x0 - rjj;
+    load_pivot(x, j, p, s2, rjj, rv0, tj);
     if (lane == p) {
-      pk[j] = p;
-      beta[j] = rjj;
+      if (wv == 0) {
+        pk[j] = p;
+        beta[j] = rjj;
+      }
       pos = j;
     }
-    __syncthreads();
-    if (pos < 0) nrm = reflect(x, j, rv0, tj);
-    __syncthreads();
+    const double d = xsum(dot_part(x, j), 0);
+    nrm = xsum(update(x, j, pos < 0 ? tj * rv0 * rv0 * d : 0.0), 1);
   }
   // ---- 2. rank proof: sigma_{k+1} <= ||R22||_F <= sqrt((n - k) s2stop) and sigma_k >=
-  // 1 / ||R11^-1||_F - ||R22||_F (as in k_tsvd2)
+  // 1 / ||R11^-1||_F - ||R22||_F (as in k_tsvd2). R11 lies in the first wave's points.
   const double r22 = kq < kmax ? sqrt((double)(n - kq) * s2stop) : 0.0;
-  if (pos >= 1 && pos < kq) {
-    const int base = pos * (pos - 1) / 2;
+  if (wv == 0) {
+    if (pos >= 1 && pos < kq) {
+      const int base = pos * (pos - 1) / 2;
 #pragma unroll
-    for (int m = 0; m < WR - 1; ++m)
-      if (m < pos) rp[base + m] = x[m];
+      for (int m = 0; m < WR - 1; ++m)
+        if (m < pos) rp[base + m] = x[m];
+    }
+    if (lane < kq) ib[lane] = 1.0 / beta[lane];
   }
-  if (lane < kq) ib[lane] = 1.0 / beta[lane];
   __syncthreads();
   double lo = 0.0;
-  bool fast = false;
-  if (s20 > 0.0 && kq > 0) {
-    // column `lane` of S = R11^-T (lower triangular): S[ii][c] = (delta - sum_{jj < ii}
-    // R[jj][ii] S[jj][c]) / R[ii][ii]; the entries above the diagonal come out zero
-    double t[WR];
-    double tn = 0.0;
+  if (wv == 0) {
+    bool fast = false;
+    if (s20 > 0.0 && kq > 0) {
+      // column `lane` of S = R11^-T (lower triangular): S[ii][c] = (delta - sum_{jj < ii}
+      // R[jj][ii] S[jj][c]) / R[ii][ii]; the entries above the diagonal come out zero
+      double t[WR];
+      double tn = 0.0;
 #pragma unroll
-    for (int ii = 0; ii < WR; ++ii) {
-      if (ii < kq) {  // a uniform branch, not an exit: the loop unrolls fully
-        double sa[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int ii = 0; ii < WR; ++ii) {
+        if (ii < kq) {  // a uniform branch, not an exit: the loop unrolls fully
+          double sa[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int jj = 0; jj < ii; ++jj) {
-          sa[jj & 3] = fma(rp[ii * (ii - 1) / 2 + jj], t[jj], sa[jj & 3]);
-          if ((jj & 15) == 15) asm volatile("" ::: "memory");  // at most 16 loads in flight
+          for (int jj = 0; jj < ii; ++jj) {
+            sa[jj & 3] = fma(rp[ii * (ii - 1) / 2 + jj], t[jj], sa[jj & 3]);
+            if ((jj & 15) == 15) asm volatile("" ::: "memory");  // at most 16 loads in flight
+          }
+          const double v = ((lane == ii ? 1.0 : 0.0) - ((sa[0] + sa[1]) + (sa[2] + sa[3]))) * ib[ii];
+          t[ii] = v;
+          tn = fma(v, v, tn);
         }
-        const double v = ((lane == ii ? 1.0 : 0.0) - ((sa[0] + sa[1]) + (sa[2] + sa[3]))) * ib[ii];
-        t[ii] = v;
-        tn = fma(v, v, tn);
       }
+      lo = 1.0 / sqrt(wave_sum64(tn)) - r22;
+      fast = lo > 100.0 * a.tau * sqrt(fa2);
     }
-    lo = 1.0 / sqrt(wave_sum64(tn)) - r22;
-    fast = lo > 100.0 * a.tau * sqrt(fa2);
+    if (RW > 1 && lane == 0) flag = fast ? 1 : 0;
+    if (RW == 1 && !fast) {
+      to_svd();
+      return;
+    }
   }
-  if (!fast) {
-    to_svd();
-    return;
+  if constexpr (RW > 1) {
+    __syncthreads();
+    if (!flag) {
+      to_svd();
+      return;
+    }
   }
   // ---- 3. Householder QR of X = Z A_k^T (lane c: position c)
   gather(lane < kq ? pk[lane] : 0, lane < kq, true, x);
-  nrm = 0.0;
+  {
+    double nn = 0.0;
 #pragma unroll
-  for (int m = 0; m < WR; ++m) nrm = fma(x[m], x[m], nrm);
+    for (int m = 0; m < WR; ++m) nn = fma(x[m], x[m], nn);
+    nrm = xsum(nn, 1);
+  }
   for (int j = 0; j < kq; ++j) {
-    const double x0 = load_pivot(x, j, j);
     double rjj, rv0, tj;
-    householder(x0, readlane_f64(nrm, j), &rjj, &rv0, &tj);
-    if (lane == 0) {
-      vb[j] = x0 - rjj;
+    load_pivot(x, j, j, readlane_f64(nrm, j), rjj, rv0, tj);
+    if (threadIdx.x == 0) {
       beta[j] = rjj;
       tau2[j] = tj;
       rv2[j] = rv0;
-      uv2[j] = x0 - rjj;
+      uv2[j] = hx0 - rjj;  // x0 - R_jj
     }
-    __syncthreads();
-    if (lane > j && lane < kq) nrm = reflect(x, j, rv0, tj);
-    __syncthreads();
+    const bool act = lane > j && lane < kq;
+    const double d = xsum(dot_part(x, j), 0);
+    nrm = xsum(update(x, j, act ? tj * rv0 * rv0 * d : 0.0), 1);
   }
   // X has full column rank (sigma_k(A) > 0 and z > 0 on the points); R_jj != 0 is checked
-  // anyway before dividing by it
+  // anyway before dividing by it (beta is the same in every wave: the last write precedes
+  // a barrier)
   if (__any(lane < kq && !(fabs(beta[lane]) > 0.0 && fabs(beta[lane]) < INFINITY))) {
     to_svd();
     return;
   }
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     atomicMin(a.min_kept, dbits(lo / sqrt(fa2)));       // a lower bound of sigma_k / sigma_1
     atomicMax(a.max_dropped, dbits(r22 / sqrt(s20)));  // an upper bound of sigma_{k+1} / sigma_1
     if (kq < n) atomicAdd(a.truncated, 1ULL);
     atomicAdd(a.certified, 1ULL);
   }
-  // ---- 4. u = Q [R^-T c; 0] for the right-hand side c (lane c: c_c; result: lane m, row
-  // m). R^-T by columns of R (lane c holds R[0..c-1][c]); Q = H_0 ... H_{k-1} applied to
-  // [y; 0] in reverse, with the reflectors of step 3.
+  // ---- 4. u = Q [R^-T c; 0] for the right-hand side c (lane c of the first wave: c_c;
+  // result: lane m of wave v, point 64 v + m). R^-T by columns of R (lane c of the first
+  // wave holds R[0..c-1][c]); Q = H_0 ... H_{k-1} applied to [y; 0] in reverse, with the
+  // reflectors of step 3.
   auto solve = [&](double cv) -> double {
-    const double id = lane < kq ? 1.0 / beta[lane] : 0.0;
-    double u = 0.0, acc = 0.0;
+    double u = 0.0;
+    if (wv == 0) {
+      const double id = lane < kq ? 1.0 / beta[lane] : 0.0;
+      double acc = 0.0;
 #pragma unroll
-    for (int ii = 0; ii < WR; ++ii) {
-      if (ii < kq) {
-        const double yi = readlane_f64((cv - acc) * id, ii);
-        if (lane == ii) u = yi;
-        acc = fma(x[ii], yi, acc);
+      for (int ii = 0; ii < WR; ++ii) {
+        if (ii < kq) {
+          const double yi = readlane_f64((cv - acc) * id, ii);
+          if (lane == ii) u = yi;
+          acc = fma(x[ii], yi, acc);
+        }
       }
     }
     for (int j = kq - 1; j >= 0; --j) {
       if (lane == j) {
 #pragma unroll
-        for (int m = 0; m < WR; ++m) vb[m] = x[m];
+        for (int b = 0; b < WR / WB; ++b)
+          if (j < r0 + WB * b + WB) {
+#pragma unroll
+            for (int m = WB * b; m < WB * b + WB; ++m) vb[r0 + m] = x[m];
+          }
       }
-      if (lane < j) vb[lane] = 0.0;
-      if (lane == 0) vb[j] = uv2[j];
+      if (r0 + lane < j) vb[r0 + lane] = 0.0;
+      if (threadIdx.x == 0) vb[j] = uv2[j];
       __syncthreads();
-      const double vm = lane < r ? vb[lane] * rv2[j] : 0.0;
-      const double d = wave_sum64(vm * u);
+      const double vm = r0 + lane < r ? vb[r0 + lane] * rv2[j] : 0.0;
+      const double d = xsum(wave_sum64(vm * u), 0);
       u = fma(-tau2[j] * d, vm, u);
-      __syncthreads();
+      if constexpr (RW == 1) __syncthreads();
     }
     return u;
   };
@@ -1530,16 +1607,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
   // A_k w (A_k re-read from the basis blocks, w broadcast through vb), w += Z solve(rho).
   // It takes the residual of the kept equations from about eps kappa(X) to rounding level.
   // (solve runs in every lane: it holds barriers and cross-lane sums)
-  const double u0 = solve(lane < kq ? bv[pk[lane]] : 0.0);
-  const double w = lane < r ? zv[lane] * u0 : 0.0;
-  vb[lane] = w;
+  const double u0 = solve(wv == 0 && lane < kq ? bv[pk[lane]] : 0.0);
+  const double w = r0 + lane < r ? zv[r0 + lane] * u0 : 0.0;
+  vb[r0 + lane] = w;
   __syncthreads();
   double rho = 0.0;
   {
     const int fq = lane < kq ? pk[lane] : 0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int m0 = 0; m0 < r; m0 += 4) {  // a runtime loop (no register index depends on m); rows
-      // past r read the pads (sentinel cell, vb = 0)
+    const int m1 = min(r, r0 + WR);
+    for (int m0 = r0; m0 < m1; m0 += 4) {  // a runtime loop (no register index depends on m);
+      // points past r read the sentinel cell (and vb = 0), the last wave's the pads
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int m = m0 + e;
@@ -1550,11 +1628,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
         acc[e] = fma(has ? v : 0.0, vb[m], acc[e]);
       }
     }
-    if (lane < kq) rho = bv[fq] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    const double s = xsum((acc[0] + acc[1]) + (acc[2] + acc[3]), 1);
+    if (lane < kq) rho = bv[fq] - s;
   }
   __syncthreads();
-  const double dw = solve(rho);
-  if (lane < r) a.W[fs][a.qptr[i] + lane] = fma(zv[lane], dw, w);
+  const double dw = solve(wv == 0 ? rho : 0.0);
+  if (r0 + lane < r) a.W[fs][a.qptr[i] + r0 + lane] = fma(zv[r0 + lane], dw, w);
 }
 
 
@@ -1817,9 +1896,9 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     tm.stop();
     return ls;
   };
-  // Systems of at most 64 constraints and 64 points go to the one-wave solver first; the
-  // ones its rank proof does not cover are listed and solved by the SVD kernel of their
-  // bucket afterwards (one synchronisation to read the list lengths).
+  // Systems of at most 64 constraints (and 256 points) go to the register-resident solver
+  // first; the ones its rank proof does not cover are listed and solved by the SVD kernel
+  // of their bucket afterwards (one synchronisation to read the list lengths).
   DBuf fbl, fbc;
   int fbn[NBKT];
   bool any_w = false;
@@ -1830,7 +1909,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     const int64_t ns = hist[b];
     if (ns == 0) continue;
     const int bn = b / NB_R, br = b % NB_R;
-    if (bn <= 3 && br == 0) {  // n <= 64, r <= 64
+    if (bn <= 3) {  // n <= 64: the register-resident solver, one wave per 64 points
       TsvdArgs ta = base;
       ta.rows = lists.as<int32_t>() + start[b];
       ta.nsys = ns;
@@ -1841,8 +1920,12 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       const int mn = hist[2 * (NBKT + 1) + 2 * b];
       ta.rp_n = mn;
       const size_t lds = (size_t)mn * (mn - 1) / 2 * sizeof(double);
-      KTimer tm("k_wsolve", (int64_t)bflops[b] * nfam, st);
-      k_wsolve<<<dim3((unsigned)(ns * nfam)), dim3(64), lds, st>>>(ta);
+      const int rw = br == 0 ? 1 : br <= 3 ? 2 : 4;  // r <= 64, 128, 256
+      KTimer tm(rw == 1 ? "k_wsolve<1>" : rw == 2 ? "k_wsolve<2>" : "k_wsolve<4>", (int64_t)bflops[b] * nfam, st);
+      const dim3 grid((unsigned)(ns * nfam));
+      if (rw == 1) k_wsolve<1><<<grid, dim3(64), lds, st>>>(ta);
+      else if (rw == 2) k_wsolve<2><<<grid, dim3(128), lds, st>>>(ta);
+      else k_wsolve<4><<<grid, dim3(256), lds, st>>>(ta);
       tm.stop();
       if (hipGetLastError() != hipSuccess) {
         set_error("solve_weights: one-wave solver launch failed");
@@ -1858,7 +1941,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
         hipStreamSynchronize(st) != hipSuccess)
       s = WQ_EDEVICE;
     for (int b = 0; b < NBKT && s == WQ_OK; ++b)
-      if (hist[b] && b / NB_R <= 3 && b % NB_R == 0 && fbn[b] > 0)
+      if (hist[b] && b / NB_R <= 3 && fbn[b] > 0)
         s = svd_launch(b, fbl.as<int32_t>() + start[b] * nfam, fbn[b], 0);
   }
   dfree(fbl);
