@@ -66,7 +66,7 @@ def roofline_of(name, e):
     over the average launch duration."""
     avg_ms = e["ms"] / e["launches"]
     per_launch = e["work"] / e["launches"]
-    if name.startswith("k_tsvd"):
+    if name.startswith(("k_tsvd", "k_wsolve")):
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_of(name), "avg_launch_ms": avg_ms,

@@ -2,6 +2,8 @@
 #include "wq_internal.h"
 
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 
 namespace wq {
 
@@ -9,23 +11,124 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+namespace {
+
+constexpr int CACHE_DEVS = 64;
+constexpr size_t CACHE_LIMIT = size_t(8) << 30;  // cached bytes kept per device
+
+struct DevCache {
+  std::mutex mu;
+  std::unordered_map<size_t, std::vector<void*>> ready;  // size class -> free blocks
+  size_t bytes = 0;
+};
+
+DevCache* cache_of(int dev) {
+  static DevCache caches[CACHE_DEVS];
+  return dev >= 0 && dev < CACHE_DEVS ? &caches[dev] : nullptr;
+}
+
+size_t size_class(size_t b) {
+  if (b <= (size_t(1) << 20)) return (b + 511) & ~size_t(511);
+  size_t g = size_t(1) << 20;  // an eighth of the largest power of two not above b
+  while ((g << 4) <= b) g <<= 1;
+  return (b + g - 1) / g * g;
+}
+
+// Hands the (idle) blocks of bufs on device dev to its cache, or back to the runtime
+// past the cache's limit. The caller has synchronised that device.
+void cache_put(int dev, DBuf* const* bufs, size_t n) {
+  DevCache* c = cache_of(dev);
+  for (size_t k = 0; k < n; ++k) {
+    DBuf& b = *bufs[k];
+    if (!b.p || b.dev != dev) continue;
+    if (c) {
+      std::lock_guard<std::mutex> lk(c->mu);
+      if (c->bytes + b.cap <= CACHE_LIMIT) {
+        c->ready[b.cap].push_back(b.p);
+        c->bytes += b.cap;
+        b.p = nullptr;
+      }
+    }
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = b.cap = 0;
+  }
+}
+
+// Returns every cached block of the current device dev to the runtime.
+void cache_trim(int dev) {
+  DevCache* c = cache_of(dev);
+  if (!c) return;
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (auto& kv : c->ready)
+    for (void* q : kv.second) (void)hipFree(q);
+  c->ready.clear();
+  c->bytes = 0;
+}
+
+}  // namespace
+
 wq_status dalloc(DBuf& b, size_t bytes) {
   dfree(b);
   if (bytes == 0) bytes = 8;  // keep pointers valid for empty arrays
-  hipError_t e = hipMalloc(&b.p, bytes);
+  const size_t cls = size_class(bytes);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  if (DevCache* c = cache_of(dev)) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->ready.find(cls);
+    if (it != c->ready.end() && !it->second.empty()) {
+      b.p = it->second.back();
+      it->second.pop_back();
+      c->bytes -= cls;
+      b.bytes = bytes;
+      b.cap = cls;
+      b.dev = dev;
+      return WQ_OK;
+    }
+  }
+  hipError_t e = hipMalloc(&b.p, cls);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    cache_trim(dev);
+    e = hipMalloc(&b.p, cls);
+  }
   if (e != hipSuccess) {
     b.p = nullptr;
     set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
     return WQ_ENOMEM;
   }
   b.bytes = bytes;
+  b.cap = cls;
+  b.dev = dev;
   return WQ_OK;
 }
 
+void dfree_many(DBuf* const* bufs, size_t n) {
+  // one synchronisation per device that holds any of the blocks
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) cur = 0;
+  int done[8];
+  int nd = 0;
+  for (size_t k = 0; k < n; ++k) {
+    if (!bufs[k]->p) continue;
+    const int dev = bufs[k]->dev;
+    bool seen = false;
+    for (int q = 0; q < nd; ++q) seen = seen || done[q] == dev;
+    if (seen) continue;
+    if (dev != cur) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    cache_put(dev, bufs, n);
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (nd < 8) done[nd++] = dev;
+  }
+}
+
 void dfree(DBuf& b) {
-  if (b.p) (void)hipFree(b.p);
+  DBuf* one = &b;
+  dfree_many(&one, 1);
   b.p = nullptr;
-  b.bytes = 0;
+  b.bytes = b.cap = 0;
 }
 
 // ------------------------------------------------------------------ exclusive scan
@@ -188,13 +291,8 @@ static wq_status upload(DBuf& b, const T* h, size_t n) {
 }
 
 static void release_mesh(wq_mesh* m) {
-  dfree(m->face_vtx);
-  dfree(m->split);
-  dfree(m->ext_ptr);
-  dfree(m->ext_fn);
-  dfree(m->coef_ptr);
-  dfree(m->coef);
-  dfree(m->ctrl);
+  DBuf* all[] = {&m->face_vtx, &m->split, &m->ext_ptr, &m->ext_fn, &m->coef_ptr, &m->coef, &m->ctrl};
+  dfree_many(all, sizeof(all) / sizeof(all[0]));
 }
 
 extern "C" wq_status wq_mesh_create(const wq_mesh_desc* d, wq_mesh** out) {

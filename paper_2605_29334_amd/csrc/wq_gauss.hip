@@ -156,7 +156,8 @@ extern "C" wq_status gauss_setup(wq_mesh* M, wq_points* P, int want_laplacian, w
 
 extern "C" void wq_gauss_destroy(wq_gauss* g) {
   if (!g) return;
-  for (DBuf* b : {&g->GN, &g->GX, &g->GY, &g->GZ, &g->GL, &g->gw, &g->gx, &g->pbase, &g->pslot}) dfree(*b);
+  DBuf* all[] = {&g->GN, &g->GX, &g->GY, &g->GZ, &g->GL, &g->gw, &g->gx, &g->pbase, &g->pslot};
+  dfree_many(all, sizeof(all) / sizeof(all[0]));
   delete g;
 }
 

@@ -42,12 +42,21 @@ void set_error(const std::string& msg);
 // A device allocation owned by a handle; freed by release().
 struct DBuf {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // requested size
+  size_t cap = 0;    // size of the block (its size class)
+  int dev = 0;       // device the block lives on
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Device buffers come from a per-device cache of freed blocks (size classes of 512 bytes
+// below 1 MiB, one eighth of a power of two above). Freeing keeps hipFree's guarantee: the
+// device is synchronised before the block can be handed out again, so no queued work on
+// any stream still uses it; dfree_many does so once for a whole set of buffers. What the
+// cache holds beyond 8 GiB per device goes back to the runtime, and a failed allocation
+// returns the cache's blocks to the runtime before it tries again.
 wq_status dalloc(DBuf& b, size_t bytes);
 void dfree(DBuf& b);
+void dfree_many(DBuf* const* bufs, size_t n);
 
 template <class T> inline wq_status dalloc_n(DBuf& b, size_t n) { return dalloc(b, n * sizeof(T)); }
 

@@ -640,22 +640,19 @@ __global__ void k_tile2_entries(int64_t n_tiles, const int32_t* row0, const int6
 struct Tmp {
   DBuf vptr, vcur, vidx, bnd, val, ep, passive, enriched, pvtx, tpoint, flags;
   void release() {
-    dfree(vptr); dfree(vcur); dfree(vidx); dfree(bnd); dfree(val); dfree(ep);
-    dfree(passive); dfree(enriched); dfree(pvtx); dfree(tpoint); dfree(flags);
+    DBuf* all[] = {&vptr, &vcur, &vidx, &bnd, &val, &ep, &passive, &enriched, &pvtx, &tpoint, &flags};
+    dfree_many(all, sizeof(all) / sizeof(all[0]));
   }
 };
 
 void release_points(wq_points* P) {
-  dfree(P->etype); dfree(P->s); dfree(P->cell_face); dfree(P->cell_sub); dfree(P->cell_pt_off);
-  dfree(P->cfn_ptr); dfree(P->cfn); dfree(P->cfn_loc); dfree(P->dptr); dfree(P->supp_ptr);
-  dfree(P->supp_cell); dfree(P->row_ptr); dfree(P->col); dfree(P->qptr); dfree(P->qidx);
-  dfree(P->soff); dfree(P->slot); dfree(P->kself); dfree(P->x); dfree(P->detJ);
-  dfree(P->DN); dfree(P->DX); dfree(P->DY); dfree(P->DZ); dfree(P->DL);
-  dfree(P->zterm_ws);
-  dfree(P->tile_eptr); dfree(P->tile_ent); dfree(P->tile_mem);
-  dfree(P->t2_row0); dfree(P->t2_eptr); dfree(P->t2_ent); dfree(P->t2_slot);
-  dfree(P->tangent_ws); dfree(P->newton_ws);
-  for (int f = 0; f < 4; ++f) dfree(P->DS[f]);
+  DBuf* all[] = {&P->etype, &P->s, &P->cell_face, &P->cell_sub, &P->cell_pt_off, &P->cfn_ptr, &P->cfn,
+                 &P->cfn_loc, &P->dptr, &P->supp_ptr, &P->supp_cell, &P->row_ptr, &P->col, &P->qptr,
+                 &P->qidx, &P->soff, &P->slot, &P->kself, &P->x, &P->detJ, &P->DN, &P->DX, &P->DY,
+                 &P->DZ, &P->DL, &P->zterm_ws, &P->tile_eptr, &P->tile_ent, &P->tile_mem, &P->t2_row0,
+                 &P->t2_eptr, &P->t2_ent, &P->t2_slot, &P->tangent_ws, &P->newton_ws, &P->DS[0],
+                 &P->DS[1], &P->DS[2], &P->DS[3]};
+  dfree_many(all, sizeof(all) / sizeof(all[0]));
   P->ds_prec = 0;
 }
 
