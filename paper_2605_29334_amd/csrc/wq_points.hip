@@ -237,68 +237,100 @@ __global__ void k_supp_fill(int32_t ncell, const int64_t* cfn_ptr, const int32_t
 }
 
 // ------------------------------------------------------------------ pattern
-// k-way merge of the ascending function lists of the cells in supp(N_i): S_i.
-__device__ int merge_row(int64_t p0, int np, const int32_t* scell, const int64_t* cfn_ptr, const int32_t* cfn,
-                         int32_t* out) {
-  int32_t pos[MAX_SUPP], end[MAX_SUPP];
-  for (int k = 0; k < np; ++k) {
-    const int32_t c = scell[p0 + k];
-    pos[k] = (int32_t)cfn_ptr[c];
-    end[k] = (int32_t)cfn_ptr[c + 1];
+// Wave-wide helpers: 64 lanes, the same result in every lane.
+__device__ inline int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline int wave_sum_i32(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// k-way merge of the ascending function lists of the cells in supp(N_i): S_i. One wave
+// per row: lane k holds the head of the list of support cell k (np <= 64 cells); each
+// round takes the smallest head (a wave minimum), lane 0 writes it, and the lanes holding
+// it advance. Returns |S_i| in every lane.
+__device__ int wave_merge_row(int64_t p0, int np, const int32_t* scell, const int64_t* cfn_ptr, const int32_t* cfn,
+                              int32_t* out, int lane) {
+  int64_t pos = 0, end = 0;
+  if (lane < np) {
+    const int32_t c = scell[p0 + lane];
+    pos = cfn_ptr[c];
+    end = cfn_ptr[c + 1];
   }
   int count = 0;
   while (true) {
-    int32_t best = INT_MAX;
-    for (int k = 0; k < np; ++k)
-      if (pos[k] < end[k]) best = min(best, cfn[pos[k]]);
+    const int32_t head = pos < end ? cfn[pos] : INT_MAX;
+    const int32_t best = wave_min_i32(head);
     if (best == INT_MAX) break;
-    if (out) out[count] = best;
+    if (out && lane == 0) out[count] = best;
     ++count;
-    for (int k = 0; k < np; ++k)
-      if (pos[k] < end[k] && cfn[pos[k]] == best) ++pos[k];
+    if (head == best) ++pos;
   }
   return count;
 }
 
+// Row sizes: |S_i| and the point count of the row. One wave per row, the waves striding
+// over the rows; each wave keeps its maxima and updates the global ones once at the end
+// (one atomic per row on the same address would serialise).
 __global__ void k_row_count(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cfn_ptr,
                             const int32_t* cfn, const int64_t* cell_pt_off, int64_t* ncnt, int64_t* rcnt,
                             int* err, int* wp_bad, int* maxrow, int* maxr) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t p0 = sptr[i];
-  const int np = (int)(sptr[i + 1] - p0);
-  if (np > MAX_SUPP || np == 0) {
-    atomicOr(err, np == 0 ? 2 : 1);
-    ncnt[i] = 0;
-    rcnt[i] = 0;
-    return;
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  int mrow = 0, mr = 0;
+  for (int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); i < n; i += nwaves) {
+    const int64_t p0 = sptr[i];
+    const int np = (int)(sptr[i + 1] - p0);
+    if (np > MAX_SUPP || np == 0) {
+      if (lane == 0) {
+        atomicOr(err, np == 0 ? 2 : 1);
+        ncnt[i] = 0;
+        rcnt[i] = 0;
+      }
+      continue;
+    }
+    const int ni = wave_merge_row(p0, np, scell, cfn_ptr, cfn, nullptr, lane);
+    int rl = 0;
+    if (lane < np) {
+      const int32_t c = scell[p0 + lane];
+      rl = (int)(cell_pt_off[c + 1] - cell_pt_off[c]);
+    }
+    const int r = wave_sum_i32(rl);
+    if (lane == 0) {
+      ncnt[i] = ni;
+      rcnt[i] = r;
+      if (ni > MAX_ROW) atomicOr(err, 4);
+      if (r < ni) atomicAdd(wp_bad, 1);
+    }
+    mrow = max(mrow, ni);
+    mr = max(mr, r);
   }
-  const int ni = merge_row(p0, np, scell, cfn_ptr, cfn, nullptr);
-  int64_t r = 0;
-  for (int k = 0; k < np; ++k) {
-    const int32_t c = scell[p0 + k];
-    r += cell_pt_off[c + 1] - cell_pt_off[c];
+  if (lane == 0) {
+    atomicMax(maxrow, mrow);
+    atomicMax(maxr, mr);
   }
-  ncnt[i] = ni;
-  rcnt[i] = r;
-  if (ni > MAX_ROW) atomicOr(err, 4);
-  if (r < ni) atomicAdd(wp_bad, 1);
-  atomicMax(maxrow, ni);
-  atomicMax(maxr, (int)r);
 }
 
+// S_i into col and the row's points (support cells in order) into qidx; one wave per row.
 __global__ void k_row_fill(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cfn_ptr,
                            const int32_t* cfn, const int64_t* cell_pt_off, const int64_t* row_ptr, const int64_t* qptr,
                            int32_t* col, int32_t* qidx) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= n) return;
   const int64_t p0 = sptr[i];
   const int np = (int)(sptr[i + 1] - p0);
-  merge_row(p0, np, scell, cfn_ptr, cfn, col + row_ptr[i]);
+  wave_merge_row(p0, np, scell, cfn_ptr, cfn, col + row_ptr[i], lane);
   int64_t o = qptr[i];
   for (int k = 0; k < np; ++k) {
     const int32_t c = scell[p0 + k];
-    for (int64_t q = cell_pt_off[c]; q < cell_pt_off[c + 1]; ++q) qidx[o++] = (int32_t)q;
+    const int64_t q0 = cell_pt_off[c], nq = cell_pt_off[c + 1] - q0;
+    for (int64_t q = lane; q < nq; q += 64) qidx[o + q] = (int32_t)(q0 + q);
+    o += nq;
   }
 }
 
@@ -309,11 +341,13 @@ __global__ void k_pair_m(int64_t npairs, const int32_t* scell, const int64_t* cf
   m[p] = (cfn_ptr[c + 1] - cfn_ptr[c] + 3) & ~int64_t(3);  // padded: slot maps start 4-byte aligned
 }
 
-// slot of every cell function in row i (position in S_i) and of N_i itself in the cell
+// slot of every cell function in row i (position in S_i) and of N_i itself in the cell;
+// one wave per row, a lane per cell function (binary search in S_i)
 __global__ void k_slots(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cfn_ptr,
                         const int32_t* cfn, const int64_t* row_ptr, const int32_t* col, const int64_t* soff,
                         uint8_t* slot, uint8_t* kself) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= n) return;
   const int32_t* row = col + row_ptr[i];
   const int ni = (int)(row_ptr[i + 1] - row_ptr[i]);
@@ -321,7 +355,7 @@ __global__ void k_slots(int64_t n, const int64_t* sptr, const int32_t* scell, co
     const int32_t c = scell[p];
     const int64_t f0 = cfn_ptr[c];
     const int m = (int)(cfn_ptr[c + 1] - f0);
-    for (int k = 0; k < m; ++k) {
+    for (int k = lane; k < m; k += 64) {
       const int32_t j = cfn[f0 + k];
       int lo = 0, hi = ni - 1;
       while (lo < hi) {
@@ -504,74 +538,84 @@ __global__ void k_pair_qoff(int64_t n, const int64_t* sptr, const int32_t* scell
   }
 }
 
-// Merge of the (ascending) cell lists of the rows of one tile. fill == false: count the
-// distinct cells; fill == true: write one entry per cell and its member records.
+// Merge of the (ascending) cell lists of the rows of one tile; one wave per tile, lane r
+// holding the head of row r's list. fill == false: count the distinct cells; fill ==
+// true: write one entry per cell and its member records (in row order).
 template <bool FILL>
 __global__ void k_tile_entries(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cfn_ptr,
                                const int64_t* cell_pt_off, const int64_t* dptr, const int64_t* qoff,
                                const int64_t* soff, const int64_t* row_ptr, int64_t* eptr, int4* ent, int2* mem,
                                int* maxnnz, int* overflow) {
-  const int64_t tile = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t i0 = tile * TILE_ROWS;
-  if (i0 >= n) return;
-  const int nr = (int)min((int64_t)TILE_ROWS, n - i0);
-  int64_t pos[TILE_ROWS], end[TILE_ROWS];
-  for (int r = 0; r < nr; ++r) {
-    pos[r] = sptr[i0 + r];
-    end[r] = sptr[i0 + r + 1];
-  }
-  if (!FILL) {
-    atomicMax(maxnnz, (int)(row_ptr[i0 + nr] - row_ptr[i0]));
-    atomicMax(maxnnz + 2, (int)(sptr[i0 + nr] - sptr[i0]));  // members of the tile
-  }
-  int64_t e = FILL ? eptr[tile] : 0;
-  int64_t mb = FILL ? sptr[i0] : 0;  // members are stored in (entry, row) order
-  int count = 0;
-  while (true) {
-    int32_t best = INT_MAX;
-    for (int r = 0; r < nr; ++r)
-      if (pos[r] < end[r]) best = min(best, scell[pos[r]]);
-    if (best == INT_MAX) break;
-    unsigned mask = 0;
-    int nm = 0;
-    for (int r = 0; r < nr; ++r) {
-      if (pos[r] < end[r] && scell[pos[r]] == best) {
-        mask |= 1u << r;
-        if (FILL) {
-          const int64_t p = pos[r];
-          const int64_t q = qoff[p], so = soff[p];
-          if (q >= (1LL << 28) || so >= (1LL << 31)) atomicOr(overflow, 1);
-          mem[mb + nm] = make_int2((int)(q | ((int64_t)r << 28)), (int)so);
-        }
-        ++nm;
-        ++pos[r];
-      }
-    }
-    if (FILL) {
-      const int np = (int)(cell_pt_off[best + 1] - cell_pt_off[best]);
-      const int m = (int)(cfn_ptr[best + 1] - cfn_ptr[best]);
-      const int64_t d0 = dptr[best];
-      if (d0 >= (1LL << 31) || cell_pt_off[best] >= (1LL << 31) || np > 255 || m > 255) atomicOr(overflow, 1);
-      ent[e] = make_int4((int)d0, (int)cell_pt_off[best], (int)(mask | (np << 16) | (m << 24)), (int)mb);
-      ++e;
-      mb += nm;
+  const int lane = threadIdx.x & 63;
+  const int64_t n_tiles = (n + TILE_ROWS - 1) / TILE_ROWS;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  // maxima of this wave's tiles (counting pass): nnz, -, members, entries, basis block,
+  // member weights; the global ones are updated once at the end
+  int mx[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t tile = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); tile < n_tiles;
+       tile += nwaves) {
+    const int64_t i0 = tile * TILE_ROWS;
+    const int nr = (int)min((int64_t)TILE_ROWS, n - i0);
+    int64_t pos = 0, end = 0;
+    if (lane < nr) {
+      pos = sptr[i0 + lane];
+      end = sptr[i0 + lane + 1];
     }
     if (!FILL) {
-      // per-entry staging sizes of the assembly: the cell's basis block and the member weights
+      mx[0] = max(mx[0], (int)(row_ptr[i0 + nr] - row_ptr[i0]));
+      mx[2] = max(mx[2], (int)(sptr[i0 + nr] - sptr[i0]));  // members of the tile
+    }
+    int64_t e = FILL ? eptr[tile] : 0;
+    int64_t mb = FILL ? sptr[i0] : 0;  // members are stored in (entry, row) order
+    int count = 0;
+    while (true) {
+      const int32_t head = pos < end ? scell[pos] : INT_MAX;
+      const int32_t best = wave_min_i32(head);
+      if (best == INT_MAX) break;
+      const bool member = head == best;
+      const unsigned long long bal = __ballot(member);
+      const unsigned mask = (unsigned)bal;  // rows of the tile (nr <= 8 lanes)
+      const int nm = __popcll(bal);
+      const int rank = __popcll(bal & ((1ULL << lane) - 1ULL));
       const int np = (int)(cell_pt_off[best + 1] - cell_pt_off[best]);
       const int m = (int)(cfn_ptr[best + 1] - cfn_ptr[best]);
-      atomicMax(maxnnz + 4, np * m);
-      atomicMax(maxnnz + 5, nm * np);
+      if (FILL) {
+        if (member) {
+          const int64_t q = qoff[pos], so = soff[pos];
+          if (q >= (1LL << 28) || so >= (1LL << 31)) atomicOr(overflow, 1);
+          mem[mb + rank] = make_int2((int)(q | ((int64_t)lane << 28)), (int)so);
+        }
+        if (lane == 0) {
+          const int64_t d0 = dptr[best];
+          if (d0 >= (1LL << 31) || cell_pt_off[best] >= (1LL << 31) || np > 255 || m > 255) atomicOr(overflow, 1);
+          ent[e] = make_int4((int)d0, (int)cell_pt_off[best], (int)(mask | (np << 16) | (m << 24)), (int)mb);
+        }
+        ++e;
+        mb += nm;
+      } else {
+        // per-entry staging sizes of the assembly: the cell's basis block and the member weights
+        mx[4] = max(mx[4], np * m);
+        mx[5] = max(mx[5], nm * np);
+      }
+      if (member) ++pos;
+      ++count;
     }
-    ++count;
+    if (!FILL) {
+      if (lane == 0) eptr[tile] = count;
+      mx[3] = max(mx[3], count);
+    }
   }
-  if (!FILL) {
-    eptr[tile] = count;
-    atomicMax(maxnnz + 3, count);
+  if (!FILL && lane == 0) {
+    atomicMax(maxnnz, mx[0]);
+    atomicMax(maxnnz + 2, mx[2]);
+    atomicMax(maxnnz + 3, mx[3]);
+    atomicMax(maxnnz + 4, mx[4]);
+    atomicMax(maxnnz + 5, mx[5]);
   }
 }
 
-// Cell-major tiles: merge of the (ascending) cell lists of the rows [row0[t], row0[t+1]).
+// Cell-major tiles: merge of the (ascending) cell lists of the rows [row0[t], row0[t+1]);
+// one wave per tile, lane r holding the head of row r's list.
 // FILL == false: count the distinct cells and the slot-map bytes of their members;
 // FILL == true: write one entry per cell and copy its member rows' slot maps behind the
 // tile's earlier ones (row order; each map padded to whole blocks of 16 functions and
@@ -583,55 +627,57 @@ __global__ void k_tile2_entries(int64_t n_tiles, const int32_t* row0, const int6
                                 const int64_t* cfn_ptr, const int64_t* cell_pt_off, const int64_t* dptr,
                                 const int64_t* soff, const uint8_t* slot, int64_t* eptr, int64_t* bptr, int4* ent,
                                 uint8_t* tslot, int* overflow) {
-  const int64_t tile = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
   if (tile >= n_tiles) return;
   const int i0 = row0[tile];
   const int nr = row0[tile + 1] - i0;
-  int64_t pos[T2_ROWS], end[T2_ROWS];
-  for (int r = 0; r < nr; ++r) {
-    pos[r] = sptr[i0 + r];
-    end[r] = sptr[i0 + r + 1];
+  int64_t pos = 0, end = 0;
+  if (lane < nr) {
+    pos = sptr[i0 + lane];
+    end = sptr[i0 + lane + 1];
   }
   int64_t e = FILL ? eptr[tile] : 0;
   int64_t sb = FILL ? bptr[tile] : 0;  // slot-map bytes
   int count = 0;
   while (true) {
-    int32_t best = INT_MAX;
-    for (int r = 0; r < nr; ++r)
-      if (pos[r] < end[r]) best = min(best, scell[pos[r]]);
+    const int32_t head = pos < end ? scell[pos] : INT_MAX;
+    const int32_t best = wave_min_i32(head);
     if (best == INT_MAX) break;
+    const bool member = head == best;
+    const unsigned long long bal = __ballot(member);
+    const unsigned mask = (unsigned)bal;  // rows of the tile (nr <= 16 lanes)
+    const int nm = __popcll(bal);
+    const int rank = __popcll(bal & ((1ULL << lane) - 1ULL));
     const int np = (int)(cell_pt_off[best + 1] - cell_pt_off[best]);
     const int m = (int)(cfn_ptr[best + 1] - cfn_ptr[best]);
     const int mpad = (m + 15) & ~15;
-    const int64_t sb0 = sb;
-    unsigned mask = 0;
-    for (int r = 0; r < nr; ++r) {
-      if (pos[r] < end[r] && scell[pos[r]] == best) {
-        mask |= 1u << r;
-        if (FILL) {
-          const int64_t so = soff[pos[r]];
-          for (int t = 0; t < mpad; ++t) {
-            const int k = (t & ~15) + ((t >> 2) & 3) + 4 * (t & 3);
-            // a position past the cell's functions gets some slot of the row: the kernel
-            // adds zero products there (no per-function predicate)
-            tslot[sb + t] = slot[so + (k < m ? k : k % m)];
-          }
-        }
-        sb += mpad;
-        ++pos[r];
-      }
-    }
     if (FILL) {
-      const int64_t d0 = dptr[best];
-      if (d0 > (int64_t)INT32_MAX || cell_pt_off[best] > (int64_t)INT32_MAX || sb > (int64_t)INT32_MAX || np > 255 ||
-          m > 255)
-        atomicOr(overflow, 1);
-      ent[e] = make_int4((int)d0, (int)cell_pt_off[best], (int)(mask | (np << 16) | (m << 24)), (int)sb0);
+      if (member) {
+        const int64_t so = soff[pos];
+        uint8_t* dst = tslot + sb + (int64_t)rank * mpad;
+        for (int t = 0; t < mpad; ++t) {
+          const int k = (t & ~15) + ((t >> 2) & 3) + 4 * (t & 3);
+          // a position past the cell's functions gets some slot of the row: the kernel
+          // adds zero products there (no per-function predicate)
+          dst[t] = slot[so + (k < m ? k : k % m)];
+        }
+      }
+      if (lane == 0) {
+        const int64_t d0 = dptr[best];
+        const int64_t sbe = sb + (int64_t)nm * mpad;
+        if (d0 > (int64_t)INT32_MAX || cell_pt_off[best] > (int64_t)INT32_MAX || sbe > (int64_t)INT32_MAX || np > 255 ||
+            m > 255)
+          atomicOr(overflow, 1);
+        ent[e] = make_int4((int)d0, (int)cell_pt_off[best], (int)(mask | (np << 16) | (m << 24)), (int)sb);
+      }
       ++e;
     }
+    sb += (int64_t)nm * mpad;
+    if (member) ++pos;
     ++count;
   }
-  if (!FILL) {
+  if (!FILL && lane == 0) {
     eptr[tile] = count;
     bptr[tile] = sb;
   }
@@ -770,7 +816,7 @@ wq_status build_structure(wq_mesh* M, wq_points* P, DBuf& flags, int* wp_bad, hi
   WQ_TRY(dalloc_n<int64_t>(P->qptr, n + 1));
   WQ_HIP(hipMemsetAsync(P->row_ptr.p, 0, (n + 1) * sizeof(int64_t), st));
   WQ_HIP(hipMemsetAsync(P->qptr.p, 0, (n + 1) * sizeof(int64_t), st));
-  k_row_count<<<nblocks(n, BS), BS, 0, st>>>(n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
+  k_row_count<<<std::min(nblocks(n, BS / 64), 1024u), BS, 0, st>>>(n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
                                               P->cfn_ptr.as<int64_t>(), P->cfn.as<int32_t>(),
                                               P->cell_pt_off.as<int64_t>(), P->row_ptr.as<int64_t>(),
                                               P->qptr.as<int64_t>(), df + 1, df + 2, df + 3, df + 4);
@@ -789,7 +835,7 @@ wq_status build_structure(wq_mesh* M, wq_points* P, DBuf& flags, int* wp_bad, hi
   WQ_TRY(exclusive_scan_i64(P->qptr.as<int64_t>(), n + 1, &sum_r, st));
   WQ_TRY(dalloc_n<int32_t>(P->col, P->nnz));
   WQ_TRY(dalloc_n<int32_t>(P->qidx, sum_r));
-  k_row_fill<<<nblocks(n, BS), BS, 0, st>>>(n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
+  k_row_fill<<<nblocks(n, BS / 64), BS, 0, st>>>(n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
                                              P->cfn_ptr.as<int64_t>(), P->cfn.as<int32_t>(),
                                              P->cell_pt_off.as<int64_t>(), P->row_ptr.as<int64_t>(),
                                              P->qptr.as<int64_t>(), P->col.as<int32_t>(), P->qidx.as<int32_t>());
@@ -801,7 +847,7 @@ wq_status build_structure(wq_mesh* M, wq_points* P, DBuf& flags, int* wp_bad, hi
   WQ_TRY(exclusive_scan_i64(P->soff.as<int64_t>(), P->n_pairs + 1, &P->n_slots, st));
   WQ_TRY(dalloc_n<uint8_t>(P->slot, P->n_slots));
   WQ_TRY(dalloc_n<uint8_t>(P->kself, P->n_pairs));
-  k_slots<<<nblocks(n, BS), BS, 0, st>>>(n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
+  k_slots<<<nblocks(n, BS / 64), BS, 0, st>>>(n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
                                           P->cfn_ptr.as<int64_t>(), P->cfn.as<int32_t>(), P->row_ptr.as<int64_t>(),
                                           P->col.as<int32_t>(), P->soff.as<int64_t>(), P->slot.as<uint8_t>(),
                                           P->kself.as<uint8_t>());
@@ -872,14 +918,14 @@ wq_status build_tiles(wq_mesh* M, wq_points* P, DBuf& flags, hipStream_t st) {
   WQ_HIP(hipMemsetAsync(flags.p, 0, 8 * sizeof(int), st));
   k_pair_qoff<<<nblocks(n, BS), BS, 0, st>>>(n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
                                               P->cell_pt_off.as<int64_t>(), P->qptr.as<int64_t>(), qoff.as<int64_t>());
-  k_tile_entries<false><<<nblocks(P->n_tiles, 64), 64, 0, st>>>(
+  k_tile_entries<false><<<std::min(nblocks(P->n_tiles, BS / 64), 1024u), BS, 0, st>>>(
       n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(), P->cfn_ptr.as<int64_t>(), P->cell_pt_off.as<int64_t>(),
       P->dptr.as<int64_t>(), qoff.as<int64_t>(), P->soff.as<int64_t>(), P->row_ptr.as<int64_t>(),
       P->tile_eptr.as<int64_t>(), nullptr, nullptr, flags.as<int>(), flags.as<int>() + 1);
   WQ_TRY(exclusive_scan_i64(P->tile_eptr.as<int64_t>(), P->n_tiles + 1, &P->n_entries, st));
   WQ_TRY(dalloc(P->tile_ent, (size_t)P->n_entries * sizeof(int4)));
   WQ_TRY(dalloc(P->tile_mem, (size_t)P->n_pairs * sizeof(int2)));
-  k_tile_entries<true><<<nblocks(P->n_tiles, 64), 64, 0, st>>>(
+  k_tile_entries<true><<<std::min(nblocks(P->n_tiles, BS / 64), 1024u), BS, 0, st>>>(
       n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(), P->cfn_ptr.as<int64_t>(), P->cell_pt_off.as<int64_t>(),
       P->dptr.as<int64_t>(), qoff.as<int64_t>(), P->soff.as<int64_t>(), P->row_ptr.as<int64_t>(),
       P->tile_eptr.as<int64_t>(), P->tile_ent.as<int4>(), P->tile_mem.as<int2>(), flags.as<int>(),
@@ -926,7 +972,7 @@ wq_status build_tiles2(wq_points* P, DBuf& flags, hipStream_t st) {
   WQ_HIP(hipMemsetAsync(P->t2_eptr.p, 0, (P->n_t2 + 1) * sizeof(int64_t), st));
   WQ_HIP(hipMemsetAsync(bptr.p, 0, (P->n_t2 + 1) * sizeof(int64_t), st));
   WQ_HIP(hipMemsetAsync(flags.p, 0, 8 * sizeof(int), st));
-  k_tile2_entries<false><<<nblocks(P->n_t2, 64), 64, 0, st>>>(
+  k_tile2_entries<false><<<nblocks(P->n_t2, BS / 64), BS, 0, st>>>(
       P->n_t2, P->t2_row0.as<int32_t>(), P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
       P->cfn_ptr.as<int64_t>(), P->cell_pt_off.as<int64_t>(), P->dptr.as<int64_t>(), P->soff.as<int64_t>(),
       P->slot.as<uint8_t>(), P->t2_eptr.as<int64_t>(), bptr.as<int64_t>(), nullptr, nullptr, flags.as<int>());
@@ -943,7 +989,7 @@ wq_status build_tiles2(wq_points* P, DBuf& flags, hipStream_t st) {
   WQ_TRY(exclusive_scan_i64(bptr.as<int64_t>(), P->n_t2 + 1, &nbytes, st));
   WQ_TRY(dalloc(P->t2_ent, (size_t)P->n_e2 * sizeof(int4)));
   WQ_TRY(dalloc(P->t2_slot, (size_t)nbytes + 4));
-  k_tile2_entries<true><<<nblocks(P->n_t2, 64), 64, 0, st>>>(
+  k_tile2_entries<true><<<nblocks(P->n_t2, BS / 64), BS, 0, st>>>(
       P->n_t2, P->t2_row0.as<int32_t>(), P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
       P->cfn_ptr.as<int64_t>(), P->cell_pt_off.as<int64_t>(), P->dptr.as<int64_t>(), P->soff.as<int64_t>(),
       P->slot.as<uint8_t>(), P->t2_eptr.as<int64_t>(), bptr.as<int64_t>(), P->t2_ent.as<int4>(),
