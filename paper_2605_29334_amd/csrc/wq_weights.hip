@@ -814,33 +814,38 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   // minimum-norm solution of those k equations, w = Z Q R^-T b_k for Z A_k^T = Q R (CGS2
   // below), the same as the SVD's to rounding times the conditioning. Otherwise the
   // factorisation runs to the end and the Jacobi SVD decides.
-  // Column c of S = R11^-T (lower triangular), one thread per column: S[ii][c] = (delta -
+  // Column c of S = R11^-T (lower triangular), eight lanes per column: S[ii][c] = (delta -
   // sum_{jj = c}^{ii - 1} R[jj][ii] S[jj][c]) / R[ii][ii], with R[.][ii] read down the
   // physical column of logical column ii (rows < ii) and S[.][c] kept in rows c+1 .. kq of
   // the physical column of logical column c (its reflector rows, no longer needed: no
-  // thread reads R there). Both are contiguous runs, summed in four chains.
+  // thread reads R there). Lane s of a column's group takes jj = c + s (mod 8), the group
+  // sums by DPP, and its first lane stores S[ii][c] (read by the group's lanes, in the same
+  // wave, at the next steps: one LDS latency per step instead of one per four terms).
   const int* pk = (kq & 1) ? cmap : piv;  // logical column l of R is constraint pk[l]
   const double r22 = kq < kmax ? sqrt((double)(n - kq) * s2stop) : 0.0;
   double lo = 0.0;
   bool fast = false;
   if (s20 > 0.0 && kq > 0) {
     double tn = 0.0;
-    for (int c = tid; c < kq; c += NT) {
+    const int cs = tid & 7;
+    for (int c = tid >> 3; c < kq; c += NT / 8) {  // (whole groups of eight lanes)
       double* Sc = G + (size_t)pk[c] * ld + 1;  // S[jj][c] at Sc[jj]
       for (int ii = c; ii < kq; ++ii) {
         const double* Rc = G + (size_t)pk[ii] * ld;  // R[jj][ii] at Rc[jj], jj < ii
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int jj = c;
-        for (; jj + 4 <= ii; jj += 4) {
+        double s0 = 0.0, s1 = 0.0;
+        int jj = c + cs;
+        for (; jj + 8 < ii; jj += 16) {
           s0 = fma(Rc[jj], Sc[jj], s0);
-          s1 = fma(Rc[jj + 1], Sc[jj + 1], s1);
-          s2 = fma(Rc[jj + 2], Sc[jj + 2], s2);
-          s3 = fma(Rc[jj + 3], Sc[jj + 3], s3);
+          s1 = fma(Rc[jj + 8], Sc[jj + 8], s1);
         }
-        for (; jj < ii; ++jj) s0 = fma(Rc[jj], Sc[jj], s0);
-        const double v = ((ii == c ? 1.0 : 0.0) - ((s0 + s1) + (s2 + s3))) / beta[ii];
-        Sc[ii] = v;
-        tn = fma(v, v, tn);
+        if (jj < ii) s0 = fma(Rc[jj], Sc[jj], s0);
+        const double sum = group_sum<8>(s0 + s1);
+        const double v = ((ii == c ? 1.0 : 0.0) - sum) / beta[ii];
+        if (cs == 0) {
+          Sc[ii] = v;
+          tn = fma(v, v, tn);
+        }
+        __builtin_amdgcn_wave_barrier();
       }
     }
     tn = block_sum(tn, red);  // the same bits in every thread: the branch is uniform
