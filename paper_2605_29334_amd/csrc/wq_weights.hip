@@ -459,6 +459,28 @@ __device__ inline void group_argmax(double& v, int& i) {
 // to the logical columns l > j (physical phys(l): cur[l], except cj for l = bi, the pivot's
 // old position), LPP lanes per column, and recompute their trailing squared norms (rows
 // > j) exactly; returns this group's largest (norm, l), ties to the smaller l.
+// Largest (value, lane) of the wave, ties to the smaller lane: the same in every lane.
+__device__ inline void wave_argmax64(double v, int i, double& bv, int& bi) {
+  group_argmax<16>(v, i);
+  bv = readlane_f64(v, 0);
+  bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+  for (int row = 1; row < 4; ++row) {
+    const double rv = readlane_f64(v, 16 * row);
+    const int ri = __builtin_amdgcn_readlane(i, 16 * row);
+    if (rv > bv || (rv == bv && ri < bi)) {
+      bv = rv;
+      bi = ri;
+    }
+  }
+}
+
+// Sum over the wave in a fixed order, the same bits in every lane.
+__device__ inline double wave_sum64(double v) {
+  v = group_sum<16>(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 template <int LPP, int EPR, int NG>
 __device__ inline double qr_update(double* G, int ld, int r, int ncol, int j, int pc, const int* cur, int bi, int cj,
                                    double tau, double rv0, int g, int sub, int* best_l) {
@@ -650,7 +672,7 @@ __device__ inline HalvingSlot halving_slot(int n, int L, int g) {
 //     than on A^T itself, and its columns have length n instead of r;
 //  3. keep sigma_k > tau sigma_1; c_k = u_k^T b / sigma_k; V_t = A^T U_t Sigma_t^-1 (A
 //     re-read from the basis blocks), X = Z V_t;
-//  4. X = Q R (CGS2), y = R^-T c, w = Z Q y.
+//  4. X = Q R (Householder), y = R^-T c, w = Z Q [y; 0].
 // Where the pivoted QR already proves which singular values the cutoff keeps (a gap at
 // tau around its k-th step, certified by bounds on ||R22|| and ||R11^-1||), the QR stops
 // at step k and steps 2-3 are skipped: X = Z A_k^T over the k pivot rows of A and c =
@@ -811,7 +833,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   // tau R_00 and tau ||A||_F. So when ||R22|| is below tau R_00 / 10 and the kept bound
   // is above 100 tau ||A||_F, the cutoff keeps exactly k singular values, and their span is
   // that of the k pivot rows of A up to O(eps / gap): the solution is then the weighted
-  // minimum-norm solution of those k equations, w = Z Q R^-T b_k for Z A_k^T = Q R (CGS2
+  // minimum-norm solution of those k equations, w = Z Q R^-T b_k for Z A_k^T = Q R (step 4
   // below), the same as the SVD's to rounding times the conditioning. Otherwise the
   // factorisation runs to the end and the Jacobi SVD decides.
   // Column c of S = R11^-T (lower triangular), eight lanes per column: S[ii][c] = (delta -
@@ -1118,130 +1140,98 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       }
     }
   }
-  // ---- 4. CGS2 on the columns of X; y_k = (c_k - sum_{j<k} R_jk y_j) / R_kk, w = Z Q y.
-  // The columns stay unnormalised: column j keeps x_j = R_jj q_j and iq[j] = 1 / R_jj, so
-  // no pass rescales them. The norm and the sum_j R_jk y_j of column k are reduced into
-  // red at the column's last barrier; every thread reads them at the start of column k+1
-  // (or after the loop), and thread 0 stores iq[k], ys[k] (beta is free once M is formed),
-  // visible from the next barrier on. yv[k] = c_k is only read.
-  double* ys = beta;
-  double* iq = nrm;  // free after the Jacobi sweeps
-  // lanes per dot product: 8 where the k dot products still take one pass over the
-  // threads (the 1024-thread instance, k <= 128; the 512-thread one with 16 lanes per
-  // pair, k <= 64), each lane then taking half the terms; else 4
-  constexpr int DL = (NT >= 1024 || (NT == 512 && LPP == 16)) ? 8 : 4;
-  double inv_prev = 0.0;  // 1 / R_{k-1,k-1}, in every thread
-  auto finish = [&](int k) {  // column k's R_kk and y_k from the reduced partial sums
-    double nn2 = 0.0, acc = 0.0;
-    for (int w8 = 0; w8 < NT / 64; ++w8) {
-      nn2 += red[w8];
-      acc += red[NT / 64 + w8];
-    }
-    const double nrmx = sqrt(nn2);
-    inv_prev = 1.0 / nrmx;
+  // ---- 4. Householder QR of X (no pivoting; reflector j kept unscaled in its column as in
+  // step 2, R_jj in beta, tau in tq, 1 / (x_j - R_jj) in rvq, the trailing squared norms
+  // in nq), one barrier per column; then, in the first wave, y = R^-T c over c (lanes over
+  // columns, y_j handed on by read-lane) and u = Q [y; 0] = H_0 ... H_{t-1} [y; 0] (the
+  // reflectors in reverse, u in registers, four points per lane); w = Z u.
+  double* tq = sig;   // free: the singular values only formed X and c
+  double* rvq = Rk;   // free: b is in c (yv) by now
+  double* nq = nrm;   // free after the Jacobi sweeps
+  for (int l = g; l < t; l += NG) {
+    double s2 = 0.0;
+    for (int m = sub; m < r; m += LPP) s2 += G[(size_t)l * ld + m] * G[(size_t)l * ld + m];
+    s2 = group_sum<LPP>(s2);
+    if (sub == 0) nq[l] = s2;
+  }
+  __syncthreads();
+  for (int j = 0; j < t; ++j) {
+    double rjj, rv0, tj;
+    householder(G[(size_t)j * ld + j], nq[j], &rjj, &rv0, &tj);
     if (tid == 0) {
-      iq[k] = inv_prev;
-      ys[k] = (yv[k] - acc) / nrmx;
+      beta[j] = rjj;
+      tq[j] = tj;
+      rvq[j] = rv0;
     }
-  };
-  for (int k = 0; k < t; ++k) {
-    if (k > 0) finish(k - 1);
-    double* x = G + (size_t)k * ld;
-    double part_n = 0.0, part_a = 0.0;
-    for (int pass = 0; pass < 2; ++pass) {
-      // d_j = x_j . x for j < k (DL lanes per j): R_jk += d_j / R_jj (both passes), and
-      // the coefficient of x_j in the update, d_j / R_jj^2
-      for (int jb = 0; jb < k; jb += NT / DL) {
-        const int j = jb + tid / DL, s4 = tid % DL;
-        double d = 0.0;
-        if (j < k) {
-          const double* qj = G + (size_t)j * ld;
-          for (int m = s4; m < r; m += DL) d += qj[m] * x[m];
-        }
-        d = group_sum<DL>(d);
-        if (j < k && s4 == 0) {
-          const double ij = (pass == 0 && j == k - 1) ? inv_prev : iq[j];
-          const double h = d * ij;
-          Rk[j] = pass == 0 ? h : Rk[j] + h;
-          sig[j] = h * ij;  // this pass's coefficients (sig is free now)
+    const double* cp = G + (size_t)j * ld;
+    for (int l = j + 1 + g; l < t; l += NG) {
+      double* cl = G + (size_t)l * ld;
+      double x[EPR], v[EPR];
+      double sv = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPR; ++e) {
+        const int m = j + sub + LPP * e;
+        x[e] = (m < r) ? cl[m] : 0.0;
+        v[e] = (m == j) ? 1.0 : ((m < r) ? cp[m] * rv0 : 0.0);
+        sv += v[e] * x[e];
+      }
+      sv = tj * group_sum<LPP>(sv);
+      double ns = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPR; ++e) {
+        const int m = j + sub + LPP * e;
+        if (m < r) {
+          const double y = x[e] - sv * v[e];
+          if (tj != 0.0) cl[m] = y;
+          if (m > j) ns += y * y;
         }
       }
-      __syncthreads();
-      // x -= sum_j sig_j x_j as four chains, chain c taking j = c (mod 4) below 4 floor(k/4)
-      // and chain 0 also the rest, combined as (c0 + c1) + (c2 + c3). RS = 4, 2 or 1 lanes
-      // per row (as many as the threads allow for this r) share the chains of a row (RS = 4:
-      // one each; RS = 2: lane p takes chains p and p + 2), so x itself does not depend on
-      // RS. The second pass also forms the partial sums of |x|^2 (per wave, so their
-      // grouping follows RS, which depends on r and the instance only) and of
-      // sum_j R_jk y_j.
-      {
-        const int lg = 4 * r <= NT ? 2 : 2 * r <= NT ? 1 : 0;
-        const int m = tid >> lg, p = tid & ((1 << lg) - 1);
-        const int k4 = k & ~3;
-        if (m < r) {  // whole groups of 1 << lg lanes (r (1 << lg) <= NT)
-          double v;
-          if (lg == 2) {
-            v = p == 0 ? x[m] : 0.0;
-            for (int j = p; j < k4; j += 4) v -= G[(size_t)j * ld + m] * sig[j];
-            if (p == 0)
-              for (int j = k4; j < k; ++j) v -= G[(size_t)j * ld + m] * sig[j];
-            v = group_sum<4>(v);  // (c0 + c1) + (c2 + c3)
-          } else if (lg == 1) {
-            double va = p == 0 ? x[m] : 0.0, vb = 0.0;  // chains p and p + 2
-            for (int j = 0; j < k4; j += 4) {
-              va -= G[(size_t)(j + p) * ld + m] * sig[j + p];
-              vb -= G[(size_t)(j + p + 2) * ld + m] * sig[j + p + 2];
-            }
-            if (p == 0)
-              for (int j = k4; j < k; ++j) va -= G[(size_t)j * ld + m] * sig[j];
-            va += dpp_f64<0xB1>(va);  // c0 + c1 in both lanes
-            vb += dpp_f64<0xB1>(vb);  // c2 + c3
-            v = va + vb;
-          } else {
-            double v0 = x[m], v1 = 0.0, v2 = 0.0, v3 = 0.0;  // four chains in flight
-            for (int j = 0; j < k4; j += 4) {
-              v0 -= G[(size_t)j * ld + m] * sig[j];
-              v1 -= G[(size_t)(j + 1) * ld + m] * sig[j + 1];
-              v2 -= G[(size_t)(j + 2) * ld + m] * sig[j + 2];
-              v3 -= G[(size_t)(j + 3) * ld + m] * sig[j + 3];
-            }
-            for (int j = k4; j < k; ++j) v0 -= G[(size_t)j * ld + m] * sig[j];
-            v = (v0 + v1) + (v2 + v3);
-          }
-          if (p == 0) {
-            x[m] = v;
-            if (pass == 1) part_n += v * v;
-          }
-        }
-      }
-      if (pass == 1)
-        for (int j = tid; j < k; j += NT) part_a += Rk[j] * ys[j];
-      if (pass == 0) __syncthreads();
-    }
-    // one block reduction of the two partial sums into red (read by every thread at the
-    // start of column k+1; the previous values were read before this column's first
-    // barrier)
-    part_n = wave_sum(part_n);
-    part_a = wave_sum(part_a);
-    if ((tid & 63) == 0) {
-      red[tid >> 6] = part_n;
-      red[NT / 64 + (tid >> 6)] = part_a;
+      ns = group_sum<LPP>(ns);
+      if (sub == 0) nq[l] = ns;
     }
     __syncthreads();
   }
-  if (t > 0) finish(t - 1);
-  __syncthreads();
-  // w = Z sum_k x_k y_k / R_kk
-  double* W = a.W[fs] + a.qptr[i];
-  for (int m = tid; m < r; m += NT) {
-    double v0 = 0.0, v1 = 0.0;
-    int k = 0;
-    for (; k + 2 <= t; k += 2) {
-      v0 += G[(size_t)k * ld + m] * (ys[k] * iq[k]);
-      v1 += G[(size_t)(k + 1) * ld + m] * (ys[k + 1] * iq[k + 1]);
+  if (tid >= 64) return;
+  {
+    const int lane = tid;
+    // y_jj = (c_jj - sum_{jj' < jj} R[jj'][jj] y_jj') / R_jj; lane l accumulates the sums of
+    // columns l and 64 + l (R[jj][k] at G[k ld + jj])
+    double a0 = 0.0, a1 = 0.0;
+    for (int jj = 0; jj < t; ++jj) {
+      const double aj = readlane_f64(jj < 64 ? a0 : a1, jj & 63);
+      const double yj = (yv[jj] - aj) / beta[jj];
+      if (lane == 0) yv[jj] = yj;
+      if (lane > jj && lane < t) a0 = fma(G[(size_t)lane * ld + jj], yj, a0);
+      if (64 + lane > jj && 64 + lane < t) a1 = fma(G[(size_t)(64 + lane) * ld + jj], yj, a1);
     }
-    if (k < t) v0 += G[(size_t)k * ld + m] * (ys[k] * iq[k]);
-    W[m] = z[m] * (v0 + v1);
+    __builtin_amdgcn_wave_barrier();
+    double u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = lane + 64 * q;
+      u[q] = m < t ? yv[m] : 0.0;
+    }
+    for (int j = t - 1; j >= 0; --j) {
+      const double* cp = G + (size_t)j * ld;
+      const double rv = rvq[j], tj = tq[j];
+      double vm[4];
+      double d = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = lane + 64 * q;
+        vm[q] = m == j ? 1.0 : (m > j && m < r ? cp[m] * rv : 0.0);
+        d = fma(vm[q], u[q], d);
+      }
+      d = wave_sum64(d);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u[q] = fma(-tj * d, vm[q], u[q]);
+    }
+    double* W = a.W[fs] + a.qptr[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = lane + 64 * q;
+      if (m < r) W[m] = z[m] * u[q];
+    }
   }
 }
 
@@ -1255,7 +1245,7 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
 // squared norms of the row waves are summed through LDS in wave order (the same bits in
 // every wave).
 // The steps are those of the certified path of k_tsvd2 (the kept count proved from the
-// pivoted QR of A^T), with the second factorisation by Householder instead of CGS2:
+// pivoted QR of A^T), with the second factorisation and the solve held in registers:
 //  1. pivoted Householder QR of A^T, stopped once the trailing block is negligible;
 //  2. the rank proof (||R11^-1||_F from R11^-T, one column per lane);
 //  3. Householder QR of X = Z A_k^T (the k pivot rows of A, re-read from the basis blocks);
@@ -1267,28 +1257,6 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
 // A system the proof does not cover is appended to a list for k_tsvd2 (the Jacobi SVD).
 constexpr int WR = 64;  // points (rows) held per lane and wave
 constexpr int WB = 16;  // rows per skipped block
-
-// Largest (value, lane) of the wave, ties to the smaller lane: the same in every lane.
-__device__ inline void wave_argmax64(double v, int i, double& bv, int& bi) {
-  group_argmax<16>(v, i);
-  bv = readlane_f64(v, 0);
-  bi = __builtin_amdgcn_readlane(i, 0);
-#pragma unroll
-  for (int row = 1; row < 4; ++row) {
-    const double rv = readlane_f64(v, 16 * row);
-    const int ri = __builtin_amdgcn_readlane(i, 16 * row);
-    if (rv > bv || (rv == bv && ri < bi)) {
-      bv = rv;
-      bi = ri;
-    }
-  }
-}
-
-// Sum over the wave in a fixed order, the same bits in every lane.
-__device__ inline double wave_sum64(double v) {
-  v = group_sum<16>(v);
-  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
-}
 
 template <int RW, int CW>
 __global__ void __launch_bounds__(64 * RW * CW) __attribute__((amdgpu_waves_per_eu(3))) k_wsolve(TsvdArgs a) {
