@@ -1237,15 +1237,13 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
 
 
 // ---------------------------------------------------------------------------------
-// Register-resident solver for systems of at most 64 CW constraints and 64 RW points:
-// RW x CW waves per system, wave (v, c) holding points [64 v, 64 v + 64) of columns
-// [64 c, 64 c + 64) of the factorised matrix (one column per lane), one double per point
-// in registers. The Householder steps broadcast the reflector's column through LDS and
-// every lane forms its own partial dot product and update; the partial dot products and
-// squared norms of the row waves are summed through LDS in wave order (the same bits in
-// every wave).
-// The steps are those of the certified path of k_tsvd2 (the kept count proved from the
-// pivoted QR of A^T), with the second factorisation and the solve held in registers:
+// One wave per weight system, for systems of at most 64 constraints and 64 points (the
+// rows of regular cells and most of their neighbours). Lane l holds a column of the
+// factorised matrix in registers, one double per point, so the Householder steps need no
+// cross-lane reductions: the reflector's column is broadcast through LDS and every lane
+// forms its own dot product and update. The steps are those of the certified path of
+// k_tsvd2 (the kept count proved from the pivoted QR of A^T), with the second
+// factorisation and the solve held in registers:
 //  1. pivoted Householder QR of A^T, stopped once the trailing block is negligible;
 //  2. the rank proof (||R11^-1||_F from R11^-T, one column per lane);
 //  3. Householder QR of X = Z A_k^T (the k pivot rows of A, re-read from the basis blocks);
@@ -1255,35 +1253,20 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
 // blocks of 16 rows that lie wholly above it (a uniform branch; the sums are unchanged,
 // the skipped terms being exact zeros).
 // A system the proof does not cover is appended to a list for k_tsvd2 (the Jacobi SVD).
-constexpr int WR = 64;  // points (rows) held per lane and wave
-constexpr int WB = 16;  // rows per skipped block
+constexpr int WR = 64;     // points (rows) held per lane
+constexpr int WB = 16;     // rows per skipped block
+constexpr int WMAXC = 40;  // support cells of a row in the gather tables
 
-template <int RW, int CW>
-__global__ void __launch_bounds__(64 * RW * CW) __attribute__((amdgpu_waves_per_eu(3))) k_wsolve(TsvdArgs a) {
-  constexpr int NR = RW * WR;               // points of the workgroup
-  constexpr int NF = CW * 64;               // constraints (columns) of the workgroup
-  constexpr int NW = RW * CW;               // waves
-  constexpr int WMAXC = NW == 1 ? 40 : 64;  // support cells of a row in the gather tables
-  __shared__ double vb[NR + 4];  // the current reflector's column (4 zero pads past the rows)
-  __shared__ double zv[NR], bv[NF], beta[NF], ib[NF], tau2[NF], rv2[NF], uv2[NF];
-  __shared__ double xpart[NW > 1 ? 2 * NW * WR : 1];  // per-wave partial sums (dot, norm)
-  __shared__ double ysh[CW > 1 ? NF : 1];             // triangular-solve hand-over
-  __shared__ double tsum[4];
-  __shared__ double hx0;  // row-j entry of the pivot column
-  __shared__ int flag;
-  // R11 above the diagonal by columns, n_max (n_max - 1) / 2, then (two column waves) the
-  // hand-over of the rank proof, (n_max - 64) x 64
-  extern __shared__ double rp[];
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_wsolve(TsvdArgs a) {
+  __shared__ double vb[WR + 4];  // the current reflector's column (4 zero pads past the rows)
+  __shared__ double zv[WR], bv[WR], beta[WR], ib[WR], tau2[WR], rv2[WR], uv2[WR];
+  extern __shared__ double rp[];  // R11 above the diagonal by columns: n_max (n_max - 1) / 2
   __shared__ int64_t cbase[WMAXC];
   __shared__ int cmc[WMAXC];
-  __shared__ uint8_t invk[WMAXC * NF];  // local index of row function l in support cell p, 255: none
-  __shared__ uint8_t ptp[NR + 4], ptq[NR + 4];  // support cell and local index of every point
-  __shared__ int pk[NF];                        // position -> constraint of the pivoted QR
-  const int lane = threadIdx.x & 63;
-  const int wi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform in the wave
-  const int rw = wi % RW, cw = wi / RW;
-  const int r0 = WR * rw;  // first point of this wave
-  const int col = 64 * cw + lane;  // this lane's column
+  __shared__ uint8_t invk[WMAXC * WR];  // local index of row function l in support cell p, 255: none
+  __shared__ uint8_t ptp[WR + 4], ptq[WR + 4];  // support cell and local index of every point
+  __shared__ int pk[WR];                        // position -> constraint of the pivoted QR
+  const int lane = threadIdx.x;
   const int fs = (int)(blockIdx.x / a.nsys);
   const int64_t sys = blockIdx.x - (int64_t)fs * a.nsys;
   const double* AD = a.D[fs];
@@ -1293,48 +1276,28 @@ __global__ void __launch_bounds__(64 * RW * CW) __attribute__((amdgpu_waves_per_
   const int64_t s0 = a.sptr[i];
   const int nc = (int)(a.sptr[i + 1] - s0);
   auto to_svd = [&]() {
-    if (threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)blockIdx.x;
+    if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)blockIdx.x;
   };
-  if (n > NF || n > a.rp_n || (CW > 1 && a.rp_n <= 64) || r > NR || nc < 1 || nc >= WMAXC) {
+  if (n > WR || n > a.rp_n || r > WR || nc < 1 || nc >= WMAXC) {
     to_svd();
     return;
   }
-  // Sum over the row waves of a per-lane partial, in wave order (slot 0: dot products, 1:
-  // norms; a slot is rewritten only after a barrier that follows every read of it); colsum
-  // reads the same sum for any column from any wave (the same bits).
-  auto colsum = [&](int slot, int c) -> double {
-    const double* xp = xpart + slot * NW * WR + (c >> 6) * NR + (c & 63);
-    double s = xp[0];
-#pragma unroll
-    for (int w = 1; w < RW; ++w) s += xp[w * WR];
-    return s;
-  };
-  auto xsum = [&](double v, int slot) -> double {
-    if constexpr (NW == 1) {
-      return v;
-    } else {
-      xpart[slot * NW * WR + threadIdx.x] = v;
-      __syncthreads();
-      return colsum(slot, col);
-    }
-  };
-  // ---- gather tables (every point belongs to one support cell). Points past r point at
-  // a sentinel cell nc whose functions are all absent.
-  if (wi == 0) {
+  // ---- gather tables (every point belongs to one support cell; np, m <= r, n <= 64).
+  // Rows past r point at a sentinel cell nc whose functions are all absent.
+  {
     int moff = 0;
     for (int p = 0; p < nc; ++p) {
       const int32_t c = a.scell[s0 + p];
       const int mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
       const int np = (int)(a.cell_pt_off[c + 1] - a.cell_pt_off[c]);
       const int64_t d0 = a.dptr[c];
-#pragma unroll
-      for (int q = 0; q < NF; q += 64) invk[p * NF + q + lane] = 255;
+      invk[p * WR + lane] = 255;
       __builtin_amdgcn_wave_barrier();
-      if (lane < mc) invk[p * NF + a.slot[a.soff[s0 + p] + lane]] = (uint8_t)lane;
-      for (int q = lane; q < np; q += 64) {
-        ptp[moff + q] = (uint8_t)p;
-        ptq[moff + q] = (uint8_t)q;
-        zv[moff + q] = a.DN[d0 + (int64_t)q * mc + a.kself[s0 + p]];
+      if (lane < mc) invk[p * WR + a.slot[a.soff[s0 + p] + lane]] = (uint8_t)lane;
+      if (lane < np) {
+        ptp[moff + lane] = (uint8_t)p;
+        ptq[moff + lane] = (uint8_t)lane;
+        zv[moff + lane] = a.DN[d0 + (int64_t)lane * mc + a.kself[s0 + p]];
       }
       if (lane == 0) {
         cbase[p] = d0;
@@ -1342,127 +1305,109 @@ __global__ void __launch_bounds__(64 * RW * CW) __attribute__((amdgpu_waves_per_
       }
       moff += np;
     }
-#pragma unroll
-    for (int q = 0; q < NF; q += 64) invk[nc * NF + q + lane] = 255;
+    invk[nc * WR + lane] = 255;
     if (lane == 0) {
       cbase[nc] = cbase[0];
       cmc[nc] = 0;
     }
-    if (lane < 4) {  // pads read by the residual loop (rows in fours)
-      ptp[NR + lane] = (uint8_t)nc;
-      ptq[NR + lane] = 0;
-      vb[NR + lane] = 0.0;
+    if (lane >= r) {
+      ptp[lane] = (uint8_t)nc;
+      ptq[lane] = 0;
+      zv[lane] = 0.0;
     }
-  }
-  if (threadIdx.x < n) bv[threadIdx.x] = a.rhs[fs][a.row_ptr[i] + threadIdx.x];
-  if (cw == 0 && r0 + lane >= r) {
-    ptp[r0 + lane] = (uint8_t)nc;
-    ptq[r0 + lane] = 0;
-    zv[r0 + lane] = 0.0;
+    if (lane < 4) {  // pads read by the residual loop (rows in fours)
+      ptp[WR + lane] = (uint8_t)nc;
+      ptq[WR + lane] = 0;
+      vb[WR + lane] = 0.0;
+    }
+    if (lane < n) bv[lane] = a.rhs[fs][a.row_ptr[i] + lane];
   }
   __syncthreads();
-  // This wave's points of the column of A^T for row function fl, times z when zs; zero
-  // where !valid. Branch-free: every lane loads from a valid address and selects away what
-  // it does not have; the loads go out in batches of 16.
+  // Column of A^T for row function fl (every point), times z when zs; zero where !valid.
+  // Branch-free: every lane loads from a valid address and selects away what it does not
+  // have; the loads go out in batches of 16.
   auto gather = [&](int fl, bool valid, bool zs, double(&x)[WR]) {
     const int fq = valid ? fl : 0;
 #pragma unroll
     for (int m = 0; m < WR; ++m) {
-      const int p = ptp[r0 + m];
-      const int kk = invk[p * NF + fq];
+      const int p = ptp[m];
+      const int kk = invk[p * WR + fq];
       const bool has = valid && kk != 255;
-      const double v = AD[cbase[p] + (int64_t)ptq[r0 + m] * cmc[p] + (has ? kk : 0)];
-      x[m] = has ? (zs ? v * zv[r0 + m] : v) : 0.0;
+      const double v = AD[cbase[p] + (int64_t)ptq[m] * cmc[p] + (has ? kk : 0)];
+      x[m] = has ? (zs ? v * zv[m] : v) : 0.0;
       if ((m & 15) == 15) asm volatile("" ::: "memory");
     }
   };
-  // Column p of step j into vb, rows above j zero (written by the waves holding column p).
-  // The wave holding row j of it keeps the entry x0 in hx0 and sets vb[j] = x0 - R_jj =
-  // 1 / rv0 (so v_j = 1 up to rounding); its own LDS accesses are ordered, the other waves
-  // read vb after the barrier. Blocks wholly above row j are neither written nor read.
-  auto load_pivot = [&](const double(&x)[WR], int j, int p, double s2, double& rjj, double& rv0, double& tj) {
-    const bool own = cw == (p >> 6), rowj = own && j >= r0 && j < r0 + WR;
-    if (own) {
-      if (lane == (p & 63)) {
+  // The pivot column (lane p) of step j into vb, rows above j zero, and its reflector: vb[j]
+  // = x0 - R_jj = 1 / rv0 (so v_j = 1 up to rounding). Blocks wholly above row j are neither
+  // written nor read. Returns x0.
+  auto load_pivot = [&](const double(&x)[WR], int j, int p, double s2, double& rjj, double& rv0,
+                        double& tj) -> double {
+    if (lane == p) {
 #pragma unroll
-        for (int b = 0; b < WR / WB; ++b)
-          if (j < r0 + WB * b + WB) {
+      for (int b = 0; b < WR / WB; ++b)
+        if (j < WB * b + WB) {
 #pragma unroll
-            for (int m = WB * b; m < WB * b + WB; ++m) vb[r0 + m] = x[m];
-          }
-      }
-      if (r0 + lane < j) vb[r0 + lane] = 0.0;
+          for (int m = WB * b; m < WB * b + WB; ++m) vb[m] = x[m];
+        }
     }
-    if (rowj) {
-      asm volatile("" ::: "memory");
-      const double x0 = vb[j];
-      householder(x0, s2, &rjj, &rv0, &tj);
-      if (lane == 0) {
-        hx0 = x0;
-        vb[j] = x0 - rjj;
-      }
-    }
+    if (lane < j) vb[lane] = 0.0;
     __syncthreads();
-    if (!rowj) householder(hx0, s2, &rjj, &rv0, &tj);
+    const double x0 = vb[j];
+    householder(x0, s2, &rjj, &rv0, &tj);
+    if (lane == 0) vb[j] = x0 - rjj;
+    __syncthreads();
+    return x0;
   };
-  // This wave's part of v^T x (v = vb, zero above row j).
-  auto dot_part = [&](const double(&x)[WR], int j) -> double {
+  // v^T x (v = vb, zero above row j).
+  auto dot = [&](const double(&x)[WR], int j) -> double {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int b = 0; b < WR / WB; ++b)
-      if (j < r0 + WB * b + WB) {
+      if (j < WB * b + WB) {
 #pragma unroll
-        for (int m = WB * b; m < WB * b + WB; ++m) acc[m & 3] = fma(vb[r0 + m], x[m], acc[m & 3]);
+        for (int m = WB * b; m < WB * b + WB; ++m) acc[m & 3] = fma(vb[m], x[m], acc[m & 3]);
       }
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
   };
-  // x -= sv v on this wave's points; returns its part of the squared norm of the rows
-  // below j. Every lane runs it (sv = 0 leaves a column as it is).
+  // x -= sv v; returns the squared norm of the rows below j. Every lane runs it (sv = 0
+  // leaves a column as it is).
   auto update = [&](double(&x)[WR], int j, double sv) -> double {
     asm volatile("" ::: "memory");  // re-read vb rather than hold 64 more doubles
 #pragma unroll
     for (int b = 0; b < WR / WB; ++b)
-      if (j < r0 + WB * b + WB) {
+      if (j < WB * b + WB) {
 #pragma unroll
-        for (int m = WB * b; m < WB * b + WB; ++m) x[m] = fma(-sv, vb[r0 + m], x[m]);
+        for (int m = WB * b; m < WB * b + WB; ++m) x[m] = fma(-sv, vb[m], x[m]);
       }
     double ns[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int b = 0; b < WR / WB; ++b) {
-      if (j < r0 + WB * b) {
+      if (j < WB * b) {
 #pragma unroll
         for (int m = WB * b; m < WB * b + WB; ++m) ns[m & 3] = fma(x[m], x[m], ns[m & 3]);
-      } else if (j < r0 + WB * b + WB) {
+      } else if (j < WB * b + WB) {
 #pragma unroll
-        for (int m = WB * b; m < WB * b + WB; ++m) ns[m & 3] = fma(x[m], r0 + m > j ? x[m] : 0.0, ns[m & 3]);
+        for (int m = WB * b; m < WB * b + WB; ++m) ns[m & 3] = fma(x[m], m > j ? x[m] : 0.0, ns[m & 3]);
       }
     }
     return (ns[0] + ns[1]) + (ns[2] + ns[3]);
   };
   double x[WR];
-  // ---- 1. pivoted Householder QR of A^T (lane l of column wave c: column 64 c + l), with
-  // the early stop of k_tsvd2
-  gather(col, col < n, false, x);
-  double fro = 0.0;
+  // ---- 1. pivoted Householder QR of A^T (lane l: column l), with the early stop of k_tsvd2
+  gather(lane, lane < n, false, x);
+  double nrm = 0.0;  // squared norm of the rows from the current step on
 #pragma unroll
-  for (int m = 0; m < WR; ++m) fro = fma(x[m], x[m], fro);
-  double nrm = xsum(fro, 1);  // squared norm of the rows from the current step on
-  // position of columns lane and 64 + lane once pivoted (columns past n never are), kept in
-  // every wave so that all of them choose the same pivot
-  int posl = lane < n ? -1 : NF, posh = 64 + lane < n ? -1 : NF;
-  const double fa2 = wave_sum64(CW == 1 ? nrm : colsum(1, lane) + colsum(1, 64 + lane));
+  for (int m = 0; m < WR; ++m) nrm = fma(x[m], x[m], nrm);
+  const double fa2 = wave_sum64(nrm);
   const int kmax = min(n, r);
+  int pos = lane < n ? -1 : WR;  // position once pivoted (lanes past n never are)
   double s20 = 0.0, s2stop = 0.0;
   int kq = kmax;
   for (int j = 0; j < kmax; ++j) {
     double s2;
     int p;
-    if constexpr (CW == 1) {
-      wave_argmax64(posl < 0 ? nrm : -1.0, lane, s2, p);
-    } else {
-      const double vl = posl < 0 ? colsum(1, lane) : -1.0, vh = posh < 0 ? colsum(1, 64 + lane) : -1.0;
-      wave_argmax64(vh > vl ? vh : vl, vh > vl ? 64 + lane : lane, s2, p);
-    }
+    wave_argmax64(pos < 0 ? nrm : -1.0, lane, s2, p);
     if (j == 0) s20 = s2;
     if ((double)(n - j) * s2 < 1e-2 * a.tau * a.tau * s20) {
       kq = j;
@@ -1471,216 +1416,112 @@ __global__ void __launch_bounds__(64 * RW * CW) __attribute__((amdgpu_waves_per_
     }
     double rjj, rv0, tj;
     load_pivot(x, j, p, s2, rjj, rv0, tj);
-    if (threadIdx.x == 0) {
+    if (lane == p) {
       pk[j] = p;
       beta[j] = rjj;
+      pos = j;
     }
-    if (p == lane) posl = j;
-    if (p == 64 + lane) posh = j;
-    const int pos = cw == 0 ? posl : posh;
-    const double d = xsum(dot_part(x, j), 0);
-    nrm = xsum(update(x, j, pos < 0 ? tj * rv0 * rv0 * d : 0.0), 1);
+    const double d = dot(x, j);
+    nrm = update(x, j, pos < 0 ? tj * rv0 * rv0 * d : 0.0);
   }
   // ---- 2. rank proof: sigma_{k+1} <= ||R22||_F <= sqrt((n - k) s2stop) and sigma_k >=
   // 1 / ||R11^-1||_F - ||R22||_F (as in k_tsvd2)
   const double r22 = kq < kmax ? sqrt((double)(n - kq) * s2stop) : 0.0;
-  {
-    const int pos = cw == 0 ? posl : posh;
-    if (pos >= 1 && pos < kq && r0 < pos) {
-      const int base = pos * (pos - 1) / 2 + r0;
+  if (pos >= 1 && pos < kq) {
+    const int base = pos * (pos - 1) / 2;
 #pragma unroll
-      for (int m = 0; m < WR; ++m)
-        if (r0 + m < pos) rp[base + m] = x[m];
-    }
-    for (int c = threadIdx.x; c < kq; c += 64 * NW) ib[c] = 1.0 / beta[c];
+    for (int m = 0; m < WR - 1; ++m)
+      if (m < pos) rp[base + m] = x[m];
   }
+  if (lane < kq) ib[lane] = 1.0 / beta[lane];
   __syncthreads();
-  // Column c of S = R11^-T (lower triangular), rows [i0, i1): S[ii][c] = (delta_{ii c} -
-  // g_ii - sum_{i0 <= jj < ii} R[jj][ii] S[jj][c]) / R[ii][ii], with g_ii the sum over the
-  // rows before i0 (zero for i0 = 0, or for c >= i0, where they are zero). With gout, also
-  // g_ii for the rows [64, kq) after the block, into gh (64 values per row).
-  double* gh = rp + (size_t)a.rp_n * (a.rp_n - 1) / 2;
-  auto fsub = [&](int c, int i0, int i1, bool gin, bool gout) -> double {
+  double lo = 0.0;
+  bool fast = false;
+  if (s20 > 0.0 && kq > 0) {
+    // column `lane` of S = R11^-T (lower triangular): S[ii][c] = (delta - sum_{jj < ii}
+    // R[jj][ii] S[jj][c]) / R[ii][ii]; the entries above the diagonal come out zero
     double t[WR];
     double tn = 0.0;
 #pragma unroll
-    for (int q = 0; q < WR; ++q) {
-      const int ii = i0 + q;
-      if (ii < i1) {  // a uniform branch, not an exit: the loop unrolls fully
-        const double* Rc = rp + ii * (ii - 1) / 2;
+    for (int ii = 0; ii < WR; ++ii) {
+      if (ii < kq) {  // a uniform branch, not an exit: the loop unrolls fully
         double sa[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int qq = 0; qq < q; ++qq) {
-          sa[qq & 3] = fma(Rc[i0 + qq], t[qq], sa[qq & 3]);
-          if ((qq & 15) == 15) asm volatile("" ::: "memory");  // at most 16 loads in flight
+        for (int jj = 0; jj < ii; ++jj) {
+          sa[jj & 3] = fma(rp[ii * (ii - 1) / 2 + jj], t[jj], sa[jj & 3]);
+          if ((jj & 15) == 15) asm volatile("" ::: "memory");  // at most 16 loads in flight
         }
-        // (read in any case, without a branch; with two column waves gh holds at least one
-        // row, n_max > 64)
-        const double gv = CW > 1 ? gh[max(ii - 64, 0) * 64 + lane] : 0.0;
-        const double g = gin ? gv : 0.0;
-        const double v = ((c == ii ? 1.0 : 0.0) - g - ((sa[0] + sa[1]) + (sa[2] + sa[3]))) * ib[ii];
-        t[q] = v;
+        const double v = ((lane == ii ? 1.0 : 0.0) - ((sa[0] + sa[1]) + (sa[2] + sa[3]))) * ib[ii];
+        t[ii] = v;
         tn = fma(v, v, tn);
       }
     }
-    if (gout)
-      for (int ii = 64; ii < kq; ++ii) {
-        const double* Rc = rp + ii * (ii - 1) / 2;
-        double sa[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int q = 0; q < WR; ++q) {
-          sa[q & 3] = fma(Rc[q], t[q], sa[q & 3]);
-          if ((q & 15) == 15) asm volatile("" ::: "memory");
-        }
-        gh[(ii - 64) * 64 + lane] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
-      }
-    return tn;
-  };
-  double lo = 0.0;
-  bool fast = false;
-  if constexpr (CW == 1) {
-    if (wi == 0) {
-      if (s20 > 0.0 && kq > 0) {
-        lo = 1.0 / sqrt(wave_sum64(fsub(lane, 0, kq, false, false))) - r22;
-        fast = lo > 100.0 * a.tau * sqrt(fa2);
-      }
-      if (NW > 1 && lane == 0) flag = fast ? 1 : 0;
-    }
-    if constexpr (NW > 1) {
-      __syncthreads();
-      fast = flag != 0;
-    }
-  } else {
-    // columns below 64: rows [0, 64) in the first wave, handing over the rest of each row's
-    // sum in gh, then rows [64, kq) in the wave of the second 64 points; columns from 64 on:
-    // rows [64, kq) in the first wave of the second column wave (one call site for the two,
-    // so that the compiler keeps one copy of the substitution's registers)
-    const bool ok = s20 > 0.0 && kq > 0;
-    if (ok && wi == 0) {
-      const double tn = wave_sum64(fsub(lane, 0, min(kq, 64), false, kq > 64));
-      if (lane == 0) tsum[0] = tn;
-    }
-    __syncthreads();
-    if (ok && kq > 64 && rw + cw == 1) {  // (kq > 64 implies r > 64: wave (1, 0) exists)
-      const double tn = wave_sum64(fsub(64 * cw + lane, 64, kq, cw == 0, false));
-      if (lane == 0) tsum[1 + cw] = tn;
-    }
-    __syncthreads();
-    if (ok) {
-      lo = 1.0 / sqrt(kq > 64 ? (tsum[0] + tsum[1]) + tsum[2] : tsum[0]) - r22;
-      fast = lo > 100.0 * a.tau * sqrt(fa2);
-    }
+    lo = 1.0 / sqrt(wave_sum64(tn)) - r22;
+    fast = lo > 100.0 * a.tau * sqrt(fa2);
   }
   if (!fast) {
     to_svd();
     return;
   }
-  // ---- 3. Householder QR of X = Z A_k^T (column c: position c)
-  gather(col < kq ? pk[col] : 0, col < kq, true, x);
-  {
-    double nn = 0.0;
+  // ---- 3. Householder QR of X = Z A_k^T (lane c: position c)
+  gather(lane < kq ? pk[lane] : 0, lane < kq, true, x);
+  nrm = 0.0;
 #pragma unroll
-    for (int m = 0; m < WR; ++m) nn = fma(x[m], x[m], nn);
-    nrm = xsum(nn, 1);
-  }
+  for (int m = 0; m < WR; ++m) nrm = fma(x[m], x[m], nrm);
   for (int j = 0; j < kq; ++j) {
     double rjj, rv0, tj;
-    load_pivot(x, j, j, NW == 1 ? readlane_f64(nrm, j) : colsum(1, j), rjj, rv0, tj);
-    if (threadIdx.x == 0) {
+    const double x0 = load_pivot(x, j, j, readlane_f64(nrm, j), rjj, rv0, tj);
+    if (lane == 0) {
       beta[j] = rjj;
       tau2[j] = tj;
       rv2[j] = rv0;
-      uv2[j] = hx0 - rjj;  // x0 - R_jj
+      uv2[j] = x0 - rjj;
     }
-    const bool act = col > j && col < kq;
-    const double d = xsum(dot_part(x, j), 0);
-    nrm = xsum(update(x, j, act ? tj * rv0 * rv0 * d : 0.0), 1);
+    const double d = dot(x, j);
+    nrm = update(x, j, lane > j && lane < kq ? tj * rv0 * rv0 * d : 0.0);
   }
   // X has full column rank (sigma_k(A) > 0 and z > 0 on the points); R_jj != 0 is checked
-  // anyway before dividing by it (beta is the same in every wave: its last write precedes
-  // a barrier, or with one wave, the reads)
-  {
-    bool bad = lane < kq && !(fabs(beta[lane]) > 0.0 && fabs(beta[lane]) < INFINITY);
-    if (CW > 1) bad = bad || (64 + lane < kq && !(fabs(beta[64 + lane]) > 0.0 && fabs(beta[64 + lane]) < INFINITY));
-    if (__any(bad)) {
-      to_svd();
-      return;
-    }
+  // anyway before dividing by it
+  if (__any(lane < kq && !(fabs(beta[lane]) > 0.0 && fabs(beta[lane]) < INFINITY))) {
+    to_svd();
+    return;
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     atomicMin(a.min_kept, dbits(lo / sqrt(fa2)));       // a lower bound of sigma_k / sigma_1
     atomicMax(a.max_dropped, dbits(r22 / sqrt(s20)));  // an upper bound of sigma_{k+1} / sigma_1
     if (kq < n) atomicAdd(a.truncated, 1ULL);
     atomicAdd(a.certified, 1ULL);
   }
-  // ---- 4. u = Q [R^-T c; 0] for the right-hand side c (cv: c of the lane's column;
-  // result in the first column wave: lane m of row wave v, point 64 v + m). R^-T by
-  // columns of R (the lane of column c holds R[.][c] at its points); Q = H_0 ... H_{k-1}
-  // applied to [y; 0] in reverse, with the reflectors of step 3.
+  // ---- 4. u = Q [R^-T c; 0] for the right-hand side c (lane c: c_c; result: lane m, row
+  // m). R^-T by columns of R (lane c holds R[0..c-1][c]); Q = H_0 ... H_{k-1} applied to
+  // [y; 0] in reverse, with the reflectors of step 3.
   auto solve = [&](double cv) -> double {
-    double u = 0.0;
-    // y_ii for ii < 64 in the first wave (lane ii)
-    if (wi == 0) {
-      const double id = lane < kq ? 1.0 / beta[lane] : 0.0;
-      double acc = 0.0;
+    const double id = lane < kq ? 1.0 / beta[lane] : 0.0;
+    double u = 0.0, acc = 0.0;
 #pragma unroll
-      for (int ii = 0; ii < WR; ++ii) {
-        if (ii < kq) {
-          const double yi = readlane_f64((cv - acc) * id, ii);
-          if (lane == ii) u = yi;
-          acc = fma(x[ii], yi, acc);
-        }
-      }
-    }
-    if constexpr (CW > 1) {
-      if (kq > 64) {  // (implies r > 64: the second row wave exists)
-        if (wi == 0) ysh[lane] = u;
-        __syncthreads();
-        // columns from 64 on: the part of their sums over rows below 64 (first row wave of
-        // the second column wave), then rows [64, kq) in the second row wave
-        if (rw == 0 && cw == 1) {
-          double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int m = 0; m < WR; ++m) acc[m & 3] = fma(x[m], ysh[m], acc[m & 3]);
-          ysh[64 + lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        }
-        __syncthreads();
-        if (rw == 1 && cw == 1) {
-          const int c = 64 + lane;
-          const double id = c < kq ? 1.0 / beta[c] : 0.0;
-          double acc = ysh[c], yv = 0.0;
-#pragma unroll
-          for (int q = 0; q < WR; ++q) {
-            if (64 + q < kq) {
-              const double yi = readlane_f64((cv - acc) * id, q);
-              if (lane == q) yv = yi;
-              acc = fma(x[q], yi, acc);
-            }
-          }
-          ysh[c] = yv;  // (this lane read ysh[c] above: its own accesses are ordered)
-        }
-        __syncthreads();
-        if (rw == 1 && cw == 0) u = ysh[64 + lane];
+    for (int ii = 0; ii < WR; ++ii) {
+      if (ii < kq) {
+        const double yi = readlane_f64((cv - acc) * id, ii);
+        if (lane == ii) u = yi;
+        acc = fma(x[ii], yi, acc);
       }
     }
     for (int j = kq - 1; j >= 0; --j) {
-      if (cw == (j >> 6)) {
-        if (lane == (j & 63)) {
+      if (lane == j) {
 #pragma unroll
-          for (int b = 0; b < WR / WB; ++b)
-            if (j < r0 + WB * b + WB) {
+        for (int b = 0; b < WR / WB; ++b)
+          if (j < WB * b + WB) {
 #pragma unroll
-              for (int m = WB * b; m < WB * b + WB; ++m) vb[r0 + m] = x[m];
-            }
-        }
-        if (r0 + lane < j) vb[r0 + lane] = 0.0;
-        if (lane == 0 && j >= r0 && j < r0 + WR) vb[j] = uv2[j];
+            for (int m = WB * b; m < WB * b + WB; ++m) vb[m] = x[m];
+          }
       }
+      if (lane < j) vb[lane] = 0.0;
+      if (lane == 0) vb[j] = uv2[j];
       __syncthreads();
-      const double vm = cw == 0 && r0 + lane < r ? vb[r0 + lane] * rv2[j] : 0.0;
-      const double d = xsum(wave_sum64(vm * u), 0);
+      const double vm = lane < r ? vb[lane] * rv2[j] : 0.0;
+      const double d = wave_sum64(vm * u);
       u = fma(-tau2[j] * d, vm, u);
-      if constexpr (NW == 1) __syncthreads();
+      __syncthreads();
     }
     return u;
   };
@@ -1688,33 +1529,31 @@ __global__ void __launch_bounds__(64 * RW * CW) __attribute__((amdgpu_waves_per_
   // A_k w (A_k re-read from the basis blocks, w broadcast through vb), w += Z solve(rho).
   // It takes the residual of the kept equations from about eps kappa(X) to rounding level.
   // (solve runs in every lane: it holds barriers and cross-lane sums)
-  const double u0 = solve(col < kq ? bv[pk[col]] : 0.0);
-  const double w = r0 + lane < r ? zv[r0 + lane] * u0 : 0.0;
-  if (cw == 0) vb[r0 + lane] = w;
+  const double u0 = solve(lane < kq ? bv[pk[lane]] : 0.0);
+  const double w = lane < r ? zv[lane] * u0 : 0.0;
+  vb[lane] = w;
   __syncthreads();
   double rho = 0.0;
   {
-    const int fq = col < kq ? pk[col] : 0;
+    const int fq = lane < kq ? pk[lane] : 0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int m1 = min(r, r0 + WR);
-    for (int m0 = r0; m0 < m1; m0 += 4) {  // a runtime loop (no register index depends on m);
-      // points past r read the sentinel cell (and vb = 0), the last wave's the pads
+    for (int m0 = 0; m0 < r; m0 += 4) {  // a runtime loop (no register index depends on m); rows
+      // past r read the pads (sentinel cell, vb = 0)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int m = m0 + e;
         const int p = ptp[m];
-        const int kk = invk[p * NF + fq];
-        const bool has = col < kq && kk != 255;
+        const int kk = invk[p * WR + fq];
+        const bool has = lane < kq && kk != 255;
         const double v = AD[cbase[p] + (int64_t)ptq[m] * cmc[p] + (has ? kk : 0)];
         acc[e] = fma(has ? v : 0.0, vb[m], acc[e]);
       }
     }
-    const double s = xsum((acc[0] + acc[1]) + (acc[2] + acc[3]), 1);
-    if (col < kq) rho = bv[fq] - s;
+    if (lane < kq) rho = bv[fq] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
   }
   __syncthreads();
   const double dw = solve(rho);
-  if (cw == 0 && r0 + lane < r) a.W[fs][a.qptr[i] + r0 + lane] = fma(zv[r0 + lane], dw, w);
+  if (lane < r) a.W[fs][a.qptr[i] + lane] = fma(zv[lane], dw, w);
 }
 
 
@@ -1979,9 +1818,11 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     tm.stop();
     return ls;
   };
-  // Systems of at most 128 constraints (and 256 points) go to the register-resident solver
-  // first; the ones its rank proof does not cover are listed and solved by the SVD kernel
-  // of their bucket afterwards (one synchronisation to read the list lengths).
+  // Systems of at most 64 constraints and 64 points go to the one-wave solver first; the
+  // ones its rank proof does not cover are listed and solved by the SVD kernel of their
+  // bucket afterwards (one synchronisation to read the list lengths). (Several waves per
+  // system, for more points or constraints, lost to the SVD kernel's certified path once
+  // its second factorisation was Householder: their barriers cost more than they save.)
   DBuf fbl, fbc;
   int fbn[NBKT];
   bool any_w = false;
@@ -1992,47 +1833,22 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     const int64_t ns = hist[b];
     if (ns == 0) continue;
     const int bn = b / NB_R, br = b % NB_R;
-    // the register-resident solver, one wave per 64 points and 64 constraints: all systems
-    // of n <= 64, and those of n <= 128 with r <= 128 (for larger ones, whose waves spend
-    // more of their time at barriers, the SVD kernel's certified path is as fast)
-    if (bn <= 3 || br <= 3) {
+    if (bn <= 3 && br == 0) {  // n <= 64, r <= 64
       TsvdArgs ta = base;
       ta.rows = lists.as<int32_t>() + start[b];
       ta.nsys = ns;
       ta.fb_list = fbl.as<int32_t>() + start[b] * nfam;
       ta.fb_count = fbc.as<int>() + b;
       // dynamic LDS: R11 of the bucket's largest system (more workgroups per CU for the
-      // smaller buckets; the layout, and so the arithmetic, does not depend on it), and with
-      // two column waves the hand-over of the rank proof
+      // smaller buckets; the layout, and so the arithmetic, does not depend on it)
       const int mn = hist[2 * (NBKT + 1) + 2 * b];
       ta.rp_n = mn;
-      const int rw = br == 0 ? 1 : br <= 3 ? 2 : br <= 5 ? 3 : 4;  // r <= 64, 128, 192, 256
-      const int cw = bn <= 3 ? 1 : 2;                              // n <= 64, 128
-      const size_t lds = ((size_t)mn * (mn - 1) / 2 + (cw > 1 && mn > 64 ? (size_t)(mn - 64) * 64 : 0)) * sizeof(double);
-      static const void* const fns[2][4] = {
-          {(const void*)k_wsolve<1, 1>, (const void*)k_wsolve<2, 1>, (const void*)k_wsolve<3, 1>, (const void*)k_wsolve<4, 1>},
-          {(const void*)k_wsolve<1, 2>, (const void*)k_wsolve<2, 2>, nullptr, nullptr}};  // (r <= 128 with n > 64)
-      static const char* const names[2][4] = {{"k_wsolve<1,1>", "k_wsolve<2,1>", "k_wsolve<3,1>", "k_wsolve<4,1>"},
-                                              {"k_wsolve<1,2>", "k_wsolve<2,2>", "", ""}};
-      const void* fn = fns[cw - 1][rw - 1];
-      hipFuncAttributes fa{};
-      if (hipFuncGetAttributes(&fa, fn) != hipSuccess || fa.sharedSizeBytes + lds > 160 * 1024) {
-        set_error("solve_weights: a weight system (n=" + std::to_string(mn) + ") does not fit the solver's LDS");
-        s = WQ_EINVAL;
-        break;
-      }
-      if (lds > 64 * 1024 &&
-          hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
-        set_error("solve_weights: cannot raise the LDS limit of the register-resident solver");
-        s = WQ_EDEVICE;
-        break;
-      }
-      KTimer tm(names[cw - 1][rw - 1], (int64_t)bflops[b] * nfam, st);
-      void* args[] = {&ta};
-      const hipError_t le = hipLaunchKernel(fn, dim3((unsigned)(ns * nfam)), dim3(64 * rw * cw), args, lds, st);
+      const size_t lds = (size_t)mn * (mn - 1) / 2 * sizeof(double);
+      KTimer tm("k_wsolve", (int64_t)bflops[b] * nfam, st);
+      k_wsolve<<<dim3((unsigned)(ns * nfam)), dim3(64), lds, st>>>(ta);
       tm.stop();
-      if (le != hipSuccess) {
-        set_error("solve_weights: register-resident solver launch failed");
+      if (hipGetLastError() != hipSuccess) {
+        set_error("solve_weights: one-wave solver launch failed");
         s = WQ_EDEVICE;
       }
       any_w = true;
@@ -2045,7 +1861,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
         hipStreamSynchronize(st) != hipSuccess)
       s = WQ_EDEVICE;
     for (int b = 0; b < NBKT && s == WQ_OK; ++b)
-      if (hist[b] && (b / NB_R <= 3 || b % NB_R <= 3) && fbn[b] > 0)
+      if (hist[b] && b / NB_R <= 3 && b % NB_R == 0 && fbn[b] > 0)
         s = svd_launch(b, fbl.as<int32_t>() + start[b] * nfam, fbn[b], 0);
   }
   dfree(fbl);
