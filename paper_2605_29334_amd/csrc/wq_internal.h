@@ -178,6 +178,7 @@ struct KTimer {
 constexpr int TILE_ROWS = 8;
 constexpr int T2_ROWS = 16;    // rows per cell-major assembly tile (MFMA 16 x 16 x 4 columns)
 constexpr int T2_NZCAP = 416;  // CSR entries per cell-major tile (8 rows of 52; 16 short rows)
+constexpr int T2_STEPCAP = 128;  // summed row steps (support cells' blocks of 4 points) per tile
 
 // 64-bit index launch helper
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }

@@ -942,21 +942,50 @@ wq_status build_tiles(wq_mesh* M, wq_points* P, DBuf& flags, hipStream_t st) {
   return WQ_OK;
 }
 
-// Cell-major tiles: runs of consecutive rows, at most T2_ROWS rows and T2_NZCAP CSR entries
-// each (the tile's accumulators live in LDS), cut greedily in row order on the host.
+// Work of each row in the cell-major assembly: one step per block of four points of each of
+// its support cells.
+__global__ void k_row_steps(int64_t n, const int64_t* sptr, const int32_t* scell, const int64_t* cell_pt_off,
+                            int32_t* steps) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int w = 0;
+  for (int64_t p = sptr[i]; p < sptr[i + 1]; ++p) {
+    const int32_t c = scell[p];
+    w += (int)((cell_pt_off[c + 1] - cell_pt_off[c] + 3) / 4);
+  }
+  steps[i] = w;
+}
+
+// Cell-major tiles: runs of consecutive rows, at most T2_ROWS rows, T2_NZCAP CSR entries
+// (the tile's accumulators live in LDS) and T2_STEPCAP summed row steps each, cut greedily in
+// row order on the host. The step cap keeps the tiles next to extraordinary points (rows of
+// many cells with many points) from taking several times the average tile's time: one wave
+// runs a tile, so the heaviest tile sets the launch's end. (A row's sums do not depend on
+// the tile it is in.)
 wq_status build_tiles2(wq_points* P, DBuf& flags, hipStream_t st) {
   const int64_t n = P->n_rows;
   WQ_CHECK(n < INT32_MAX, WQ_EINVAL, "build_points: too many rows for 32-bit tile row ids");
   std::vector<int64_t> rp(n + 1);
-  WQ_HIP(hipMemcpyAsync(rp.data(), P->row_ptr.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  WQ_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> rw(n);
+  {
+    DBuf steps;
+    WQ_TRY(dalloc_n<int32_t>(steps, (size_t)n));
+    if (n > 0)
+      k_row_steps<<<nblocks(n, BS), BS, 0, st>>>(n, P->supp_ptr.as<int64_t>(), P->supp_cell.as<int32_t>(),
+                                                  P->cell_pt_off.as<int64_t>(), steps.as<int32_t>());
+    WQ_HIP(hipMemcpyAsync(rp.data(), P->row_ptr.p, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    WQ_HIP(hipMemcpyAsync(rw.data(), steps.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    WQ_HIP(hipStreamSynchronize(st));
+    dfree(steps);
+  }
   std::vector<int32_t> row0;
   row0.reserve(n / 8 + 2);
   int32_t maxnz = 0;
   for (int64_t i = 0; i < n;) {
     const int64_t s = i;
-    int64_t nz = 0;
-    while (i < n && i - s < T2_ROWS && nz + (rp[i + 1] - rp[i]) <= T2_NZCAP) nz += rp[i + 1] - rp[i], ++i;
+    int64_t nz = 0, w = 0;
+    while (i < n && i - s < T2_ROWS && nz + (rp[i + 1] - rp[i]) <= T2_NZCAP && (i == s || w + rw[i] <= T2_STEPCAP))
+      nz += rp[i + 1] - rp[i], w += rw[i], ++i;
     WQ_CHECK(i > s, WQ_EINVAL, "build_points: a row exceeds the cell-major tile capacity");
     row0.push_back((int32_t)s);
     maxnz = std::max(maxnz, (int32_t)nz);
