@@ -117,16 +117,22 @@ def measure_batched(W, torch, pool, copies):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     s = torch.cuda.Stream()
-    B.graph_assemble(None, None, Mb, Kb, stream=s)
-    s.synchronize()
     reps = 20
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        B.graph_assemble(None, None, Mb, Kb, stream=s)
-    e1.record(s)
-    e1.synchronize()
-    g_ms = e0.elapsed_time(e1) / reps
+
+    def graph_ms():
+        B.graph_assemble(None, None, Mb, Kb, stream=s)  # (captured again after a retune)
+        s.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            B.graph_assemble(None, None, Mb, Kb, stream=s)
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    g0_ms = graph_ms()
+    cap, chunk, _ = W.autotune_tiles(B.points, B.weights)  # tile work cap and XCD run length
+    g_ms = graph_ms()
     outs = [(W.assemble_mass_stiffness(p, w)) for (_, p, w) in per]  # outputs allocated once
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -140,7 +146,8 @@ def measure_batched(W, torch, pool, copies):
     return {"meshes": len(meshes), "rows": int(B.points.n_rows), "nnz_M_plus_K": int(nnz),
             "setup_to_matrices_s": {"one_by_one": t_single, "batched": t_batch},
             "nnz_per_s_setup_to_matrices": {"one_by_one": nnz / t_single, "batched": nnz / t_batch},
-            "assembly_ms": {"eager_per_mesh": s_ms, "batched_graph": g_ms},
+            "assembly_ms": {"eager_per_mesh": s_ms, "batched_graph": g_ms, "batched_graph_default_tiles": g0_ms},
+            "autotuned": {"tile_step_cap": cap, "xcd_chunk": chunk},
             "nnz_per_s_assembly": {"eager_per_mesh": nnz / (s_ms * 1e-3), "batched_graph": nnz / (g_ms * 1e-3)}}
 
 

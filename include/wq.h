@@ -404,6 +404,19 @@ void wq_batch_destroy(wq_batch* batch);
 wq_status wq_autotune_assembly(wq_points* pts, const wq_weights* w, wq_stream stream, int32_t* chosen_chunk,
                                double* best_ms);
 
+/* wq_autotune_tiles: the tile shape of the same assembly, tuned with the run length. The
+ * cell-major tiles (runs of at most 16 consecutive rows and 416 CSR entries, one wave each)
+ * are also capped by their summed row steps (a row's step count: the blocks of four points
+ * of its support cells), so that tiles next to extraordinary points do not take several
+ * times the average tile's time. For each candidate cap (64, 96, 128, 192, 256, none) the
+ * tiles of `pts` are rebuilt and the run length tuned as above; the fastest pair is kept in
+ * the handle and returned with its median time in ms (the default cap is 128). Values are
+ * unchanged: a row's sums do not depend on its tile. A batch's captured assembly graph is
+ * captured again at its next call. Calls on `pts` must not overlap this one; synchronises
+ * `stream`. */
+wq_status wq_autotune_tiles(wq_points* pts, const wq_weights* w, wq_stream stream, int32_t* chosen_stepcap,
+                            int32_t* chosen_chunk, double* best_ms);
+
 /* ------------------------------------------------------------------ kernel timing
  * Measurement aid. While enabled (per process), the library records a pair of HIP
  * events on the launch stream around each of its main kernels (basis evaluation,

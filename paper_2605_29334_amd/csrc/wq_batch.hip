@@ -4,7 +4,8 @@
 // points, weights and matrix values are those it gets alone, while the uneven weight
 // systems of all meshes share the size buckets of one TSVD launch per bucket and the
 // assembly tiles run in one launch. The repeated assembly can be captured in a HIP graph
-// and replayed. An autotuner picks the assembly's XCD chunk length by measurement.
+// and replayed. An autotuner picks the assembly's tile shape (the cap on a tile's work) and
+// XCD run length by measurement.
 #include "wq_internal.h"
 
 #include <algorithm>
@@ -24,6 +25,7 @@ struct wq_batch {
   hipGraphExec_t exec = nullptr;
   const void* g_args[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int g_prec = -1;
+  int64_t g_gen = -1;  // tile generation of the points when captured
   hipStream_t g_stream = nullptr;
 };
 
@@ -142,7 +144,7 @@ extern "C" wq_status wq_batch_graph_assemble(wq_batch* b, const double* c, const
   hipStream_t st = (hipStream_t)stream;
   WQ_CHECK(st != nullptr, WQ_EINVAL, "wq_batch_graph_assemble: capture needs a created stream, not the null stream");
   const void* args[5] = {c, k, mass_vals, stiff_vals, nullptr};
-  bool same = b->exec && b->g_prec == (int)prec && b->g_stream == st;
+  bool same = b->exec && b->g_prec == (int)prec && b->g_stream == st && b->g_gen == b->pts->t2_gen;
   for (int t = 0; t < 4; ++t) same = same && args[t] == b->g_args[t];
   if (!same) {
     drop_graph(b);
@@ -167,6 +169,7 @@ extern "C" wq_status wq_batch_graph_assemble(wq_batch* b, const double* c, const
     for (int t = 0; t < 4; ++t) b->g_args[t] = args[t];
     b->g_prec = (int)prec;
     b->g_stream = st;
+    b->g_gen = b->pts->t2_gen;
   }
   WQ_HIP(hipGraphLaunch(b->exec, st));
   return WQ_OK;
@@ -182,31 +185,34 @@ extern "C" void wq_batch_destroy(wq_batch* b) {
 }
 
 // ------------------------------------------------------------------ autotuner
-extern "C" wq_status wq_autotune_assembly(wq_points* P, const wq_weights* w, wq_stream stream, int32_t* chosen,
-                                          double* best_ms) {
-  WQ_CHECK(P && w, WQ_EINVAL, "wq_autotune_assembly: null argument");
-  hipStream_t st = (hipStream_t)stream;
-  DBuf M, K;
-  WQ_TRY(dalloc_n<double>(M, P->nnz));
-  WQ_TRY(dalloc_n<double>(K, P->nnz));
-  // run lengths up to one contiguous band of tiles per XCD
+namespace {
+
+// Median time (ms) of the FP64 mass + stiffness assembly on P for each candidate XCD run
+// length (powers of two from 4 to 1024 below one contiguous band of tiles per XCD, then
+// the band); sets P->asm_chunk to the fastest and returns it with its time.
+wq_status tune_chunk(wq_points* P, const wq_weights* w, hipStream_t st, double* M, double* K, int* best,
+                     double* best_t) {
   const int band = (int)((P->n_t2 + 7) / 8);
   std::vector<int> cand;
   for (int c = 4; c < band && c <= 1024; c *= 2) cand.push_back(c);
-  cand.push_back(band);
+  cand.push_back(std::max(band, 1));
   hipEvent_t e0, e1;
   WQ_HIP(hipEventCreate(&e0));
-  WQ_HIP(hipEventCreate(&e1));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("autotune: hipEventCreate failed");
+    return WQ_EDEVICE;
+  }
   const int keep = P->asm_chunk;
-  int best = keep;
-  double best_t = 1e300;
+  *best = keep;
+  *best_t = 1e300;
   wq_status s = WQ_OK;
   for (int c : cand) {
     P->asm_chunk = c;
     std::vector<float> ts;
     for (int rep = 0; rep < 6 && s == WQ_OK; ++rep) {
       if (hipEventRecord(e0, st) != hipSuccess) s = WQ_EDEVICE;
-      if (s == WQ_OK) s = assemble_mass_stiffness(P, w, nullptr, nullptr, M.p, K.p, WQ_FP64, stream);
+      if (s == WQ_OK) s = assemble_mass_stiffness(P, w, nullptr, nullptr, M, K, WQ_FP64, (wq_stream)st);
       float ms = 0.f;
       if (s == WQ_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
@@ -216,17 +222,72 @@ extern "C" wq_status wq_autotune_assembly(wq_points* P, const wq_weights* w, wq_
     if (s != WQ_OK) break;
     std::sort(ts.begin(), ts.end());
     const double med = ts[ts.size() / 2];
-    if (med < best_t) {
-      best_t = med;
-      best = c;
+    if (med < *best_t) {
+      *best_t = med;
+      *best = c;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  dfree(M);
-  dfree(K);
-  P->asm_chunk = s == WQ_OK ? best : keep;
+  P->asm_chunk = s == WQ_OK ? *best : keep;
+  return s;
+}
+
+}  // namespace
+
+extern "C" wq_status wq_autotune_assembly(wq_points* P, const wq_weights* w, wq_stream stream, int32_t* chosen,
+                                          double* best_ms) {
+  WQ_CHECK(P && w && w->pts == P, WQ_EINVAL, "wq_autotune_assembly: bad arguments");
+  DBuf M, K;
+  WQ_TRY(dalloc_n<double>(M, P->nnz));
+  WQ_TRY(dalloc_n<double>(K, P->nnz));
+  int best = P->asm_chunk;
+  double best_t = 0.0;
+  const wq_status s = tune_chunk(P, w, (hipStream_t)stream, M.as<double>(), K.as<double>(), &best, &best_t);
+  ++P->t2_gen;  // the schedule changed
+  DBuf* tmp[] = {&M, &K};
+  dfree_many(tmp, 2);
   if (chosen) *chosen = P->asm_chunk;
+  if (best_ms) *best_ms = best_t;
+  return s;
+}
+
+extern "C" wq_status wq_autotune_tiles(wq_points* P, const wq_weights* w, wq_stream stream, int32_t* chosen_stepcap,
+                                       int32_t* chosen_chunk, double* best_ms) {
+  WQ_CHECK(P && w && w->pts == P, WQ_EINVAL, "wq_autotune_tiles: bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  DBuf M, K;
+  WQ_TRY(dalloc_n<double>(M, P->nnz));
+  WQ_TRY(dalloc_n<double>(K, P->nnz));
+  // candidate caps on a tile's summed row steps (blocks of four points of its rows' support
+  // cells): from about four regular rows up to none (the row and CSR-entry limits alone)
+  const int caps[] = {64, 96, 128, 192, 256, 1 << 30};
+  const int keep_cap = P->t2_stepcap, keep_chunk = P->asm_chunk;
+  int best_cap = keep_cap, best_chunk = keep_chunk;
+  double best_t = 1e300;
+  wq_status s = WQ_OK;
+  for (int cap : caps) {
+    P->t2_stepcap = cap;
+    s = rebuild_tiles2(P, st);
+    int ch = 0;
+    double t = 0.0;
+    if (s == WQ_OK) s = tune_chunk(P, w, st, M.as<double>(), K.as<double>(), &ch, &t);
+    if (s != WQ_OK) break;
+    if (t < best_t) {
+      best_t = t;
+      best_cap = cap;
+      best_chunk = ch;
+    }
+  }
+  // keep the fastest (or, after an error, what the handle had)
+  P->t2_stepcap = s == WQ_OK ? best_cap : keep_cap;
+  const wq_status s2 = rebuild_tiles2(P, st);
+  P->asm_chunk = s == WQ_OK ? best_chunk : keep_chunk;
+  DBuf* tmp[] = {&M, &K};
+  dfree_many(tmp, 2);
+  if (s == WQ_OK && s2 != WQ_OK) s = s2;
+  if (chosen_stepcap) *chosen_stepcap = P->t2_stepcap;
+  if (chosen_chunk) *chosen_chunk = P->asm_chunk;
   if (best_ms) *best_ms = best_t;
   return s;
 }

@@ -63,6 +63,11 @@ template <class T> inline wq_status dalloc_n(DBuf& b, size_t n) { return dalloc(
 // element type codes (WQ_ARR_ETYPE)
 enum : uint8_t { ET_PASSIVE = 0, ET_REGULAR = 1, ET_BOUNDARY = 2, ET_IRREGULAR = 3, ET_TRANSITION = 4 };
 
+constexpr int TILE_ROWS = 8;
+constexpr int T2_ROWS = 16;    // rows per cell-major assembly tile (MFMA 16 x 16 x 4 columns)
+constexpr int T2_NZCAP = 416;  // CSR entries per cell-major tile (8 rows of 52; 16 short rows)
+constexpr int T2_STEPCAP = 128;  // default: summed row steps (support cells' blocks of 4 points) per tile
+
 }  // namespace wq
 
 struct wq_mesh {
@@ -99,6 +104,8 @@ struct wq_points {
   int32_t max_tile_nnz = 0, max_tile_ent = 0, max_tile_mem = 0;
   int32_t max_tile_nd = 0 /*max np*m of an entry*/, max_tile_nw = 0 /*max members*np*/;
   int32_t asm_chunk = 64;  // consecutive tiles per XCD turn in the assembly launch (tunable)
+  int32_t t2_stepcap = wq::T2_STEPCAP;  // summed row steps per cell-major tile (tunable)
+  int64_t t2_gen = 0;  // counts (re)builds of the cell-major tiles and schedule changes
   wq::DBuf tile_eptr /*int64 [tiles+1]*/, tile_ent /*int4 [entries]: dptr, pt0, mask|np<<16|m<<24, mbase*/,
       tile_mem /*int2 [pairs]: qoff | rowloc<<28, soff*/;
   // cell-major assembly tiles: runs of up to T2_ROWS consecutive rows with at most T2_NZCAP CSR
@@ -175,10 +182,6 @@ struct KTimer {
   void stop();
 };
 
-constexpr int TILE_ROWS = 8;
-constexpr int T2_ROWS = 16;    // rows per cell-major assembly tile (MFMA 16 x 16 x 4 columns)
-constexpr int T2_NZCAP = 416;  // CSR entries per cell-major tile (8 rows of 52; 16 short rows)
-constexpr int T2_STEPCAP = 128;  // summed row steps (support cells' blocks of 4 points) per tile
 
 // 64-bit index launch helper
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -236,5 +239,9 @@ __device__ inline void surf_basis(const SurfGeom& G, const double v[6], double* 
 // Asynchronous on st.
 wq_status gauss_basis(wq_mesh* M, wq_points* P, double* GN, double* GX, double* GY, double* GZ, double* GL,
                       double* gw, double* gx, hipStream_t st);
+
+// Rebuilds the cell-major assembly tiles of P with its current t2_stepcap (and counts the
+// rebuild in t2_gen). Synchronises st.
+wq_status rebuild_tiles2(wq_points* P, hipStream_t st);
 
 }  // namespace wq

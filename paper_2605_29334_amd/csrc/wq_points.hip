@@ -957,7 +957,7 @@ __global__ void k_row_steps(int64_t n, const int64_t* sptr, const int32_t* scell
 }
 
 // Cell-major tiles: runs of consecutive rows, at most T2_ROWS rows, T2_NZCAP CSR entries
-// (the tile's accumulators live in LDS) and T2_STEPCAP summed row steps each, cut greedily in
+// (the tile's accumulators live in LDS) and P->t2_stepcap summed row steps each, cut greedily in
 // row order on the host. The step cap keeps the tiles next to extraordinary points (rows of
 // many cells with many points) from taking several times the average tile's time: one wave
 // runs a tile, so the heaviest tile sets the launch's end. (A row's sums do not depend on
@@ -984,7 +984,7 @@ wq_status build_tiles2(wq_points* P, DBuf& flags, hipStream_t st) {
   for (int64_t i = 0; i < n;) {
     const int64_t s = i;
     int64_t nz = 0, w = 0;
-    while (i < n && i - s < T2_ROWS && nz + (rp[i + 1] - rp[i]) <= T2_NZCAP && (i == s || w + rw[i] <= T2_STEPCAP))
+    while (i < n && i - s < T2_ROWS && nz + (rp[i + 1] - rp[i]) <= T2_NZCAP && (i == s || w + rw[i] <= P->t2_stepcap))
       nz += rp[i + 1] - rp[i], w += rw[i], ++i;
     WQ_CHECK(i > s, WQ_EINVAL, "build_points: a row exceeds the cell-major tile capacity");
     row0.push_back((int32_t)s);
@@ -1028,6 +1028,7 @@ wq_status build_tiles2(wq_points* P, DBuf& flags, hipStream_t st) {
   dfree(bptr);
   WQ_CHECK(!hf[0], WQ_EINVAL, "build_points: mesh too large for 32-bit cell-major tile offsets; split it");
   WQ_HIP(hipGetLastError());
+  ++P->t2_gen;
   return WQ_OK;
 }
 
@@ -1139,6 +1140,14 @@ wq_status build_points_impl(wq_mesh* M, int want_lap, const uint8_t* s_host, hip
 }
 
 }  // namespace
+
+wq_status wq::rebuild_tiles2(wq_points* P, hipStream_t st) {
+  DBuf flags;
+  WQ_TRY(dalloc_n<int>(flags, 8));
+  const wq_status s = build_tiles2(P, flags, st);
+  dfree(flags);
+  return s;
+}
 
 void wq_release_points(wq_points* P) { release_points(P); }
 

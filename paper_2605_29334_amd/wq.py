@@ -119,6 +119,7 @@ def _lib():
             "wq_batch_graph_assemble": ([P, P, P, P, P, C.c_int, P], C.c_int),
             "wq_batch_destroy": ([P], None),
             "wq_autotune_assembly": ([P, P, P, P, P], C.c_int),
+            "wq_autotune_tiles": ([P, P, P, P, P, P], C.c_int),
             "gauss_setup": ([P, P, C.c_int, P, P], C.c_int),
             "wq_gauss_destroy": ([P], None),
             "wq_gauss_size": ([P], I64),
@@ -145,7 +146,7 @@ def exported_symbols():
             "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
             "assemble_tangent", "assemble_tangent_noalloc", "assemble_tangent_exact", "wq_heat_step", "wq_server_start", "wq_server_submit", "wq_server_poll",
             "wq_server_stop", "wq_batch_create", "wq_batch_build", "wq_batch_info", "wq_batch_points",
-            "wq_batch_weights", "wq_batch_graph_assemble", "wq_batch_destroy", "wq_autotune_assembly",
+            "wq_batch_weights", "wq_batch_graph_assemble", "wq_batch_destroy", "wq_autotune_assembly", "wq_autotune_tiles",
             "gauss_setup", "wq_gauss_destroy", "wq_gauss_size", "wq_gauss_get_x", "assemble_gauss",
             "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
 
@@ -557,6 +558,15 @@ def autotune_assembly(points, weights, stream=None):
     _check(_lib().wq_autotune_assembly(points.h, weights.h, _stream(stream), C.byref(ch), C.byref(ms)),
            "wq_autotune_assembly")
     return ch.value, ms.value
+
+
+def autotune_tiles(points, weights, stream=None):
+    """Pick the assembly's tile work cap and XCD chunk length on `points` by measurement;
+    returns (step cap, chunk, ms)."""
+    cap, ch, ms = C.c_int32(), C.c_int32(), C.c_double()
+    _check(_lib().wq_autotune_tiles(points.h, weights.h, _stream(stream), C.byref(cap), C.byref(ch), C.byref(ms)),
+           "wq_autotune_tiles")
+    return cap.value, ch.value, ms.value
 
 
 def timing_enable(on=True):

@@ -113,6 +113,39 @@ def test_autotune_changes_schedule_not_values(batch):
     assert torch.equal(M0, M1) and torch.equal(K0, K1)
 
 
+def test_autotune_tiles_changes_schedule_not_values(batch):
+    """The tile-shape autotuner rebuilds the cell-major tiles: values are unchanged, eager
+    and through the batch's captured graph (captured again after the rebuild)."""
+    W, pool, B = batch
+    P, Wt = B.points, B.weights
+    x = P.get(W.ARR_X).reshape(-1, 2)
+    c, k = _coef(x, 0.3)
+    M0, K0 = W.assemble_mass_stiffness(P, Wt, c, k)
+    s = torch.cuda.Stream()
+    Mg, Kg = torch.empty_like(M0), torch.empty_like(K0)
+    torch.cuda.synchronize()
+    B.graph_assemble(c, k, Mg, Kg, stream=s)
+    s.synchronize()
+    assert torch.equal(Mg, M0) and torch.equal(Kg, K0)
+    tiles0 = P.info()["tiles"]
+    cap, chunk, ms = W.autotune_tiles(P, Wt)
+    tiles1 = P.info()["tiles"]
+    print(f"[gpu] autotune tiles: step cap {cap}, chunk {chunk}, {ms:.4f} ms; tiles {tiles0} -> {tiles1}")
+    band = -(-tiles1 // 8)
+    assert cap in (64, 96, 128, 192, 256, 1 << 30) and ms > 0
+    assert chunk in (4, 8, 16, 32, 64, 128, 256, 512, 1024) and chunk < band or chunk == band
+    M1, K1 = W.assemble_mass_stiffness(P, Wt, c, k)
+    torch.cuda.synchronize()
+    assert torch.equal(M0, M1) and torch.equal(K0, K1)
+    Mg.zero_()
+    Kg.zero_()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        B.graph_assemble(c, k, Mg, Kg, stream=s)
+        s.synchronize()
+        assert torch.equal(Mg, M0) and torch.equal(Kg, K0), rep
+
+
 def test_batch_meshes_against_oracle(batch):
     W, pool, B = batch
     P, Wt = B.points, B.weights
