@@ -627,6 +627,7 @@ __global__ void k_tile2_entries(int64_t n_tiles, const int32_t* row0, const int6
                                 const int64_t* cfn_ptr, const int64_t* cell_pt_off, const int64_t* dptr,
                                 const int64_t* soff, const uint8_t* slot, int64_t* eptr, int64_t* bptr, int4* ent,
                                 uint8_t* tslot, int* overflow) {
+  __shared__ int64_t msoff[BS / 64][T2_ROWS];  // per wave: slot-map offsets of an entry's members
   const int lane = threadIdx.x & 63;
   const int64_t tile = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
   if (tile >= n_tiles) return;
@@ -653,16 +654,18 @@ __global__ void k_tile2_entries(int64_t n_tiles, const int32_t* row0, const int6
     const int m = (int)(cfn_ptr[best + 1] - cfn_ptr[best]);
     const int mpad = (m + 15) & ~15;
     if (FILL) {
-      if (member) {
-        const int64_t so = soff[pos];
-        uint8_t* dst = tslot + sb + (int64_t)rank * mpad;
-        for (int t = 0; t < mpad; ++t) {
-          const int k = (t & ~15) + ((t >> 2) & 3) + 4 * (t & 3);
-          // a position past the cell's functions gets some slot of the row: the kernel
-          // adds zero products there (no per-function predicate)
-          dst[t] = slot[so + (k < m ? k : k % m)];
-        }
+      // the members' slot maps, nm * mpad bytes behind sb, copied by all lanes (the
+      // members' map offsets handed over through LDS)
+      if (member) msoff[threadIdx.x >> 6][rank] = soff[pos];
+      __builtin_amdgcn_wave_barrier();
+      for (int t = lane; t < nm * mpad; t += 64) {
+        const int u = t / mpad, tt = t - u * mpad;
+        const int k = (tt & ~15) + ((tt >> 2) & 3) + 4 * (tt & 3);
+        // a position past the cell's functions gets some slot of the row: the kernel adds
+        // zero products there (no per-function predicate)
+        tslot[sb + t] = slot[msoff[threadIdx.x >> 6][u] + (k < m ? k : k % m)];
       }
+      __builtin_amdgcn_wave_barrier();
       if (lane == 0) {
         const int64_t d0 = dptr[best];
         const int64_t sbe = sb + (int64_t)nm * mpad;
