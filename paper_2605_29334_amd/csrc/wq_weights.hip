@@ -1248,7 +1248,8 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
 //  2. the rank proof (||R11^-1||_F from R11^-T, one column per lane);
 //  3. Householder QR of X = Z A_k^T (the k pivot rows of A, re-read from the basis blocks);
 //  4. y = R^-T b_k, u = Q [y; 0] (the reflectors applied in reverse), w = Z u, and one
-//     step of iterative refinement on the residual of the k kept equations.
+//     step of iterative refinement on the residual of the k kept equations where that
+//     residual is above rounding level.
 // Rows above the current step are zero in the broadcast column, so the passes skip the
 // blocks of 16 rows that lie wholly above it (a uniform branch; the sums are unchanged,
 // the skipped terms being exact zeros).
@@ -1552,6 +1553,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
     if (lane < kq) rho = bv[fq] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
   }
   __syncthreads();
+  // The step only moves w when the residual is above rounding level: where every kept
+  // equation already holds to 1e-14 of the largest |b_k| (most systems), w stands.
+  double bmax;
+  int bl;
+  wave_argmax64(lane < kq ? fabs(bv[pk[lane]]) : 0.0, 0, bmax, bl);
+  if (!__any(fabs(rho) > 1e-14 * bmax)) {
+    if (lane < r) a.W[fs][a.qptr[i] + lane] = w;
+    return;
+  }
   const double dw = solve(rho);
   if (lane < r) a.W[fs][a.qptr[i] + lane] = fma(zv[lane], dw, w);
 }
