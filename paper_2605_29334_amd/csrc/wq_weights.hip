@@ -1148,11 +1148,11 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   double* tq = sig;   // free: the singular values only formed X and c
   double* rvq = Rk;   // free: b is in c (yv) by now
   double* nq = nrm;   // free after the Jacobi sweeps
-  for (int l = g; l < t; l += NG) {
+  if (g == 0 && t > 0) {  // the first column's norm (each step forms the next one's)
     double s2 = 0.0;
-    for (int m = sub; m < r; m += LPP) s2 += G[(size_t)l * ld + m] * G[(size_t)l * ld + m];
+    for (int m = sub; m < r; m += LPP) s2 += G[m] * G[m];
     s2 = group_sum<LPP>(s2);
-    if (sub == 0) nq[l] = s2;
+    if (sub == 0) nq[0] = s2;
   }
   __syncthreads();
   for (int j = 0; j < t; ++j) {
@@ -1176,6 +1176,8 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
         sv += v[e] * x[e];
       }
       sv = tj * group_sum<LPP>(sv);
+      // (no pivoting: only the next column's trailing norm is needed)
+      const bool next = l == j + 1;
       double ns = 0.0;
 #pragma unroll
       for (int e = 0; e < EPR; ++e) {
@@ -1183,11 +1185,13 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
         if (m < r) {
           const double y = x[e] - sv * v[e];
           if (tj != 0.0) cl[m] = y;
-          if (m > j) ns += y * y;
+          if (next && m > j) ns += y * y;
         }
       }
-      ns = group_sum<LPP>(ns);
-      if (sub == 0) nq[l] = ns;
+      if (next) {  // (one whole group)
+        ns = group_sum<LPP>(ns);
+        if (sub == 0) nq[l] = ns;
+      }
     }
     __syncthreads();
   }
