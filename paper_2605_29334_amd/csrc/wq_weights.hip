@@ -361,6 +361,7 @@ struct TsvdArgs {
   int32_t* fb_list;    // one-wave solver: systems left to the SVD kernel (family-major index)
   int rp_n;            // one-wave solver: the largest n its dynamic LDS holds R11 for
   int* fb_count;
+  unsigned direct_mask;  // SVD kernel: family slots whose systems first try the direct proof
 };
 
 __device__ inline double block_sum(double v, double* red) {
@@ -755,388 +756,405 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
   }
   const double fa2 = block_sum(fro2, red);
   const double negl = 1e-30 * fa2;
-  // ---- 2. Householder QR of A^T with column pivoting (largest trailing norm first).
-  // Columns are addressed through a permutation (no data swaps); reflector j is kept
-  // unscaled in its column (v_j = 1, v_m = x_m / (x_j - R_jj) below), R_jj in beta[j].
-  // One barrier per column: every thread picks the pivot from the per-wave candidates of
-  // the previous update and forms the reflector itself; the permutation and the
-  // candidates are double-buffered (read one buffer, write the other).
-  constexpr int NW = NT / 64;
-  {
-    double best = -1.0;
-    int bl = 0x7fffffff;
-    for (int l = g; l < n; l += NG) {
-      double s2 = 0.0;
-      for (int m = sub; m < r; m += LPP) s2 += G[(size_t)l * ld + m] * G[(size_t)l * ld + m];
-      s2 = group_sum<LPP>(s2);
-      if (s2 > best) {
-        best = s2;
-        bl = l;
-      }
-    }
-    wave_argmax<LPP>(best, bl, red + 32, red + 48);
-  }
-  __syncthreads();
-  const int kmax = min(n, r);
-  // With early set, the factorisation stops before step j once the trailing block is
-  // negligible: ||R22||_F^2 <= (n - j) * (largest trailing column norm^2) below
-  // (tau / 10)^2 R_00^2 (R_00^2 = s20, the largest column norm^2 of A^T), a hundred times
-  // the rounding level of the factorisation for tau = 1e-12. Returns the
-  // step it stopped before (kmax when it ran to the end); s2stop is that step's pivot norm^2.
-  double s20 = 0.0, s2stop = 0.0;
-  auto qr_steps = [&](int j0, bool early) -> int {
-    for (int j = j0; j < kmax; ++j) {
-      const double* cv = red + 32 + 32 * (j & 1);
-      const int* cur = (j & 1) ? cmap : piv;
-      int* nxt = (j & 1) ? piv : cmap;
-      double s2;
-      int bi;
-      if constexpr (NW >= 8) {  // one candidate per lane of each group of NW lanes
-        s2 = cv[tid & (NW - 1)];
-        bi = (int)cv[16 + (tid & (NW - 1))];
-        group_argmax<NW>(s2, bi);
-      } else {
-        s2 = cv[0];
-        bi = (int)cv[16];
-        for (int w = 1; w < NW; ++w) {
-          const double v = cv[w];
-          const int i2 = (int)cv[16 + w];
-          if (v > s2 || (v == s2 && i2 < bi)) {
-            s2 = v;
-            bi = i2;
-          }
-        }
-      }
-      if (j == 0) s20 = s2;
-      if (early && (double)(n - j) * s2 < 1e-2 * a.tau * a.tau * s20) {
-        s2stop = s2;
-        return j;
-      }
-      const int cj = cur[j], pc = cur[bi];
-      double rjj, rv0, tj;
-      householder(G[(size_t)pc * ld + j], s2, &rjj, &rv0, &tj);
-      if (tid == 0) beta[j] = rjj;
-      for (int l = tid; l < n; l += NT) nxt[l] = l == j ? pc : (l == bi ? cj : cur[l]);
-      int bl;
-      const double best = qr_update<LPP, EPR, NG>(G, ld, r, n, j, pc, cur, bi, cj, tj, rv0, g, sub, &bl);
-      double* nv = red + 32 + 32 * ((j + 1) & 1);
-      wave_argmax<LPP>(best, bl, nv, nv + 16);
-      __syncthreads();
-    }
-    return kmax;
-  };
-  const int kq = qr_steps(0, true);
-  // ---- certified rank. The truncated-SVD solution only depends on the kept count t, the
-  // span of the kept right singular vectors and the kept part of b. sigma_{k+1} <= ||R22||
-  // and sigma_k >= sigma_min(R11) - ||R22|| >= 1 / ||R11^-1||_F - ||R22|| (R11: the
-  // leading k x k block, R22: the trailing block, k = kq), and tau sigma_1 lies between
-  // tau R_00 and tau ||A||_F. So when ||R22|| is below tau R_00 / 10 and the kept bound
-  // is above 100 tau ||A||_F, the cutoff keeps exactly k singular values, and their span is
-  // that of the k pivot rows of A up to O(eps / gap): the solution is then the weighted
-  // minimum-norm solution of those k equations, w = Z Q R^-T b_k for Z A_k^T = Q R (step 4
-  // below), the same as the SVD's to rounding times the conditioning. Otherwise the
-  // factorisation runs to the end and the Jacobi SVD decides.
-  // Column c of S = R11^-T (lower triangular), eight lanes per column: S[ii][c] = (delta -
-  // sum_{jj = c}^{ii - 1} R[jj][ii] S[jj][c]) / R[ii][ii], with R[.][ii] read down the
-  // physical column of logical column ii (rows < ii) and S[.][c] kept in rows c+1 .. kq of
-  // the physical column of logical column c (its reflector rows, no longer needed: no
-  // thread reads R there). Lane s of a column's group takes jj = c + s (mod 8), the group
-  // sums by DPP, and its first lane stores S[ii][c] (read by the group's lanes, in the same
-  // wave, at the next steps: one LDS latency per step instead of one per four terms).
-  const int* pk = (kq & 1) ? cmap : piv;  // logical column l of R is constraint pk[l]
-  const double r22 = kq < kmax ? sqrt((double)(n - kq) * s2stop) : 0.0;
-  double lo = 0.0;
-  bool fast = false;
-  if (s20 > 0.0 && kq > 0) {
-    double tn = 0.0;
-    const int cs = tid & 7;
-    for (int c = tid >> 3; c < kq; c += NT / 8) {  // (whole groups of eight lanes)
-      double* Sc = G + (size_t)pk[c] * ld + 1;  // S[jj][c] at Sc[jj]
-      for (int ii = c; ii < kq; ++ii) {
-        const double* Rc = G + (size_t)pk[ii] * ld;  // R[jj][ii] at Rc[jj], jj < ii
-        double s0 = 0.0, s1 = 0.0;
-        int jj = c + cs;
-        for (; jj + 8 < ii; jj += 16) {
-          s0 = fma(Rc[jj], Sc[jj], s0);
-          s1 = fma(Rc[jj + 8], Sc[jj + 8], s1);
-        }
-        if (jj < ii) s0 = fma(Rc[jj], Sc[jj], s0);
-        const double sum = group_sum<8>(s0 + s1);
-        const double v = ((ii == c ? 1.0 : 0.0) - sum) / beta[ii];
-        if (cs == 0) {
-          Sc[ii] = v;
-          tn = fma(v, v, tn);
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    tn = block_sum(tn, red);  // the same bits in every thread: the branch is uniform
-    lo = 1.0 / sqrt(tn) - r22;
-    fast = lo > 100.0 * a.tau * sqrt(fa2);
-  }
+  // Direct path (the families whose systems are full rank but for rare exceptions, the mass
+  // family): the rank is proved from the R of X = Z A^T itself, sigma_n(A) >= sigma_n(Z A^T)
+  // / max z = 1 / (||R^-1||_2 max z), so the pivoted QR, which only serves the proof, is
+  // skipped. X is A^T scaled in place, c = b, all n constraints kept; the proof follows the
+  // second factorisation (step 4). A system it does not cover is listed and solved by the
+  // full path in a second launch.
+  const bool direct = ((a.direct_mask >> fs) & 1u) && a.sel == nullptr && n <= r;
   int t;  // the kept count
-  if (fast) {
-    // X = Z A_k^T: the k pivot rows of A, re-read from the basis blocks, as the columns
-    for (int l = tid; l < n; l += NT) pinv[pk[l]] = l;
-    for (int c = tid; c < kq; c += NT) yv[c] = Rk[pk[c]];
-    if (tid == 0) {
-      atomicMin(a.min_kept, dbits(lo / sqrt(fa2)));       // a lower bound of sigma_k / sigma_1
-      atomicMax(a.max_dropped, dbits(r22 / sqrt(s20)));  // an upper bound of sigma_{k+1} / sigma_1
-      if (kq < n) atomicAdd(a.truncated, 1ULL);
-      atomicAdd(a.certified, 1ULL);
+  if (direct) {
+    for (int e = tid; e < n * r; e += NT) {
+      const int l = e / r, m = e - l * r;
+      G[(size_t)l * ld + m] *= z[m];
     }
+    for (int l = tid; l < n; l += NT) yv[l] = Rk[l];
     __syncthreads();
-    for (int e = tid; e < kq * ld; e += NT) G[e] = 0.0;
-    __syncthreads();
-    int moff = 0;
-    for (int64_t p = a.sptr[i]; p < a.sptr[i + 1]; ++p) {
-      const int32_t c = a.scell[p];
-      const int m = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
-      const int np = (int)(a.cell_pt_off[c + 1] - a.cell_pt_off[c]);
-      const double* Dc = AD + a.dptr[c];
-      const uint8_t* sl = a.slot + a.soff[p];
-      for (int e = tid; e < np * m; e += NT) {
-        const int q = e / m, k = e - q * m;
-        const int col = pinv[sl[k]];
-        if (col < kq) G[(size_t)col * ld + moff + q] = z[moff + q] * Dc[e];
-      }
-      moff += np;
-    }
-    __syncthreads();
-    t = kq;
+    t = n;
   } else {
-    if (kq < kmax) qr_steps(kq, false);
-    // the final permutation: logical column l of R is constraint perm[l]
-    const int* perm = (kmax & 1) ? cmap : piv;
-    // ---- M = R1^T: column k of M is row k of R1, M[k][i] = R1[k][i] = G[i][k] for i >= k.
-    // M sits at the end of the G area (X is later written from the start; see step 3).
-    double* M = G + (size_t)n * ld - (size_t)n * ldm;
+    // ---- 2. Householder QR of A^T with column pivoting (largest trailing norm first).
+    // Columns are addressed through a permutation (no data swaps); reflector j is kept
+    // unscaled in its column (v_j = 1, v_m = x_m / (x_j - R_jj) below), R_jj in beta[j].
+    // One barrier per column: every thread picks the pivot from the per-wave candidates of
+    // the previous update and forms the reflector itself; the permutation and the
+    // candidates are double-buffered (read one buffer, write the other).
+    constexpr int NW = NT / 64;
     {
-      constexpr int MS = (EPJ * LPP * EPJ * LPP + NT - 1) / NT;  // n^2 <= (EPJ LPP)^2
-      double val[MS];
-  #pragma unroll
-      for (int s2 = 0; s2 < MS; ++s2) {
-        const int e = tid + NT * s2;
-        const int k = e / n, ii = e - k * n;
-        val[s2] = (e < n * n && ii >= k && k < kmax) ? (ii == k ? beta[k] : G[(size_t)perm[ii] * ld + k]) : 0.0;
+      double best = -1.0;
+      int bl = 0x7fffffff;
+      for (int l = g; l < n; l += NG) {
+        double s2 = 0.0;
+        for (int m = sub; m < r; m += LPP) s2 += G[(size_t)l * ld + m] * G[(size_t)l * ld + m];
+        s2 = group_sum<LPP>(s2);
+        if (s2 > best) {
+          best = s2;
+          bl = l;
+        }
+      }
+      wave_argmax<LPP>(best, bl, red + 32, red + 48);
+    }
+    __syncthreads();
+    const int kmax = min(n, r);
+    // With early set, the factorisation stops before step j once the trailing block is
+    // negligible: ||R22||_F^2 <= (n - j) * (largest trailing column norm^2) below
+    // (tau / 10)^2 R_00^2 (R_00^2 = s20, the largest column norm^2 of A^T), a hundred times
+    // the rounding level of the factorisation for tau = 1e-12. Returns the
+    // step it stopped before (kmax when it ran to the end); s2stop is that step's pivot norm^2.
+    double s20 = 0.0, s2stop = 0.0;
+    auto qr_steps = [&](int j0, bool early) -> int {
+      for (int j = j0; j < kmax; ++j) {
+        const double* cv = red + 32 + 32 * (j & 1);
+        const int* cur = (j & 1) ? cmap : piv;
+        int* nxt = (j & 1) ? piv : cmap;
+        double s2;
+        int bi;
+        if constexpr (NW >= 8) {  // one candidate per lane of each group of NW lanes
+          s2 = cv[tid & (NW - 1)];
+          bi = (int)cv[16 + (tid & (NW - 1))];
+          group_argmax<NW>(s2, bi);
+        } else {
+          s2 = cv[0];
+          bi = (int)cv[16];
+          for (int w = 1; w < NW; ++w) {
+            const double v = cv[w];
+            const int i2 = (int)cv[16 + w];
+            if (v > s2 || (v == s2 && i2 < bi)) {
+              s2 = v;
+              bi = i2;
+            }
+          }
+        }
+        if (j == 0) s20 = s2;
+        if (early && (double)(n - j) * s2 < 1e-2 * a.tau * a.tau * s20) {
+          s2stop = s2;
+          return j;
+        }
+        const int cj = cur[j], pc = cur[bi];
+        double rjj, rv0, tj;
+        householder(G[(size_t)pc * ld + j], s2, &rjj, &rv0, &tj);
+        if (tid == 0) beta[j] = rjj;
+        for (int l = tid; l < n; l += NT) nxt[l] = l == j ? pc : (l == bi ? cj : cur[l]);
+        int bl;
+        const double best = qr_update<LPP, EPR, NG>(G, ld, r, n, j, pc, cur, bi, cj, tj, rv0, g, sub, &bl);
+        double* nv = red + 32 + 32 * ((j + 1) & 1);
+        wave_argmax<LPP>(best, bl, nv, nv + 16);
+        __syncthreads();
+      }
+      return kmax;
+    };
+    const int kq = qr_steps(0, true);
+    // ---- certified rank. The truncated-SVD solution only depends on the kept count t, the
+    // span of the kept right singular vectors and the kept part of b. sigma_{k+1} <= ||R22||
+    // and sigma_k >= sigma_min(R11) - ||R22|| >= 1 / ||R11^-1||_F - ||R22|| (R11: the
+    // leading k x k block, R22: the trailing block, k = kq), and tau sigma_1 lies between
+    // tau R_00 and tau ||A||_F. So when ||R22|| is below tau R_00 / 10 and the kept bound
+    // is above 100 tau ||A||_F, the cutoff keeps exactly k singular values, and their span is
+    // that of the k pivot rows of A up to O(eps / gap): the solution is then the weighted
+    // minimum-norm solution of those k equations, w = Z Q R^-T b_k for Z A_k^T = Q R (step 4
+    // below), the same as the SVD's to rounding times the conditioning. Otherwise the
+    // factorisation runs to the end and the Jacobi SVD decides.
+    // Column c of S = R11^-T (lower triangular), eight lanes per column: S[ii][c] = (delta -
+    // sum_{jj = c}^{ii - 1} R[jj][ii] S[jj][c]) / R[ii][ii], with R[.][ii] read down the
+    // physical column of logical column ii (rows < ii) and S[.][c] kept in rows c+1 .. kq of
+    // the physical column of logical column c (its reflector rows, no longer needed: no
+    // thread reads R there). Lane s of a column's group takes jj = c + s (mod 8), the group
+    // sums by DPP, and its first lane stores S[ii][c] (read by the group's lanes, in the same
+    // wave, at the next steps: one LDS latency per step instead of one per four terms).
+    const int* pk = (kq & 1) ? cmap : piv;  // logical column l of R is constraint pk[l]
+    const double r22 = kq < kmax ? sqrt((double)(n - kq) * s2stop) : 0.0;
+    double lo = 0.0;
+    bool fast = false;
+    if (s20 > 0.0 && kq > 0) {
+      double tn = 0.0;
+      const int cs = tid & 7;
+      for (int c = tid >> 3; c < kq; c += NT / 8) {  // (whole groups of eight lanes)
+        double* Sc = G + (size_t)pk[c] * ld + 1;  // S[jj][c] at Sc[jj]
+        for (int ii = c; ii < kq; ++ii) {
+          const double* Rc = G + (size_t)pk[ii] * ld;  // R[jj][ii] at Rc[jj], jj < ii
+          double s0 = 0.0, s1 = 0.0;
+          int jj = c + cs;
+          for (; jj + 8 < ii; jj += 16) {
+            s0 = fma(Rc[jj], Sc[jj], s0);
+            s1 = fma(Rc[jj + 8], Sc[jj + 8], s1);
+          }
+          if (jj < ii) s0 = fma(Rc[jj], Sc[jj], s0);
+          const double sum = group_sum<8>(s0 + s1);
+          const double v = ((ii == c ? 1.0 : 0.0) - sum) / beta[ii];
+          if (cs == 0) {
+            Sc[ii] = v;
+            tn = fma(v, v, tn);
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      tn = block_sum(tn, red);  // the same bits in every thread: the branch is uniform
+      lo = 1.0 / sqrt(tn) - r22;
+      fast = lo > 100.0 * a.tau * sqrt(fa2);
+    }
+    if (fast) {
+      // X = Z A_k^T: the k pivot rows of A, re-read from the basis blocks, as the columns
+      for (int l = tid; l < n; l += NT) pinv[pk[l]] = l;
+      for (int c = tid; c < kq; c += NT) yv[c] = Rk[pk[c]];
+      if (tid == 0) {
+        atomicMin(a.min_kept, dbits(lo / sqrt(fa2)));       // a lower bound of sigma_k / sigma_1
+        atomicMax(a.max_dropped, dbits(r22 / sqrt(s20)));  // an upper bound of sigma_{k+1} / sigma_1
+        if (kq < n) atomicAdd(a.truncated, 1ULL);
+        atomicAdd(a.certified, 1ULL);
       }
       __syncthreads();
-  #pragma unroll
-      for (int s2 = 0; s2 < MS; ++s2) {
-        const int e = tid + NT * s2;
-        const int k = e / n, ii = e - k * n;
-        if (e < n * n) M[(size_t)k * ldm + ii] = val[s2];
+      for (int e = tid; e < kq * ld; e += NT) G[e] = 0.0;
+      __syncthreads();
+      int moff = 0;
+      for (int64_t p = a.sptr[i]; p < a.sptr[i + 1]; ++p) {
+        const int32_t c = a.scell[p];
+        const int m = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
+        const int np = (int)(a.cell_pt_off[c + 1] - a.cell_pt_off[c]);
+        const double* Dc = AD + a.dptr[c];
+        const uint8_t* sl = a.slot + a.soff[p];
+        for (int e = tid; e < np * m; e += NT) {
+          const int q = e / m, k = e - q * m;
+          const int col = pinv[sl[k]];
+          if (col < kq) G[(size_t)col * ld + moff + q] = z[moff + q] * Dc[e];
+        }
+        moff += np;
       }
-      for (int e = tid; e < n * (ldm - n); e += NT) M[(size_t)(e / (ldm - n)) * ldm + n + e % (ldm - n)] = 0.0;
-      for (int l = tid; l < n; l += NT) pinv[perm[l]] = l;
-    }
-    __syncthreads();
-    // ---- one-sided Jacobi on the columns of M. Rows [n, ldm) of every column are zero, and
-    // ne LPP <= ldm. Two pair orderings (each visits every pair once per sweep):
-    //  - recursive halving: each group holds the S column of its pairs in registers for a
-    //    whole level, so a rotation reads and writes only its T column in LDS (half the LDS
-    //    traffic) and sweeps are fewer; it costs registers and a few more rounds and barriers;
-    //  - the circle method: both columns of a pair through LDS in every round.
-    // Instances take the ordering that measured faster for their buckets: halving for
-    // 48 < n <= 56 (r <= 128), for 48 < n <= 64 with 80 < r <= 128 and for n <= 64 with
-    // r > 128; circle for the rest, where the held column cost occupancy or the extra rounds
-    // cost more than the LDS traffic saved.
-    constexpr bool HALVING = (NT == 256 && (EPJ == 7 || EPR == 32)) || (NT == 512 && LPP == 16);
-    const int ne = (n + LPP - 1) / LPP;
-    const bool full = ldm >= EPJ * LPP;  // all EPJ rows of a lane inside the column: no checks
-    int sweeps = 0;
-    bool converged = false;
-    double* cn = nrm;  // squared column norms of M (nrm is free after the QR)
-    if constexpr (HALVING) {
-      int nlev = 0;
-      while (((n + (1 << nlev) - 1) >> nlev) >= 2) ++nlev;
-      for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
-        bool big = false;  // a pair of this sweep met at |cos| above 3e-8
-        // fresh norms at each sweep bound the drift of the tracked updates
-        for (int l = g; l < n; l += NG) {
-          double s2 = 0.0;
-          for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
-          s2 = group_sum<LPP>(s2);
-          if (sub == 0) cn[l] = s2;
-        }
-        __syncthreads();
-        double u[EPJ];
-        double al = 0.0;
-        int held = -1;  // the column in u, or -1
-        for (int L = 0; L < nlev; ++L) {
-          const HalvingSlot sl = halving_slot(n, L, g);
-          const bool act = sl.j < sl.h;
-          const int want = act ? sl.s : -1;
-          if (L > 0) {
-            // a column no longer held goes back to LDS before anyone reads it
-            if (held >= 0 && held != want) {
-              double* gp = M + (size_t)held * ldm + sub;
-  #pragma unroll
-              for (int e = 0; e < EPJ; ++e)
-                if (full || e < ne) gp[e * LPP] = u[e];
-              if (sub == 0) cn[held] = al;
-              held = -1;
-            }
-            __syncthreads();
-          }
-          if (act && held != want) {
-            const double* gp = M + (size_t)want * ldm + sub;
-  #pragma unroll
-            for (int e = 0; e < EPJ; ++e) u[e] = (full || e < ne) ? gp[e * LPP] : 0.0;
-            al = cn[want];
-            held = want;
-          }
-          const int rounds = halving_groups((n + (1 << L) - 1) >> L);
-          for (int rd = 0; rd < rounds; ++rd) {
-            if (act && rd < sl.h) {
-              int k = sl.j + rd;
-              if (k >= sl.h) k -= sl.h;
-              if (k < sl.tcnt) {
-                const int cQ = sl.tlo + k;
-                double* gq = M + (size_t)cQ * ldm + sub;
-                big |= full ? jacobi_held<LPP, EPJ, false>(u, al, gq, cn + cQ, sub, ne, negl)
-                            : jacobi_held<LPP, EPJ, true>(u, al, gq, cn + cQ, sub, ne, negl);
-              }
-            }
-            __syncthreads();
-          }
-        }
-        if (held >= 0) {
-          double* gp = M + (size_t)held * ldm + sub;
-  #pragma unroll
-          for (int e = 0; e < EPJ; ++e)
-            if (full || e < ne) gp[e * LPP] = u[e];
-          if (sub == 0) cn[held] = al;
-        }
-        __syncthreads();
-        // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
-        // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
-        // pair is rotated at all, so the sweep that would only confirm it is skipped.
-        converged = !__syncthreads_or(big);
-      }
+      __syncthreads();
+      t = kq;
     } else {
-      const int nn = n + (n & 1);
-      const int npair = nn / 2;
-      for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
-        bool big = false;  // a pair of this sweep met at |cos| above 3e-8
-        // fresh norms at each sweep bound the drift of the tracked updates
-        for (int l = g; l < n; l += NG) {
-          double s2 = 0.0;
-          for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
-          s2 = group_sum<LPP>(s2);
-          if (sub == 0) cn[l] = s2;
+      if (kq < kmax) qr_steps(kq, false);
+      // the final permutation: logical column l of R is constraint perm[l]
+      const int* perm = (kmax & 1) ? cmap : piv;
+      // ---- M = R1^T: column k of M is row k of R1, M[k][i] = R1[k][i] = G[i][k] for i >= k.
+      // M sits at the end of the G area (X is later written from the start; see step 3).
+      double* M = G + (size_t)n * ld - (size_t)n * ldm;
+      {
+        constexpr int MS = (EPJ * LPP * EPJ * LPP + NT - 1) / NT;  // n^2 <= (EPJ LPP)^2
+        double val[MS];
+    #pragma unroll
+        for (int s2 = 0; s2 < MS; ++s2) {
+          const int e = tid + NT * s2;
+          const int k = e / n, ii = e - k * n;
+          val[s2] = (e < n * n && ii >= k && k < kmax) ? (ii == k ? beta[k] : G[(size_t)perm[ii] * ld + k]) : 0.0;
         }
         __syncthreads();
-        // Circle method on positions 0..nn-1: pair p starts at positions (p, nn - 1 - p);
-        // position 0 stays, positions 1..nn-1 advance by one per round (cyclically), so every
-        // two positions meet once per sweep. Position 0 holds column nn - 1 (the padding
-        // column when n is odd), position c > 0 column c - 1; pair 0 (which holds the padding
-        // column in every round for odd n) runs on the last group, so for odd n the last pair
-        // group does no work and a wave whose groups are all past the real pairs skips the
-        // round entirely.
-        const int pp = (g + 1 == npair) ? 0 : g + 1;
-        int P = pp, Q = nn - 1 - pp;
-        for (int rd = 0; rd < nn - 1; ++rd) {
-          const int cP = P == 0 ? nn - 1 : P - 1, cQ = Q - 1;
-          if (g < npair && cP < n && cQ < n) {
-            double* gp = M + (size_t)cP * ldm + sub;
-            double* gq = M + (size_t)cQ * ldm + sub;
-            big |= full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + cP, cn + cQ, sub, ne, negl)
-                        : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + cP, cn + cQ, sub, ne, negl);
+    #pragma unroll
+        for (int s2 = 0; s2 < MS; ++s2) {
+          const int e = tid + NT * s2;
+          const int k = e / n, ii = e - k * n;
+          if (e < n * n) M[(size_t)k * ldm + ii] = val[s2];
+        }
+        for (int e = tid; e < n * (ldm - n); e += NT) M[(size_t)(e / (ldm - n)) * ldm + n + e % (ldm - n)] = 0.0;
+        for (int l = tid; l < n; l += NT) pinv[perm[l]] = l;
+      }
+      __syncthreads();
+      // ---- one-sided Jacobi on the columns of M. Rows [n, ldm) of every column are zero, and
+      // ne LPP <= ldm. Two pair orderings (each visits every pair once per sweep):
+      //  - recursive halving: each group holds the S column of its pairs in registers for a
+      //    whole level, so a rotation reads and writes only its T column in LDS (half the LDS
+      //    traffic) and sweeps are fewer; it costs registers and a few more rounds and barriers;
+      //  - the circle method: both columns of a pair through LDS in every round.
+      // Instances take the ordering that measured faster for their buckets: halving for
+      // 48 < n <= 56 (r <= 128), for 48 < n <= 64 with 80 < r <= 128 and for n <= 64 with
+      // r > 128; circle for the rest, where the held column cost occupancy or the extra rounds
+      // cost more than the LDS traffic saved.
+      constexpr bool HALVING = (NT == 256 && (EPJ == 7 || EPR == 32)) || (NT == 512 && LPP == 16);
+      const int ne = (n + LPP - 1) / LPP;
+      const bool full = ldm >= EPJ * LPP;  // all EPJ rows of a lane inside the column: no checks
+      int sweeps = 0;
+      bool converged = false;
+      double* cn = nrm;  // squared column norms of M (nrm is free after the QR)
+      if constexpr (HALVING) {
+        int nlev = 0;
+        while (((n + (1 << nlev) - 1) >> nlev) >= 2) ++nlev;
+        for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
+          bool big = false;  // a pair of this sweep met at |cos| above 3e-8
+          // fresh norms at each sweep bound the drift of the tracked updates
+          for (int l = g; l < n; l += NG) {
+            double s2 = 0.0;
+            for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+            s2 = group_sum<LPP>(s2);
+            if (sub == 0) cn[l] = s2;
           }
-          P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
-          Q = (Q == nn - 1) ? 1 : Q + 1;
+          __syncthreads();
+          double u[EPJ];
+          double al = 0.0;
+          int held = -1;  // the column in u, or -1
+          for (int L = 0; L < nlev; ++L) {
+            const HalvingSlot sl = halving_slot(n, L, g);
+            const bool act = sl.j < sl.h;
+            const int want = act ? sl.s : -1;
+            if (L > 0) {
+              // a column no longer held goes back to LDS before anyone reads it
+              if (held >= 0 && held != want) {
+                double* gp = M + (size_t)held * ldm + sub;
+    #pragma unroll
+                for (int e = 0; e < EPJ; ++e)
+                  if (full || e < ne) gp[e * LPP] = u[e];
+                if (sub == 0) cn[held] = al;
+                held = -1;
+              }
+              __syncthreads();
+            }
+            if (act && held != want) {
+              const double* gp = M + (size_t)want * ldm + sub;
+    #pragma unroll
+              for (int e = 0; e < EPJ; ++e) u[e] = (full || e < ne) ? gp[e * LPP] : 0.0;
+              al = cn[want];
+              held = want;
+            }
+            const int rounds = halving_groups((n + (1 << L) - 1) >> L);
+            for (int rd = 0; rd < rounds; ++rd) {
+              if (act && rd < sl.h) {
+                int k = sl.j + rd;
+                if (k >= sl.h) k -= sl.h;
+                if (k < sl.tcnt) {
+                  const int cQ = sl.tlo + k;
+                  double* gq = M + (size_t)cQ * ldm + sub;
+                  big |= full ? jacobi_held<LPP, EPJ, false>(u, al, gq, cn + cQ, sub, ne, negl)
+                              : jacobi_held<LPP, EPJ, true>(u, al, gq, cn + cQ, sub, ne, negl);
+                }
+              }
+              __syncthreads();
+            }
+          }
+          if (held >= 0) {
+            double* gp = M + (size_t)held * ldm + sub;
+    #pragma unroll
+            for (int e = 0; e < EPJ; ++e)
+              if (full || e < ne) gp[e * LPP] = u[e];
+            if (sub == 0) cn[held] = al;
+          }
+          __syncthreads();
+          // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
+          // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
+          // pair is rotated at all, so the sweep that would only confirm it is skipped.
+          converged = !__syncthreads_or(big);
+        }
+      } else {
+        const int nn = n + (n & 1);
+        const int npair = nn / 2;
+        for (sweeps = 0; sweeps < MAX_SWEEPS && !converged; ++sweeps) {
+          bool big = false;  // a pair of this sweep met at |cos| above 3e-8
+          // fresh norms at each sweep bound the drift of the tracked updates
+          for (int l = g; l < n; l += NG) {
+            double s2 = 0.0;
+            for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+            s2 = group_sum<LPP>(s2);
+            if (sub == 0) cn[l] = s2;
+          }
+          __syncthreads();
+          // Circle method on positions 0..nn-1: pair p starts at positions (p, nn - 1 - p);
+          // position 0 stays, positions 1..nn-1 advance by one per round (cyclically), so every
+          // two positions meet once per sweep. Position 0 holds column nn - 1 (the padding
+          // column when n is odd), position c > 0 column c - 1; pair 0 (which holds the padding
+          // column in every round for odd n) runs on the last group, so for odd n the last pair
+          // group does no work and a wave whose groups are all past the real pairs skips the
+          // round entirely.
+          const int pp = (g + 1 == npair) ? 0 : g + 1;
+          int P = pp, Q = nn - 1 - pp;
+          for (int rd = 0; rd < nn - 1; ++rd) {
+            const int cP = P == 0 ? nn - 1 : P - 1, cQ = Q - 1;
+            if (g < npair && cP < n && cQ < n) {
+              double* gp = M + (size_t)cP * ldm + sub;
+              double* gq = M + (size_t)cQ * ldm + sub;
+              big |= full ? jacobi_pair<LPP, EPJ, false>(gp, gq, cn + cP, cn + cQ, sub, ne, negl)
+                          : jacobi_pair<LPP, EPJ, true>(gp, gq, cn + cP, cn + cQ, sub, ne, negl);
+            }
+            P = (P == 0) ? 0 : (P == nn - 1 ? 1 : P + 1);
+            Q = (Q == nn - 1) ? 1 : Q + 1;
+            __syncthreads();
+          }
+          // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
+          // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
+          // pair is rotated at all, so the sweep that would only confirm it is skipped.
+          converged = !__syncthreads_or(big);
+        }
+      }
+      if (!converged && tid == 0) atomicOr(a.fail, 1);
+      if (tid == 0) atomicMax(a.max_sweeps, sweeps);
+      // ---- 3. singular values, truncation, c
+      double smax = 0.0;
+      for (int l = g; l < n; l += NG) {
+        double s2 = 0.0;
+        for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
+        s2 = group_sum<LPP>(s2);
+        if (sub == 0) sig[l] = sqrt(s2);
+        smax = fmax(smax, sqrt(s2));
+      }
+      smax = block_max(smax, red);
+      if (tid == 0) {
+        int t = 0;
+        double kmin = INFINITY, dmax = 0.0;
+        for (int l = 0; l < n; ++l) {
+          if (sig[l] > a.tau * smax) {
+            keep[t++] = l;
+            kmin = fmin(kmin, sig[l] / smax);
+          } else {
+            dmax = fmax(dmax, sig[l] / smax);
+          }
+        }
+        keep[n] = t;
+        atomicMin(a.min_kept, dbits(kmin));
+        atomicMax(a.max_dropped, dbits(dmax));
+        if (t < n) atomicAdd(a.truncated, 1ULL);
+      }
+      __syncthreads();
+      t = keep[n];
+      // c_k = u_k^T b / sigma_k = (w_k . P^T b) / sigma_k^2
+      for (int k = g; k < t; k += NG) {
+        const double* wk = M + (size_t)keep[k] * ldm;
+        double s2 = 0.0;
+        for (int m = sub; m < n; m += LPP) s2 += wk[m] * Rk[perm[m]];
+        s2 = group_sum<LPP>(s2);
+        if (sub == 0) yv[k] = s2 / (sig[keep[k]] * sig[keep[k]]);
+      }
+      // X[m][k] = z_m sum_l A[l][m] U[l][k] / sigma_k with U[l][k] = M[pinv[l]][keep[k]] /
+      // sigma_k. The threads form NP parts of RW (r rounded up to whole waves) rows each; part
+      // g2 forms columns k0 + g2 KC + (0 .. KC-1) of a chunk of NP KC columns. Columns are
+      // written from the start of G, M's columns sit at the end: the writes of a chunk never
+      // reach a column of M still to be read (n ld >= k ld + n ldm - (n - k) ldm for k <= n,
+      // as ldm <= ld), and a chunk's own columns are read before the barrier.
+      constexpr int KC = 8;
+      {
+        const int RW = (r + 63) / 64 * 64;
+        const int NP = NT / RW;  // >= 1: r <= NT
+        const int g2 = tid / RW, m = tid - g2 * RW;
+        const bool row = g2 < NP && m < r;
+        const double* Dc = nullptr;
+        const uint8_t* sl = nullptr;
+        int mc = 0;
+        if (row) {
+          const int64_t p = a.sptr[i] + ptc[m];
+          const int32_t c = a.scell[p];
+          mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
+          Dc = AD + a.dptr[c] + (int64_t)ptq[m] * mc;
+          sl = a.slot + a.soff[p];
+        }
+        for (int k0 = 0; k0 < t; k0 += NP * KC) {
+          const int kb = k0 + g2 * KC;
+          double acc[KC];
+    #pragma unroll
+          for (int kq = 0; kq < KC; ++kq) acc[kq] = 0.0;
+          if (row)
+            for (int kk = 0; kk < mc; ++kk) {
+              const double av = Dc[kk];
+              const int ii = pinv[sl[kk]];
+    #pragma unroll
+              for (int kq = 0; kq < KC; ++kq)
+                if (kb + kq < t) acc[kq] += av * M[(size_t)keep[kb + kq] * ldm + ii];
+            }
+          __syncthreads();
+          if (row) {
+    #pragma unroll
+            for (int kq = 0; kq < KC; ++kq)
+              if (kb + kq < t) {
+                const double sk = sig[keep[kb + kq]];
+                G[(size_t)(kb + kq) * ld + m] = z[m] * acc[kq] / (sk * sk);
+              }
+          }
           __syncthreads();
         }
-        // Cyclic Jacobi converges quadratically: after a sweep whose rotations all had |cos|
-        // below 3e-8, the columns are orthogonal to about |cos| ~ 1e-15, the level at which a
-        // pair is rotated at all, so the sweep that would only confirm it is skipped.
-        converged = !__syncthreads_or(big);
-      }
-    }
-    if (!converged && tid == 0) atomicOr(a.fail, 1);
-    if (tid == 0) atomicMax(a.max_sweeps, sweeps);
-    // ---- 3. singular values, truncation, c
-    double smax = 0.0;
-    for (int l = g; l < n; l += NG) {
-      double s2 = 0.0;
-      for (int m = sub; m < n; m += LPP) s2 += M[(size_t)l * ldm + m] * M[(size_t)l * ldm + m];
-      s2 = group_sum<LPP>(s2);
-      if (sub == 0) sig[l] = sqrt(s2);
-      smax = fmax(smax, sqrt(s2));
-    }
-    smax = block_max(smax, red);
-    if (tid == 0) {
-      int t = 0;
-      double kmin = INFINITY, dmax = 0.0;
-      for (int l = 0; l < n; ++l) {
-        if (sig[l] > a.tau * smax) {
-          keep[t++] = l;
-          kmin = fmin(kmin, sig[l] / smax);
-        } else {
-          dmax = fmax(dmax, sig[l] / smax);
-        }
-      }
-      keep[n] = t;
-      atomicMin(a.min_kept, dbits(kmin));
-      atomicMax(a.max_dropped, dbits(dmax));
-      if (t < n) atomicAdd(a.truncated, 1ULL);
-    }
-    __syncthreads();
-    t = keep[n];
-    // c_k = u_k^T b / sigma_k = (w_k . P^T b) / sigma_k^2
-    for (int k = g; k < t; k += NG) {
-      const double* wk = M + (size_t)keep[k] * ldm;
-      double s2 = 0.0;
-      for (int m = sub; m < n; m += LPP) s2 += wk[m] * Rk[perm[m]];
-      s2 = group_sum<LPP>(s2);
-      if (sub == 0) yv[k] = s2 / (sig[keep[k]] * sig[keep[k]]);
-    }
-    // X[m][k] = z_m sum_l A[l][m] U[l][k] / sigma_k with U[l][k] = M[pinv[l]][keep[k]] /
-    // sigma_k. The threads form NP parts of RW (r rounded up to whole waves) rows each; part
-    // g2 forms columns k0 + g2 KC + (0 .. KC-1) of a chunk of NP KC columns. Columns are
-    // written from the start of G, M's columns sit at the end: the writes of a chunk never
-    // reach a column of M still to be read (n ld >= k ld + n ldm - (n - k) ldm for k <= n,
-    // as ldm <= ld), and a chunk's own columns are read before the barrier.
-    constexpr int KC = 8;
-    {
-      const int RW = (r + 63) / 64 * 64;
-      const int NP = NT / RW;  // >= 1: r <= NT
-      const int g2 = tid / RW, m = tid - g2 * RW;
-      const bool row = g2 < NP && m < r;
-      const double* Dc = nullptr;
-      const uint8_t* sl = nullptr;
-      int mc = 0;
-      if (row) {
-        const int64_t p = a.sptr[i] + ptc[m];
-        const int32_t c = a.scell[p];
-        mc = (int)(a.cfn_ptr[c + 1] - a.cfn_ptr[c]);
-        Dc = AD + a.dptr[c] + (int64_t)ptq[m] * mc;
-        sl = a.slot + a.soff[p];
-      }
-      for (int k0 = 0; k0 < t; k0 += NP * KC) {
-        const int kb = k0 + g2 * KC;
-        double acc[KC];
-  #pragma unroll
-        for (int kq = 0; kq < KC; ++kq) acc[kq] = 0.0;
-        if (row)
-          for (int kk = 0; kk < mc; ++kk) {
-            const double av = Dc[kk];
-            const int ii = pinv[sl[kk]];
-  #pragma unroll
-            for (int kq = 0; kq < KC; ++kq)
-              if (kb + kq < t) acc[kq] += av * M[(size_t)keep[kb + kq] * ldm + ii];
-          }
-        __syncthreads();
-        if (row) {
-  #pragma unroll
-          for (int kq = 0; kq < KC; ++kq)
-            if (kb + kq < t) {
-              const double sk = sig[keep[kb + kq]];
-              G[(size_t)(kb + kq) * ld + m] = z[m] * acc[kq] / (sk * sk);
-            }
-        }
-        __syncthreads();
       }
     }
   }
@@ -1194,6 +1212,45 @@ __global__ void __launch_bounds__(NT) k_tsvd2(TsvdArgs a) {
       }
     }
     __syncthreads();
+  }
+  if (direct) {
+    // column c of S = R^-T, eight lanes per column, lane s holding rows c + s + 8q in
+    // registers (the reflectors below the diagonal of X stay for the solve): S[c+d][c] =
+    // (delta_{d0} - sum_{d' < d} R[c+d'][c+d] S[c+d'][c]) / R[c+d][c+d]
+    constexpr int SR = (EPJ * LPP + 7) / 8;
+    const int cs = tid & 7;
+    double tn = 0.0;
+    for (int c = tid >> 3; c < t; c += NT / 8) {  // (whole groups of eight lanes)
+      double sv[SR];
+#pragma unroll
+      for (int q = 0; q < SR; ++q) sv[q] = 0.0;
+#pragma unroll
+      for (int d = 0; d < 8 * SR; ++d) {
+        if (c + d < t) {
+          const double* Rc = G + (size_t)(c + d) * ld + c;  // R[c+d'][c+d] at Rc[d']
+          double sacc = 0.0;
+#pragma unroll
+          for (int q = 0; q < SR; ++q)
+            if (cs + 8 * q < d) sacc = fma(Rc[cs + 8 * q], sv[q], sacc);
+          const double v = ((d == 0 ? 1.0 : 0.0) - group_sum<8>(sacc)) / beta[c + d];
+          if ((d & 7) == cs) sv[d >> 3] = v;
+          if (cs == 0) tn = fma(v, v, tn);
+        }
+      }
+    }
+    tn = block_sum(tn, red);
+    double zm = 0.0;
+    for (int m = tid; m < r; m += NT) zm = fmax(zm, z[m]);
+    zm = block_max(zm, red);
+    const double lo = 1.0 / (sqrt(tn) * zm);
+    if (!(tn > 0.0 && lo > 100.0 * a.tau * sqrt(fa2))) {  // (uniform)
+      if (tid == 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)wg;
+      return;
+    }
+    if (tid == 0) {
+      atomicMin(a.min_kept, dbits(lo / sqrt(fa2)));  // a lower bound of sigma_n / sigma_1
+      atomicAdd(a.certified, 1ULL);
+    }
   }
   if (tid >= 64) return;
   {
@@ -1691,6 +1748,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   // one launch per size bucket covers every family asked for (more workgroups per launch,
   // fewer partly idle tails)
   int nfam = 0;
+  unsigned direct_mask = 0;  // family slots whose systems try the SVD kernel's direct proof
   const double* famD[NFAM] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   const double* famR[NFAM] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   double* famW[NFAM] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -1701,6 +1759,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
                  : f == 3 ? P->DL.as<double>() : P->DZ.as<double>();
     famR[nfam] = w->rhs[f].as<double>();
     famW[nfam] = w->W[f].as<double>();
+    if (f == 0) direct_mask |= 1u << nfam;  // the mass family: full rank but for exceptions
     ++nfam;
   }
   // common kernel arguments
@@ -1723,6 +1782,11 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     base.W[q] = famW[q];
   }
   base.DN = P->DN.as<double>();
+  base.direct_mask = direct_mask;
+  // systems the SVD kernel's direct proof or the one-wave solver's proof does not cover,
+  // per bucket (solved in a second launch)
+  int32_t* fb_lists = nullptr;
+  int* fb_counts = nullptr;
   if (s == WQ_OK) {
     Rep* R = drep.as<Rep>();
     base.max_sweeps = &R->max_sweeps;
@@ -1790,6 +1854,10 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     ta.ld = ld;
     ta.ldm = ldm;
     ta.sel = sel;
+    if (!sel && direct_mask) {
+      ta.fb_list = fb_lists + start[b] * nfam;
+      ta.fb_count = fb_counts + b;
+    }
     // 8 lanes per column pair; systems with more than 64 constraints (more than 32
     // pairs) take 1024 threads with 16 lanes per column pair (more waves per CU to hide
     // latency: such systems fill most of a CU's LDS on their own).
@@ -1843,6 +1911,8 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   if (s == WQ_OK) s = dalloc_n<int32_t>(fbl, (size_t)n * nfam);
   if (s == WQ_OK) s = dalloc_n<int>(fbc, NBKT);
   if (s == WQ_OK && hipMemsetAsync(fbc.p, 0, NBKT * sizeof(int), st) != hipSuccess) s = WQ_EDEVICE;
+  fb_lists = fbl.as<int32_t>();
+  fb_counts = fbc.as<int>();
   for (int b = 0; b < NBKT && s == WQ_OK; ++b) {
     const int64_t ns = hist[b];
     if (ns == 0) continue;
@@ -1868,6 +1938,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       any_w = true;
     } else {
       s = svd_launch(b, nullptr, ns * nfam, (int64_t)bflops[b] * nfam);
+      any_w = any_w || direct_mask != 0;
     }
   }
   if (s == WQ_OK && any_w) {
@@ -1875,8 +1946,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
         hipStreamSynchronize(st) != hipSuccess)
       s = WQ_EDEVICE;
     for (int b = 0; b < NBKT && s == WQ_OK; ++b)
-      if (hist[b] && b / NB_R <= 3 && b % NB_R == 0 && fbn[b] > 0)
-        s = svd_launch(b, fbl.as<int32_t>() + start[b] * nfam, fbn[b], 0);
+      if (hist[b] && fbn[b] > 0) s = svd_launch(b, fbl.as<int32_t>() + start[b] * nfam, fbn[b], 0);
   }
   dfree(fbl);
   dfree(fbc);
