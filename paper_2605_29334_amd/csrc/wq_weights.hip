@@ -362,6 +362,7 @@ struct TsvdArgs {
   int rp_n;            // one-wave solver: the largest n its dynamic LDS holds R11 for
   int* fb_count;
   unsigned direct_mask;  // SVD kernel: family slots whose systems first try the direct proof
+  int fam_base;          // one-wave solver: family slot of the launch's first workgroups
 };
 
 __device__ inline double block_sum(double v, double* red) {
@@ -1319,6 +1320,13 @@ constexpr int WR = 64;     // points (rows) held per lane
 constexpr int WB = 16;     // rows per skipped block
 constexpr int WMAXC = 40;  // support cells of a row in the gather tables
 
+// DIRECT (the mass family, full rank but for rare exceptions): no pivoted QR. X = Z A^T over
+// all n constraints is factorised and solved and the weights written; the rank is then proved
+// from that QR's R, sigma_n(A) >= sigma_n(Z A^T) / max z >= 1 / (||R^-1||_F max z), once the
+// reflectors' registers are free. A system the proof does not cover is listed for k_tsvd2,
+// whose full path overwrites its weights. (A separate instance, so that the pivoted path's
+// register allocation stays as it is.)
+template <bool DIRECT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_wsolve(TsvdArgs a) {
   __shared__ double vb[WR + 4];  // the current reflector's column (4 zero pads past the rows)
   __shared__ double zv[WR], bv[WR], beta[WR], ib[WR], tau2[WR], rv2[WR], uv2[WR];
@@ -1329,18 +1337,19 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
   __shared__ uint8_t ptp[WR + 4], ptq[WR + 4];  // support cell and local index of every point
   __shared__ int pk[WR];                        // position -> constraint of the pivoted QR
   const int lane = threadIdx.x;
-  const int fs = (int)(blockIdx.x / a.nsys);
-  const int64_t sys = blockIdx.x - (int64_t)fs * a.nsys;
+  const int fl = (int)(blockIdx.x / a.nsys);
+  const int64_t sys = blockIdx.x - (int64_t)fl * a.nsys;
+  const int fs = a.fam_base + fl;  // family slot
   const double* AD = a.D[fs];
   const int64_t i = a.rows[sys];
   const int n = (int)(a.row_ptr[i + 1] - a.row_ptr[i]);
   const int r = (int)(a.qptr[i + 1] - a.qptr[i]);
   const int64_t s0 = a.sptr[i];
   const int nc = (int)(a.sptr[i + 1] - s0);
-  auto to_svd = [&]() {
-    if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)blockIdx.x;
+  auto to_svd = [&]() {  // (the family-major index over all the bucket's families)
+    if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1)] = (int32_t)((int64_t)a.fam_base * a.nsys + blockIdx.x);
   };
-  if (n > WR || n > a.rp_n || r > WR || nc < 1 || nc >= WMAXC) {
+  if (n > WR || n > a.rp_n || r > WR || nc < 1 || nc >= WMAXC || (DIRECT && n > r)) {
     to_svd();
     return;
   }
@@ -1466,7 +1475,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
   int pos = lane < n ? -1 : WR;  // position once pivoted (lanes past n never are)
   double s20 = 0.0, s2stop = 0.0;
   int kq = kmax;
-  for (int j = 0; j < kmax; ++j) {
+  for (int j = 0; j < (DIRECT ? 0 : kmax); ++j) {  // (DIRECT: no pivoted QR)
     double s2;
     int p;
     wave_argmax64(pos < 0 ? nrm : -1.0, lane, s2, p);
@@ -1489,17 +1498,18 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
   // ---- 2. rank proof: sigma_{k+1} <= ||R22||_F <= sqrt((n - k) s2stop) and sigma_k >=
   // 1 / ||R11^-1||_F - ||R22||_F (as in k_tsvd2)
   const double r22 = kq < kmax ? sqrt((double)(n - kq) * s2stop) : 0.0;
-  if (pos >= 1 && pos < kq) {
+  if (!DIRECT && pos >= 1 && pos < kq) {
     const int base = pos * (pos - 1) / 2;
 #pragma unroll
     for (int m = 0; m < WR - 1; ++m)
       if (m < pos) rp[base + m] = x[m];
   }
-  if (lane < kq) ib[lane] = 1.0 / beta[lane];
+  if (!DIRECT && lane < kq) ib[lane] = 1.0 / beta[lane];
+  if (DIRECT && lane < n) pk[lane] = lane;  // (kq = n: all constraints, in order)
   __syncthreads();
   double lo = 0.0;
-  bool fast = false;
-  if (s20 > 0.0 && kq > 0) {
+  bool fast = DIRECT;
+  if (!DIRECT && s20 > 0.0 && kq > 0) {
     // column `lane` of S = R11^-T (lower triangular): S[ii][c] = (delta - sum_{jj < ii}
     // R[jj][ii] S[jj][c]) / R[ii][ii]; the entries above the diagonal come out zero
     double t[WR];
@@ -1526,7 +1536,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
     return;
   }
   // ---- 3. Householder QR of X = Z A_k^T (lane c: position c)
-  gather(lane < kq ? pk[lane] : 0, lane < kq, true, x);
+  if constexpr (DIRECT) {  // the columns of A^T in order, already held: scaled by z
+#pragma unroll
+    for (int m = 0; m < WR; ++m) x[m] *= zv[m];
+  } else {
+    gather(lane < kq ? pk[lane] : 0, lane < kq, true, x);
+  }
   nrm = 0.0;
 #pragma unroll
   for (int m = 0; m < WR; ++m) nrm = fma(x[m], x[m], nrm);
@@ -1548,7 +1563,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
     to_svd();
     return;
   }
-  if (lane == 0) {
+  if (!DIRECT && lane == 0) {
     atomicMin(a.min_kept, dbits(lo / sqrt(fa2)));       // a lower bound of sigma_k / sigma_1
     atomicMax(a.max_dropped, dbits(r22 / sqrt(s20)));  // an upper bound of sigma_{k+1} / sigma_1
     if (kq < n) atomicAdd(a.truncated, 1ULL);
@@ -1619,12 +1634,55 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
   double bmax;
   int bl;
   wave_argmax64(lane < kq ? fabs(bv[pk[lane]]) : 0.0, 0, bmax, bl);
-  if (!__any(fabs(rho) > 1e-14 * bmax)) {
+  const bool settled = !__any(fabs(rho) > 1e-14 * bmax);
+  if (settled) {
     if (lane < r) a.W[fs][a.qptr[i] + lane] = w;
-    return;
+    if constexpr (!DIRECT) return;
   }
-  const double dw = solve(rho);
-  if (lane < r) a.W[fs][a.qptr[i] + lane] = fma(zv[lane], dw, w);
+  if (!DIRECT || !settled) {
+    const double dw = solve(rho);
+    if (lane < r) a.W[fs][a.qptr[i] + lane] = fma(zv[lane], dw, w);
+  }
+  if constexpr (DIRECT) {
+    // the rank proof from the R of X (column c above the diagonal in lane c's points below
+    // c): all n kept where 1 / (||R^-1||_F max z) > 100 tau ||A||_F
+    if (lane >= 1 && lane < n) {
+      const int base = lane * (lane - 1) / 2;
+#pragma unroll
+      for (int m = 0; m < WR - 1; ++m)
+        if (m < lane) rp[base + m] = x[m];
+    }
+    if (lane < n) ib[lane] = 1.0 / beta[lane];
+    __syncthreads();
+    double zm;
+    wave_argmax64(lane < r ? zv[lane] : 0.0, 0, zm, bl);
+    double t[WR];
+    double tn = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < WR; ++ii) {
+      if (ii < n) {  // a uniform branch, not an exit: the loop unrolls fully
+        double sa[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int jj = 0; jj < ii; ++jj) {
+          sa[jj & 3] = fma(rp[ii * (ii - 1) / 2 + jj], t[jj], sa[jj & 3]);
+          if ((jj & 15) == 15) asm volatile("" ::: "memory");  // at most 16 loads in flight
+        }
+        const double v = ((lane == ii ? 1.0 : 0.0) - ((sa[0] + sa[1]) + (sa[2] + sa[3]))) * ib[ii];
+        t[ii] = v;
+        tn = fma(v, v, tn);
+      }
+    }
+    tn = wave_sum64(tn);
+    lo = 1.0 / (sqrt(tn) * zm);
+    if (!(tn > 0.0 && lo > 100.0 * a.tau * sqrt(fa2))) {
+      to_svd();
+      return;
+    }
+    if (lane == 0) {
+      atomicMin(a.min_kept, dbits(lo / sqrt(fa2)));  // a lower bound of sigma_n / sigma_1
+      atomicAdd(a.certified, 1ULL);
+    }
+  }
 }
 
 
@@ -1928,9 +1986,20 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       const int mn = hist[2 * (NBKT + 1) + 2 * b];
       ta.rp_n = mn;
       const size_t lds = (size_t)mn * (mn - 1) / 2 * sizeof(double);
-      KTimer tm("k_wsolve", (int64_t)bflops[b] * nfam, st);
-      k_wsolve<<<dim3((unsigned)(ns * nfam)), dim3(64), lds, st>>>(ta);
-      tm.stop();
+      // the mass family's slot (slot 0) through the direct instance, the others pivoted
+      const int nd = (direct_mask & 1u) ? 1 : 0;
+      if (nd) {
+        ta.fam_base = 0;
+        KTimer tm("k_wsolve_direct", (int64_t)bflops[b], st);
+        k_wsolve<true><<<dim3((unsigned)ns), dim3(64), lds, st>>>(ta);
+        tm.stop();
+      }
+      if (nfam > nd) {
+        ta.fam_base = nd;
+        KTimer tm("k_wsolve", (int64_t)bflops[b] * (nfam - nd), st);
+        k_wsolve<false><<<dim3((unsigned)(ns * (nfam - nd))), dim3(64), lds, st>>>(ta);
+        tm.stop();
+      }
       if (hipGetLastError() != hipSuccess) {
         set_error("solve_weights: one-wave solver launch failed");
         s = WQ_EDEVICE;
