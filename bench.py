@@ -160,15 +160,20 @@ def served_pool(n_meshes=6, seed=5):
     return [fx.fixture_eps(N, 0.01, (3, 5, 6), displace=0.05, seed=5000 + j) for j, N in enumerate(sizes)], sizes
 
 
-def measure_served(W, pool, n_requests, rate, slots, seed=5, n_steps=1, tangent=0, reuse=False, workload=""):
+def measure_served(W, pool, n_requests, rate, slots, seed=5, n_steps=1, tangent=0, reuse=False, join=1,
+                   join_rows=1 << 15, workload=""):
     """Nonlinear heat requests (k = 1 + u^2, manufactured source, n_steps of dt 0.1 from
     T = 0) on meshes drawn from the pool, arriving as a Poisson stream of `rate` per
     second, served with continuous admission on `slots` concurrent streams; latency =
-    completion - arrival. reuse = False: every request sets its domain up from scratch."""
+    completion - arrival. reuse = False: every request sets its domain up from scratch.
+    join > 1: requests queued together run as one union of up to `join` meshes and
+    `join_rows` rows."""
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
     picks = rng.integers(0, len(pool), n_requests)
     S = W.Server(64 << 30, slots)
+    if join > 1:
+        S.set_join(join, join_rows)
     t0 = time.perf_counter()
     tickets = []
     for a, j in zip(arrivals, picks):
@@ -192,7 +197,8 @@ def measure_served(W, pool, n_requests, rate, slots, seed=5, n_steps=1, tangent=
             "newton_iters_mean": float(np.mean([r["newton_iters"] for r in res]) / max(n_steps, 1)),
             "krylov_iters_mean": float(np.mean([r["cg_iters"] for r in res]) / max(n_steps, 1)),
             "rows_mean": float(np.mean([r["n_rows"] for r in res])),
-            "setups_reused": int(sum(r["setup_reused"] for r in res)), "failed": failed, "workload": workload}
+            "setups_reused": int(sum(r["setup_reused"] for r in res)),
+            "joined_mean": float(np.mean([r["joined"] for r in res])), "failed": failed, "workload": workload}
 
 
 def make_fixture(N, density, seed):
@@ -637,6 +643,17 @@ def main():
         out["served_below_capacity"] = measure_served(
             W, spool, n_requests=40, rate=0.7 * cap, slots=4, seed=6, tangent=W.TANGENT_EXACT, reuse=False,
             workload="as 'served', arrivals at 0.7 x its measured throughput")
+        out["served_joined"] = measure_served(
+            W, spool, n_requests=60, rate=200.0, slots=4, tangent=W.TANGENT_EXACT, reuse=False, join=16,
+            workload="as 'served', with joining: requests queued together run as one union of up to 16 meshes "
+                     "and 32768 rows (shared launches for the setup and every Newton and Krylov step)")
+        small = ("pool of 9 meshes (16..64 faces per side, grids and 2% EPs), k = 1 + u^2, manufactured source, "
+                 "1 step of dt 0.1, exact tangent; every request sets its domain up from scratch")
+        out["served_small"] = measure_served(W, pool, n_requests=64, rate=400.0, slots=4, tangent=W.TANGENT_EXACT,
+                                             reuse=False, workload=small)
+        out["served_small_joined"] = measure_served(
+            W, pool, n_requests=64, rate=400.0, slots=4, tangent=W.TANGENT_EXACT, reuse=False, join=16,
+            workload=small + "; joining: requests queued together run as one union of up to 16 meshes and 32768 rows")
         out["served_reuse"] = measure_served(
             W, pool, n_requests=40, rate=200.0, slots=4, n_steps=2, tangent=W.TANGENT_EXACT, reuse=True,
             workload="pool of 9 meshes (16..64 faces per side, grids and 2% EPs), 2 steps of dt 0.1, exact tangent; "

@@ -362,11 +362,30 @@ typedef struct {
   size_t hbm_estimate;        /* bytes charged against the budget while running, and
                                  while the server holds the request's setup afterwards   */
   int32_t setup_reused;       /* 1 if a held setup of the same domain was taken over     */
+  int32_t joined;             /* meshes in the union the request ran in (1: alone)       */
 } wq_result;
 wq_status wq_server_start(size_t hbm_budget_bytes, int32_t slots, wq_server** out);
 wq_status wq_server_submit(wq_server* server, const wq_request* req, double* T_out, int64_t* ticket);
 int wq_server_poll(wq_server* server, int64_t ticket, int wait, wq_result* out);
 void wq_server_stop(wq_server* server);
+
+/* wq_server_set_join: joining of requests that are queued together (off by default,
+ * max_meshes = 1). When a slot admits the oldest request and it has no held setup to take
+ * over, later queued requests with the same heat parameters, step count and source (and
+ * lambda) that have no idle held setup of their own domain and fit in the budget next to
+ * it, up to max_meshes requests and max_rows rows (functions) in all, run with it as one: their meshes are joined into
+ * one disjoint union (as wq_batch_create), the points and weights are built once over it,
+ * and each time step is one wq_heat_step over the union, so that setup and every Newton
+ * and Krylov step of all of them share launches. The union's tangent is block diagonal and
+ * its Newton stop, ||R_free||_2 <= tol over the union, holds for every mesh's own
+ * residual; the Krylov solves run over the union, so a joined result agrees with the
+ * request run alone to the solver tolerances, not bit for bit. The union's iteration
+ * counts and residual are reported for each joined request (wq_result.joined > 1), and no
+ * setup of a joined request is held afterwards. Joining pays where launches and host
+ * round trips, not the device's throughput, bound a request (small meshes); max_rows keeps
+ * larger ones apart (a request above it runs alone). Applies to admissions after the call;
+ * max_meshes in 1..4096 and max_rows >= 0, else WQ_EINVAL. */
+wq_status wq_server_set_join(wq_server* server, int32_t max_meshes, int64_t max_rows);
 
 /* ------------------------------------------------------------------ batching
  * Many independent meshes through one set of launches: wq_batch_create joins them into

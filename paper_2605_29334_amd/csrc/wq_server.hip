@@ -5,7 +5,9 @@
 // overlap on the device. All state of a request stays on the device until its final
 // temperature is copied out. The setup of a domain (mesh, points, weights: computed once
 // per fixed domain) stays on the device after its request; a later request on an
-// identical domain takes it over instead of recomputing it.
+// identical domain takes it over instead of recomputing it. With joining on, requests
+// queued together with the same parameters run as one union of their meshes: one set of
+// launches for the setup and for every Newton and Krylov step of all of them.
 #include "wq_internal.h"
 
 #include <algorithm>
@@ -108,6 +110,8 @@ struct wq_server {
   int64_t clock = 0;              // admission counter (least recently used setup first)
   bool stopping = false;
   int64_t next_id = 1;
+  int32_t join = 1;         // most requests run as one union (1: each request alone)
+  int64_t join_rows = 0;    // most rows of a union (functions of its meshes)
   std::deque<Request*> queue;
   std::map<int64_t, Request*> all;
   std::mutex mu;
@@ -123,6 +127,94 @@ namespace {
 // pattern + tile records, bounded generously, plus the Newton/PCG vectors.
 size_t hbm_estimate(const wq_mesh_desc& d) {
   return (size_t)16384 * (size_t)d.nf + (size_t)256 * (size_t)d.n_fn + ((size_t)8 << 20);
+}
+
+// The request's time steps from T = Tdot = 0 (already cleared) on a points/weights pair:
+// the manufactured source at t_{n+1}, then one heat step; iteration counts add up in res.
+wq_status time_steps(const Request& r, wq_points* pts, wq_weights* w, int64_t np, const DBuf& dir, const DBuf& T,
+                     const DBuf& Td, const DBuf& S, const DBuf& f, hipStream_t st, wq_result& res) {
+  wq_status s = WQ_OK;
+  for (int step = 0; s == WQ_OK && step < r.n_steps; ++step) {
+    const double t1 = r.heat.dt * (step + 1);
+    if (r.source) {
+      k_manufactured_source<<<nblocks(np, 256), 256, 0, st>>>(np, pts->x.as<double>(), t1, r.lambda, r.heat.k,
+                                                               f.as<double>());
+      if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
+    }
+    wq_heat_report rep{};
+    if (s == WQ_OK)
+      s = wq_heat_step(pts, w, &r.heat, dir.as<uint8_t>(), nullptr, r.source ? f.as<double>() : nullptr,
+                       T.as<double>(), Td.as<double>(), S.as<double>(), &rep, (wq_stream)st);
+    res.newton_iters += rep.newton_iters;
+    res.cg_iters += rep.cg_iters;
+    res.residual = rep.residual;
+  }
+  return s;
+}
+
+// Requests that may share launches: the same heat parameters, step count and source.
+bool joinable(const Request& a, const Request& b) {
+  const wq_heat_params &p = a.heat, &q = b.heat;
+  return p.dt == q.dt && p.theta == q.theta && p.k.kind == q.k.kind && p.k.a == q.k.a && p.k.b == q.k.b &&
+         p.tol == q.tol && p.max_newton == q.max_newton && p.cg_rtol == q.cg_rtol && p.max_cg == q.max_cg &&
+         p.tangent == q.tangent && a.n_steps == b.n_steps && a.source == b.source &&
+         (!a.source || a.lambda == b.lambda);
+}
+
+// Runs several requests as one: their meshes joined into a disjoint union (wq_batch), the
+// points and weights built once over it (every system binned with the others by size),
+// and every time step one heat step over the union, whose tangent is block diagonal
+// (mesh by mesh). Newton stops when the union's ||R_free||_2 <= tol, so every mesh's own
+// residual meets the tolerance too; the Krylov solves run over the union, so a result
+// agrees with the request run alone to the solver tolerances, not bit for bit. Iteration
+// counts and the residual reported are the union's. No setup is held afterwards.
+wq_status run_joined(const std::vector<Request*>& g, hipStream_t st) {
+  const int m = (int)g.size();
+  std::vector<wq_mesh_desc> descs(m);
+  for (int k = 0; k < m; ++k) descs[k] = g[k]->desc;
+  wq_batch* b = nullptr;
+  wq_status s = wq_batch_create(descs.data(), m, &b);
+  if (s == WQ_OK) s = wq_batch_build(b, WQ_FAM_MASS | WQ_FAM_DX | WQ_FAM_DY, 1e-12, (wq_stream)st, nullptr);
+  wq_points* pts = s == WQ_OK ? wq_batch_points(b) : nullptr;
+  wq_weights* w = s == WQ_OK ? wq_batch_weights(b) : nullptr;
+  const int64_t n = pts ? pts->n_rows : 0, nnz = pts ? pts->nnz : 0, np = pts ? pts->n_points : 0;
+  DBuf T, Td, S, dir, f;
+  if (s == WQ_OK) s = dalloc_n<double>(T, n);
+  if (s == WQ_OK) s = dalloc_n<double>(Td, n);
+  if (s == WQ_OK) s = dalloc_n<double>(S, nnz);
+  if (s == WQ_OK) s = dalloc_n<uint8_t>(dir, n);
+  if (s == WQ_OK && g[0]->source) s = dalloc_n<double>(f, np);
+  std::vector<int64_t> row0(m), nr(m), nz(m);
+  for (int k = 0; k < m && s == WQ_OK; ++k) s = wq_batch_info(b, k, &row0[k], &nr[k], nullptr, &nz[k], nullptr, nullptr);
+  if (s == WQ_OK) {
+    if (hipMemsetAsync(T.p, 0, n * sizeof(double), st) != hipSuccess ||
+        hipMemsetAsync(Td.p, 0, n * sizeof(double), st) != hipSuccess)
+      s = WQ_EDEVICE;
+    for (int k = 0; k < m && s == WQ_OK; ++k)
+      if (hipMemcpyAsync(dir.as<uint8_t>() + row0[k], g[k]->dirichlet.data(), nr[k], hipMemcpyHostToDevice, st) !=
+          hipSuccess)
+        s = WQ_EDEVICE;
+  }
+  wq_result acc{};
+  if (s == WQ_OK) s = time_steps(*g[0], pts, w, np, dir, T, Td, S, f, st, acc);
+  for (int k = 0; k < m && s == WQ_OK; ++k)
+    if (g[k]->T_out && hipMemcpyAsync(g[k]->T_out, T.as<double>() + row0[k], nr[k] * sizeof(double),
+                                      hipMemcpyDeviceToHost, st) != hipSuccess)
+      s = WQ_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess && s == WQ_OK) s = WQ_EDEVICE;
+  for (int k = 0; k < m; ++k) {
+    wq_result& res = g[k]->res;
+    res.n_rows = nr[k];
+    res.nnz = nz[k];
+    res.newton_iters = acc.newton_iters;
+    res.cg_iters = acc.cg_iters;
+    res.residual = acc.residual;
+    res.joined = m;
+  }
+  DBuf* bufs[5] = {&T, &Td, &S, &dir, &f};
+  dfree_many(bufs, 5);
+  wq_batch_destroy(b);
+  return s;
 }
 
 // Runs one request. With r->setup, its mesh, points and weights are reused; otherwise
@@ -156,21 +248,8 @@ wq_status run_request(Request* r, hipStream_t st, Setup** built) {
   }
   r->res.n_rows = n;
   r->res.nnz = nnz;
-  for (int step = 0; s == WQ_OK && step < r->n_steps; ++step) {
-    const double t1 = r->heat.dt * (step + 1);
-    if (r->source) {
-      k_manufactured_source<<<nblocks(np, 256), 256, 0, st>>>(np, pts->x.as<double>(), t1, r->lambda, r->heat.k,
-                                                               f.as<double>());
-      if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
-    }
-    wq_heat_report rep{};
-    if (s == WQ_OK)
-      s = wq_heat_step(pts, w, &r->heat, dir.as<uint8_t>(), nullptr, r->source ? f.as<double>() : nullptr,
-                       T.as<double>(), Td.as<double>(), S.as<double>(), &rep, (wq_stream)st);
-    r->res.newton_iters += rep.newton_iters;
-    r->res.cg_iters += rep.cg_iters;
-    r->res.residual = rep.residual;
-  }
+  r->res.joined = 1;
+  if (s == WQ_OK) s = time_steps(*r, pts, w, np, dir, T, Td, S, f, st, r->res);
   if (s == WQ_OK && r->T_out) {
     if (hipMemcpyAsync(r->T_out, T.p, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
@@ -214,6 +293,7 @@ void worker(wq_server* sv) {
   const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
   for (;;) {
     Request* r = nullptr;
+    std::vector<Request*> group;  // r and the requests joined to it
     std::vector<Setup*> evicted;
     {
       std::unique_lock<std::mutex> lk(sv->mu);
@@ -254,15 +334,37 @@ void worker(wq_server* sv) {
         }
         sv->in_use += r->est;
       }
-      r->res.setup_reused = r->setup ? 1 : 0;
-      r->res.started = now_s(sv->t0);
+      group.push_back(r);
+      // joining: later queued requests with r's parameters that have no idle setup to
+      // take over and fit next to it in the budget (no further setups are released)
+      if (!r->setup && sv->join > 1) {
+        int64_t rows = r->desc.n_fn;
+        for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)group.size() < sv->join;) {
+          Request* q = *it;
+          if (joinable(*r, *q) && !idle_match(*q) && sv->in_use + q->est <= sv->budget &&
+              rows + q->desc.n_fn <= sv->join_rows) {
+            sv->in_use += q->est;
+            rows += q->desc.n_fn;
+            group.push_back(q);
+            it = sv->queue.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      }
+      for (Request* q : group) {
+        q->res.setup_reused = q->setup ? 1 : 0;
+        q->res.started = now_s(sv->t0);
+      }
     }
     for (Setup* h : evicted) {  // device frees outside the lock
       h->release();
       delete h;
     }
     Setup* built = nullptr;
-    const wq_status s = have_stream ? run_request(r, st, &built) : WQ_EDEVICE;
+    const wq_status s = !have_stream        ? WQ_EDEVICE
+                        : group.size() == 1 ? run_request(r, st, &built)
+                                            : run_joined(group, st);
     {
       std::lock_guard<std::mutex> lk(sv->mu);
       if (r->setup) {
@@ -274,9 +376,12 @@ void worker(wq_server* sv) {
       } else {
         sv->in_use -= r->est;
       }
-      r->res.status = s;
-      r->res.finished = now_s(sv->t0);
-      r->done = true;
+      for (size_t k = 1; k < group.size(); ++k) sv->in_use -= group[k]->est;
+      for (Request* q : group) {
+        q->res.status = s;
+        q->res.finished = now_s(sv->t0);
+        q->done = true;
+      }
     }
     sv->cv_done.notify_all();
     sv->cv_work.notify_all();
@@ -295,6 +400,18 @@ extern "C" wq_status wq_server_start(size_t hbm_budget_bytes, int32_t slots, wq_
   sv->t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker, sv);
   *out = sv;
+  return WQ_OK;
+}
+
+extern "C" wq_status wq_server_set_join(wq_server* sv, int32_t max_meshes, int64_t max_rows) {
+  WQ_CHECK(sv && max_meshes >= 1 && max_meshes <= 4096 && max_rows >= 0, WQ_EINVAL,
+           "wq_server_set_join: need 1..4096 meshes and max_rows >= 0");
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->join = max_meshes;
+    sv->join_rows = max_rows;
+  }
+  sv->cv_work.notify_all();
   return WQ_OK;
 }
 

@@ -74,7 +74,8 @@ class Request(C.Structure):
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("newton_iters", C.c_int32), ("cg_iters", C.c_int32), ("n_rows", C.c_int64),
                 ("nnz", C.c_int64), ("residual", C.c_double), ("submitted", C.c_double), ("started", C.c_double),
-                ("finished", C.c_double), ("hbm_estimate", C.c_size_t), ("setup_reused", C.c_int32)]
+                ("finished", C.c_double), ("hbm_estimate", C.c_size_t), ("setup_reused", C.c_int32),
+                ("joined", C.c_int32)]
 
 _LIB = None
 
@@ -111,6 +112,7 @@ def _lib():
             "wq_server_submit": ([P, C.POINTER(Request), P, P], C.c_int),
             "wq_server_poll": ([P, C.c_int64, C.c_int, C.POINTER(Result)], C.c_int),
             "wq_server_stop": ([P], None),
+            "wq_server_set_join": ([P, C.c_int32, C.c_int64], C.c_int),
             "wq_batch_create": ([P, C.c_int32, P], C.c_int),
             "wq_batch_build": ([P, U, D, P, P], C.c_int),
             "wq_batch_info": ([P, C.c_int32, P, P, P, P, P, P], C.c_int),
@@ -145,7 +147,7 @@ def exported_symbols():
             "wq_points_size", "wq_points_info", "wq_points_get", "solve_weights", "wq_weights_destroy", "wq_weights_get",
             "wq_rhs_get", "assemble_mass", "assemble_stiffness", "assemble_biharmonic", "assemble_mass_stiffness",
             "assemble_tangent", "assemble_tangent_noalloc", "assemble_tangent_exact", "wq_heat_step", "wq_server_start", "wq_server_submit", "wq_server_poll",
-            "wq_server_stop", "wq_batch_create", "wq_batch_build", "wq_batch_info", "wq_batch_points",
+            "wq_server_stop", "wq_server_set_join", "wq_batch_create", "wq_batch_build", "wq_batch_info", "wq_batch_points",
             "wq_batch_weights", "wq_batch_graph_assemble", "wq_batch_destroy", "wq_autotune_assembly", "wq_autotune_tiles",
             "gauss_setup", "wq_gauss_destroy", "wq_gauss_size", "wq_gauss_get_x", "assemble_gauss",
             "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
@@ -463,6 +465,11 @@ class Server:
                "wq_server_submit")
         self._out[ticket.value] = T
         return ticket.value
+
+    def set_join(self, max_meshes, max_rows=1 << 15):
+        """Requests queued together with the same parameters run as one union of up to
+        `max_meshes` meshes and `max_rows` rows (1 mesh: each alone)."""
+        _check(_lib().wq_server_set_join(self.h, int(max_meshes), int(max_rows)), "wq_server_set_join")
 
     def poll(self, ticket, wait=True):
         """None while pending; else (T, result dict)."""

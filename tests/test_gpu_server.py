@@ -170,3 +170,57 @@ def test_requests_without_setup_reuse(pool):
     print(f"[gpu] served Newton iterations: symmetric {r1['newton_iters']}, exact {r3['newton_iters']}")
     assert r3["newton_iters"] < r1["newton_iters"]
     assert np.abs(T3 - T1).max() <= 1e-8 * np.abs(T1).max()
+
+
+def test_joined_requests_agree_with_alone(pool):
+    """Joining (wq_server_set_join): requests queued together with the same parameters run
+    as one union of their meshes. With one slot, the requests submitted while the first one
+    runs are joined at the next admission; each reports the union's size, and its
+    temperature agrees with the same request run alone to the solver tolerances (Newton
+    stops at ||R_free||_2 <= 1e-10 over the union, so over every mesh). A request with other
+    heat parameters is not joined and gives the bits it gives alone."""
+    W = _wq()
+    same = [(pool[i % len(pool)], KINDS[0], 0.25) for i in range(6)]
+    odd = (pool[1], KINDS[1], 0.3)
+    S = W.Server(8 << 30, 1)
+    alone = [S.poll(_submit(S, r)) for r in same + [odd]]
+    with pytest.raises(W.WQError):
+        S.set_join(0)
+    with pytest.raises(W.WQError):
+        S.set_join(4, -1)
+    S.close()
+    S = W.Server(8 << 30, 1)
+    S.set_join(8)
+    tickets = [_submit(S, r) for r in same + [odd]]
+    out = [S.poll(t) for t in tickets]
+    S.close()
+    joined = [res["joined"] for _, res in out]
+    print(f"[gpu] joined sizes {joined}", flush=True)
+    assert all(res["status"] == 0 for _, res in out)
+    assert max(joined[:-1]) >= 2 and joined[-1] == 1
+    for (Ta, ra), (Tj, rj) in zip(alone, out):
+        assert rj["n_rows"] == ra["n_rows"] and rj["nnz"] == ra["nnz"]
+        assert rj["residual"] <= 1e-10
+        err = np.abs(Tj - Ta).max()
+        print(f"[gpu] joined {rj['joined']}: max |T_joined - T_alone| {err:.2e} (max |T| {np.abs(Ta).max():.2f})")
+        if rj["joined"] == 1:  # (alone, it may take over a setup held by an earlier request)
+            assert np.array_equal(Tj, Ta)
+        else:
+            assert err < 1e-7 and rj["setup_reused"] == 0
+
+
+def test_join_row_cap_keeps_requests_apart(pool):
+    """A union may not exceed max_rows: with a cap below any two meshes together, no
+    request is joined and every result is bit-identical to the request run alone."""
+    W = _wq()
+    reqs = [(pool[i % len(pool)], KINDS[0], 0.25) for i in range(4)]
+    S = W.Server(8 << 30, 1)
+    alone = [S.poll(_submit(S, r))[0] for r in reqs]
+    S.close()
+    S = W.Server(8 << 30, 1)
+    S.set_join(8, max_rows=min(F["n_fn"] for F in pool))
+    out = [S.poll(t) for t in [_submit(S, r) for r in reqs]]
+    S.close()
+    assert [res["joined"] for _, res in out] == [1] * len(reqs)
+    for Ta, (Tj, _) in zip(alone, out):
+        assert np.array_equal(Tj, Ta)
