@@ -375,13 +375,13 @@ void wq_server_stop(wq_server* server);
  * lambda) that have no idle held setup of their own domain and fit in the budget next to
  * it, up to max_meshes requests and max_rows rows (functions) in all, run with it as one: their meshes are joined into
  * one disjoint union (as wq_batch_create), the points and weights are built once over it,
- * and each time step is one wq_heat_step over the union, so that setup and every Newton
- * and Krylov step of all of them share launches. The union's tangent is block diagonal and
- * its Newton stop, ||R_free||_2 <= tol over the union, holds for every mesh's own
- * residual; the Krylov solves run over the union, so a joined result agrees with the
- * request run alone to the solver tolerances, not bit for bit. The union's iteration
- * counts and residual are reported for each joined request (wq_result.joined > 1), and no
- * setup of a joined request is held afterwards. Joining pays where launches and host
+ * and each time step is one heat step over the union with one segment per mesh, so that
+ * setup and every Newton and Krylov step of all of them share launches. The union's tangent
+ * is block diagonal; each segment is solved as if alone (its reductions sum its own rows in
+ * the order they take alone, its scalars and its Newton and Krylov stops are its own), so a
+ * joined request's temperature, iteration counts, residual and status are bit for bit those
+ * it gets alone (wq_result.joined > 1 reports the union's size). A failed member does not
+ * stop the others. No setup of a joined request is held afterwards. Joining pays where launches and host
  * round trips, not the device's throughput, bound a request (small meshes); max_rows keeps
  * larger ones apart (a request above it runs alone). Applies to admissions after the call;
  * max_meshes in 1..4096 and max_rows >= 0, else WQ_EINVAL. */

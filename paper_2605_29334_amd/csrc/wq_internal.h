@@ -243,5 +243,15 @@ wq_status gauss_basis(wq_mesh* M, wq_points* P, double* GN, double* GX, double* 
 // Rebuilds the cell-major assembly tiles of P with its current t2_stepcap (and counts the
 // rebuild in t2_gen). Synchronises st.
 wq_status rebuild_tiles2(wq_points* P, hipStream_t st);
+// One heat time step (as wq_heat_step) on rows split into nseg consecutive segments
+// [seg_row0[k], seg_row0[k + 1]) (host array) whose rows couple only within the segment
+// (the meshes of a union): every segment is solved as if alone (its own reductions in its
+// own block order, scalars, Newton and Krylov stops), in shared launches. reps[k] and
+// stats[k] receive segment k's report and status; the return value is the call's own
+// (arguments, device).
+wq_status heat_step_segments(const wq_points* P, const wq_weights* w, const wq_heat_params* hp,
+                             const uint8_t* dirichlet, const double* g_next, const double* f_at_pts, double* T,
+                             double* Tdot, double* S_vals, int32_t nseg, const int64_t* seg_row0,
+                             wq_heat_report* reps, wq_status* stats, hipStream_t st);
 
 }  // namespace wq

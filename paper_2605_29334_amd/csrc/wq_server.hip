@@ -129,25 +129,38 @@ size_t hbm_estimate(const wq_mesh_desc& d) {
   return (size_t)16384 * (size_t)d.nf + (size_t)256 * (size_t)d.n_fn + ((size_t)8 << 20);
 }
 
-// The request's time steps from T = Tdot = 0 (already cleared) on a points/weights pair:
-// the manufactured source at t_{n+1}, then one heat step; iteration counts add up in res.
+// The time steps from T = Tdot = 0 (already cleared) on a points/weights pair whose rows
+// form nseg segments, one request each (parameters from r): the manufactured source at
+// t_{n+1}, then one heat step of every segment as if alone; iteration counts add up in
+// *res[k], and seg_status[k] receives segment k's first failure. The steps end once
+// every segment has failed or the device fails (the call's status).
 wq_status time_steps(const Request& r, wq_points* pts, wq_weights* w, int64_t np, const DBuf& dir, const DBuf& T,
-                     const DBuf& Td, const DBuf& S, const DBuf& f, hipStream_t st, wq_result& res) {
+                     const DBuf& Td, const DBuf& S, const DBuf& f, hipStream_t st, int32_t nseg, const int64_t* row0,
+                     wq_result* const* res, wq_status* seg_status) {
+  std::vector<wq_heat_report> reps(nseg);
+  std::vector<wq_status> ss(nseg);
+  for (int32_t k = 0; k < nseg; ++k) seg_status[k] = WQ_OK;
   wq_status s = WQ_OK;
-  for (int step = 0; s == WQ_OK && step < r.n_steps; ++step) {
+  bool live = true;
+  for (int step = 0; s == WQ_OK && live && step < r.n_steps; ++step) {
     const double t1 = r.heat.dt * (step + 1);
     if (r.source) {
       k_manufactured_source<<<nblocks(np, 256), 256, 0, st>>>(np, pts->x.as<double>(), t1, r.lambda, r.heat.k,
                                                                f.as<double>());
       if (hipGetLastError() != hipSuccess) s = WQ_EDEVICE;
     }
-    wq_heat_report rep{};
     if (s == WQ_OK)
-      s = wq_heat_step(pts, w, &r.heat, dir.as<uint8_t>(), nullptr, r.source ? f.as<double>() : nullptr,
-                       T.as<double>(), Td.as<double>(), S.as<double>(), &rep, (wq_stream)st);
-    res.newton_iters += rep.newton_iters;
-    res.cg_iters += rep.cg_iters;
-    res.residual = rep.residual;
+      s = heat_step_segments(pts, w, &r.heat, dir.as<uint8_t>(), nullptr, r.source ? f.as<double>() : nullptr,
+                             T.as<double>(), Td.as<double>(), S.as<double>(), nseg, row0, reps.data(), ss.data(), st);
+    if (s != WQ_OK) break;
+    live = false;
+    for (int32_t k = 0; k < nseg; ++k) {
+      res[k]->newton_iters += reps[k].newton_iters;
+      res[k]->cg_iters += reps[k].cg_iters;
+      res[k]->residual = reps[k].residual;
+      if (seg_status[k] == WQ_OK) seg_status[k] = ss[k];
+      live = live || seg_status[k] == WQ_OK;
+    }
   }
   return s;
 }
@@ -163,11 +176,10 @@ bool joinable(const Request& a, const Request& b) {
 
 // Runs several requests as one: their meshes joined into a disjoint union (wq_batch), the
 // points and weights built once over it (every system binned with the others by size),
-// and every time step one heat step over the union, whose tangent is block diagonal
-// (mesh by mesh). Newton stops when the union's ||R_free||_2 <= tol, so every mesh's own
-// residual meets the tolerance too; the Krylov solves run over the union, so a result
-// agrees with the request run alone to the solver tolerances, not bit for bit. Iteration
-// counts and the residual reported are the union's. No setup is held afterwards.
+// and every time step one heat step over the union with one segment per mesh (the
+// tangent is block diagonal): shared launches, each mesh solved as if alone, so every
+// request's temperature, iteration counts and residual are those it gets alone. No setup
+// is held afterwards.
 wq_status run_joined(const std::vector<Request*>& g, hipStream_t st) {
   const int m = (int)g.size();
   std::vector<wq_mesh_desc> descs(m);
@@ -195,22 +207,24 @@ wq_status run_joined(const std::vector<Request*>& g, hipStream_t st) {
           hipSuccess)
         s = WQ_EDEVICE;
   }
-  wq_result acc{};
-  if (s == WQ_OK) s = time_steps(*g[0], pts, w, np, dir, T, Td, S, f, st, acc);
+  std::vector<int64_t> seg(m + 1, n);
+  std::vector<wq_result*> res(m);
+  std::vector<wq_status> ss(m, WQ_OK);
+  for (int k = 0; k < m; ++k) {
+    seg[k] = row0[k];
+    res[k] = &g[k]->res;
+    res[k]->n_rows = nr[k];
+    res[k]->nnz = nz[k];
+    res[k]->joined = m;
+  }
+  if (s == WQ_OK) s = time_steps(*g[0], pts, w, np, dir, T, Td, S, f, st, m, seg.data(), res.data(), ss.data());
   for (int k = 0; k < m && s == WQ_OK; ++k)
-    if (g[k]->T_out && hipMemcpyAsync(g[k]->T_out, T.as<double>() + row0[k], nr[k] * sizeof(double),
-                                      hipMemcpyDeviceToHost, st) != hipSuccess)
+    if (ss[k] == WQ_OK && g[k]->T_out &&
+        hipMemcpyAsync(g[k]->T_out, T.as<double>() + row0[k], nr[k] * sizeof(double), hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
       s = WQ_EDEVICE;
   if (hipStreamSynchronize(st) != hipSuccess && s == WQ_OK) s = WQ_EDEVICE;
-  for (int k = 0; k < m; ++k) {
-    wq_result& res = g[k]->res;
-    res.n_rows = nr[k];
-    res.nnz = nz[k];
-    res.newton_iters = acc.newton_iters;
-    res.cg_iters = acc.cg_iters;
-    res.residual = acc.residual;
-    res.joined = m;
-  }
+  for (int k = 0; k < m; ++k) g[k]->res.status = s != WQ_OK ? s : ss[k];
   DBuf* bufs[5] = {&T, &Td, &S, &dir, &f};
   dfree_many(bufs, 5);
   wq_batch_destroy(b);
@@ -249,7 +263,13 @@ wq_status run_request(Request* r, hipStream_t st, Setup** built) {
   r->res.n_rows = n;
   r->res.nnz = nnz;
   r->res.joined = 1;
-  if (s == WQ_OK) s = time_steps(*r, pts, w, np, dir, T, Td, S, f, st, r->res);
+  if (s == WQ_OK) {
+    const int64_t seg[2] = {0, n};
+    wq_result* res = &r->res;
+    wq_status ss = WQ_OK;
+    s = time_steps(*r, pts, w, np, dir, T, Td, S, f, st, 1, seg, &res, &ss);
+    if (s == WQ_OK) s = ss;
+  }
   if (s == WQ_OK && r->T_out) {
     if (hipMemcpyAsync(r->T_out, T.p, n * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
@@ -378,7 +398,7 @@ void worker(wq_server* sv) {
       }
       for (size_t k = 1; k < group.size(); ++k) sv->in_use -= group[k]->est;
       for (Request* q : group) {
-        q->res.status = s;
+        if (group.size() == 1 || !have_stream) q->res.status = s;  // (else run_joined set each one's own)
         q->res.finished = now_s(sv->t0);
         q->done = true;
       }
