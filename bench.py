@@ -515,6 +515,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--cpu-all-cores", type=float, default=12.0, help="seconds of the all-cores oracle run (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--side-streams", type=int, default=4,
+                    help="streams for the independent launches within one call in the timed steps (1: none)")
     ap.add_argument("--no-extra-forms", action="store_true", help="skip the batched and served measurements")
     ap.add_argument("--extra", default="", help="comma-separated extra workloads: c1, c3, c4")
     args = ap.parse_args()
@@ -525,6 +527,7 @@ def main():
 
     import torch
     import paper_2605_29334_amd.wq as W
+    W.set_side_streams(args.side_streams)
 
     torch.cuda.set_device(0)
     print(f"[bench] generating fixture N={args.N}", file=sys.stderr, flush=True)
@@ -560,8 +563,6 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
     live = None
-    W.timing_enable(True)
-    W.timings()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -569,13 +570,27 @@ def main():
         live = step((c, k))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s ({args.side_streams} side streams)",
+          file=sys.stderr, flush=True)
+    # per-kernel records (HIP events on each launch's stream): the same steps again with
+    # every launch on the step's stream, so that a record is the kernel's own time and not
+    # shared with kernels of other size buckets running beside it
+    W.set_side_streams(1)
+    W.timing_enable(True)
+    W.timings()
+    for _ in range(args.steps):
+        live = None
+        live = step((c, k))
+    torch.cuda.synchronize()
     recs = W.timings()
     W.timing_enable(False)
-    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    W.set_side_streams(args.side_streams)
 
     per_kernel = aggregate(recs, args.steps)
     dom_name, dom = max(per_kernel.items(), key=lambda kv: kv[1]["ms"])
     roofline = roofline_of(dom_name, dom)
+    roofline["launch_timing"] = ("a second pass of the timed steps with one launch at a time (side streams 1), "
+                                 "so that each kernel's duration is its own")
 
     # assembly only (weights and basis resident; caches flushed between repetitions),
     # timed by the library's HIP events on the launch stream; FP64 and the low-precision

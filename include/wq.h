@@ -452,6 +452,16 @@ typedef struct {
   int64_t work;
 } wq_timing;
 void wq_timing_enable(int on);
+
+/* wq_set_side_streams: streams for the independent launches within one call (the size
+ * buckets of solve_weights and their second launches): n non-blocking streams of default
+ * priority, created per call, forked from the caller's stream and joined back into it by
+ * events, so the call stays ordered on `stream` as before. Small and partial launches then
+ * fill CUs the large ones leave idle. 4 by default; n = 1 keeps every launch on the
+ * caller's stream (then a timing record is the kernel's own time: with several, records
+ * of concurrent kernels overlap). Results do not depend on it. n in 1..8, else WQ_EINVAL;
+ * applies to calls that start after it. */
+wq_status wq_set_side_streams(int32_t n);
 int wq_timings(wq_timing* out, int cap);
 
 /* ------------------------------------------------------------------ errors */

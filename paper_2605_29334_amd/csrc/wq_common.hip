@@ -1,6 +1,8 @@
 // Errors, device buffers, scans and the mesh handle.
 #include "wq_internal.h"
 
+#include <atomic>
+
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
@@ -214,6 +216,10 @@ wq_status exclusive_scan_i64(int64_t* d, int64_t n, int64_t* total, hipStream_t 
   return WQ_OK;
 }
 
+// ------------------------------------------------------------------ side streams
+static std::atomic<int> g_side{4};
+int side_streams() { return g_side.load(); }
+
 // ------------------------------------------------------------------ kernel timing
 static bool g_timing = false;
 struct TRec {
@@ -246,6 +252,12 @@ void KTimer::stop() {
 using namespace wq;
 
 extern "C" void wq_timing_enable(int on) { g_timing = on != 0; }
+
+extern "C" wq_status wq_set_side_streams(int32_t n) {
+  WQ_CHECK(n >= 1 && n <= 8, WQ_EINVAL, "wq_set_side_streams: need 1..8 streams");
+  g_side.store(n);
+  return WQ_OK;
+}
 
 extern "C" int wq_timings(wq_timing* out, int cap) {
   int n = 0;

@@ -171,6 +171,8 @@ wq_status exclusive_scan_i64(int64_t* d, int64_t n, int64_t* total, hipStream_t 
 
 // whether kernel timing records are being taken (wq_timing_enable)
 bool timing_enabled();
+// side streams for independent launches of one call (wq_set_side_streams; 1: none)
+int side_streams();
 
 // kernel timing (wq_timing_enable): records events around a launch when enabled
 struct KTimer {

@@ -2,6 +2,7 @@
 // and truncated-SVD weights (Section 4.3, Eqs. (19)-(22)) for every (row, family).
 #include "wq_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -1686,6 +1687,52 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_
 }
 
 
+// Side streams for the independent launches of one call (the size buckets): created per
+// call (wq_set_side_streams of them, 4 by default), non-blocking and of default priority,
+// forked from the caller's stream and joined back into it by events. Launch k goes to side
+// stream k mod N, so that the small launches (a bucket's last partial round of workgroups,
+// the second launches of the few systems a first pass leaves) fill the CUs the large ones
+// leave idle. With one (or if creation fails) every launch stays on the caller's stream.
+struct Fork {
+  static constexpr int NMAX = 8;
+  hipStream_t home;
+  hipStream_t s[NMAX] = {};
+  hipEvent_t e[NMAX + 1] = {};
+  int n = 0;
+  bool ok = false;
+  int next = 0;
+  explicit Fork(hipStream_t st) : home(st) {
+    const int want = std::min(std::max(side_streams(), 1), NMAX);
+    if (want < 2) return;
+    ok = true;
+    for (; n < want && ok; ++n) ok = hipStreamCreateWithFlags(&s[n], hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k <= n && ok; ++k) ok = hipEventCreateWithFlags(&e[k], hipEventDisableTiming) == hipSuccess;
+  }
+  ~Fork() {
+    for (int k = 0; k < NMAX; ++k)
+      if (s[k]) (void)hipStreamDestroy(s[k]);
+    for (int k = 0; k <= NMAX; ++k)
+      if (e[k]) (void)hipEventDestroy(e[k]);
+  }
+  // the side streams wait for the caller's work so far
+  bool fork() {
+    next = 0;
+    if (!ok) return true;
+    if (hipEventRecord(e[n], home) != hipSuccess) return false;
+    for (int k = 0; k < n; ++k)
+      if (hipStreamWaitEvent(s[k], e[n], 0) != hipSuccess) return false;
+    return true;
+  }
+  hipStream_t lane() { return ok ? s[next++ % n] : home; }
+  // the caller's stream waits for the side streams' work
+  bool join() {
+    if (!ok) return true;
+    for (int k = 0; k < n; ++k)
+      if (hipEventRecord(e[k], s[k]) != hipSuccess || hipStreamWaitEvent(home, e[k], 0) != hipSuccess) return false;
+    return true;
+  }
+};
+
 void release_weights(wq_weights* w) {
   DBuf* all[2 * NFAM];
   for (int f = 0; f < NFAM; ++f) {
@@ -1855,7 +1902,7 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
     base.fail = &R->fail;
   }
   // The SVD kernel for the systems of bucket b (all of them, or the `grid` listed in sel).
-  auto svd_launch = [&](int b, const int32_t* sel, int64_t grid, int64_t flops) -> wq_status {
+  auto svd_launch = [&](int b, const int32_t* sel, int64_t grid, int64_t flops, hipStream_t ls) -> wq_status {
     const int64_t ns = hist[b];
     const int mn = hist[2 * (NBKT + 1) + 2 * b];      // largest n in the bucket
     const int mr = hist[2 * (NBKT + 1) + 2 * b + 1];  // largest r in the bucket
@@ -1948,15 +1995,15 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       set_error("solve_weights: cannot raise the LDS limit of the TSVD kernel");
       return WQ_EDEVICE;
     }
-    KTimer tm(kname, flops, st);
+    KTimer tm(kname, flops, ls);
     void* args[] = {&ta};
-    wq_status ls = WQ_OK;
-    if (hipLaunchKernel(fn, dim3((unsigned)grid), dim3(nt), args, lds, st) != hipSuccess) {
+    wq_status res = WQ_OK;
+    if (hipLaunchKernel(fn, dim3((unsigned)grid), dim3(nt), args, lds, ls) != hipSuccess) {
       set_error("solve_weights: TSVD launch failed");
-      ls = WQ_EDEVICE;
+      res = WQ_EDEVICE;
     }
     tm.stop();
-    return ls;
+    return res;
   };
   // Systems of at most 64 constraints and 64 points go to the one-wave solver first; the
   // ones its rank proof does not cover are listed and solved by the SVD kernel of their
@@ -1971,6 +2018,10 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
   if (s == WQ_OK && hipMemsetAsync(fbc.p, 0, NBKT * sizeof(int), st) != hipSuccess) s = WQ_EDEVICE;
   fb_lists = fbl.as<int32_t>();
   fb_counts = fbc.as<int>();
+  // the buckets' launches are independent (each system's weights are written by one
+  // workgroup; the reports and the second-launch lists are updated atomically)
+  Fork fk(st);
+  if (s == WQ_OK && !fk.fork()) s = WQ_EDEVICE;
   for (int b = 0; b < NBKT && s == WQ_OK; ++b) {
     const int64_t ns = hist[b];
     if (ns == 0) continue;
@@ -1990,14 +2041,16 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       const int nd = (direct_mask & 1u) ? 1 : 0;
       if (nd) {
         ta.fam_base = 0;
-        KTimer tm("k_wsolve_direct", (int64_t)bflops[b], st);
-        k_wsolve<true><<<dim3((unsigned)ns), dim3(64), lds, st>>>(ta);
+        const hipStream_t ls = fk.lane();
+        KTimer tm("k_wsolve_direct", (int64_t)bflops[b], ls);
+        k_wsolve<true><<<dim3((unsigned)ns), dim3(64), lds, ls>>>(ta);
         tm.stop();
       }
       if (nfam > nd) {
         ta.fam_base = nd;
-        KTimer tm("k_wsolve", (int64_t)bflops[b] * (nfam - nd), st);
-        k_wsolve<false><<<dim3((unsigned)(ns * (nfam - nd))), dim3(64), lds, st>>>(ta);
+        const hipStream_t ls = fk.lane();
+        KTimer tm("k_wsolve", (int64_t)bflops[b] * (nfam - nd), ls);
+        k_wsolve<false><<<dim3((unsigned)(ns * (nfam - nd))), dim3(64), lds, ls>>>(ta);
         tm.stop();
       }
       if (hipGetLastError() != hipSuccess) {
@@ -2006,16 +2059,19 @@ extern "C" wq_status solve_weights(wq_mesh* M, wq_points* P, unsigned fam_mask, 
       }
       any_w = true;
     } else {
-      s = svd_launch(b, nullptr, ns * nfam, (int64_t)bflops[b] * nfam);
+      s = svd_launch(b, nullptr, ns * nfam, (int64_t)bflops[b] * nfam, fk.lane());
       any_w = any_w || direct_mask != 0;
     }
   }
+  if (!fk.join() && s == WQ_OK) s = WQ_EDEVICE;
   if (s == WQ_OK && any_w) {
     if (hipMemcpyAsync(fbn, fbc.p, NBKT * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       s = WQ_EDEVICE;
+    if (s == WQ_OK && !fk.fork()) s = WQ_EDEVICE;
     for (int b = 0; b < NBKT && s == WQ_OK; ++b)
-      if (hist[b] && fbn[b] > 0) s = svd_launch(b, fbl.as<int32_t>() + start[b] * nfam, fbn[b], 0);
+      if (hist[b] && fbn[b] > 0) s = svd_launch(b, fbl.as<int32_t>() + start[b] * nfam, fbn[b], 0, fk.lane());
+    if (!fk.join() && s == WQ_OK) s = WQ_EDEVICE;
   }
   dfree(fbl);
   dfree(fbc);

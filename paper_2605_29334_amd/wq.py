@@ -113,6 +113,7 @@ def _lib():
             "wq_server_poll": ([P, C.c_int64, C.c_int, C.POINTER(Result)], C.c_int),
             "wq_server_stop": ([P], None),
             "wq_server_set_join": ([P, C.c_int32, C.c_int64], C.c_int),
+            "wq_set_side_streams": ([C.c_int32], C.c_int),
             "wq_batch_create": ([P, C.c_int32, P], C.c_int),
             "wq_batch_build": ([P, U, D, P, P], C.c_int),
             "wq_batch_info": ([P, C.c_int32, P, P, P, P, P, P], C.c_int),
@@ -150,7 +151,7 @@ def exported_symbols():
             "wq_server_stop", "wq_server_set_join", "wq_batch_create", "wq_batch_build", "wq_batch_info", "wq_batch_points",
             "wq_batch_weights", "wq_batch_graph_assemble", "wq_batch_destroy", "wq_autotune_assembly", "wq_autotune_tiles",
             "gauss_setup", "wq_gauss_destroy", "wq_gauss_size", "wq_gauss_get_x", "assemble_gauss",
-            "wq_timing_enable", "wq_timings", "wq_strerror", "wq_last_error"]
+            "wq_timing_enable", "wq_timings", "wq_set_side_streams", "wq_strerror", "wq_last_error"]
 
 
 def _check(status, where):
@@ -579,6 +580,11 @@ def autotune_tiles(points, weights, stream=None):
 def timing_enable(on=True):
     """Record HIP events around the library's main kernels (measurement aid)."""
     _lib().wq_timing_enable(1 if on else 0)
+
+
+def set_side_streams(n):
+    """Streams for the independent launches within one call (1: all on the caller's stream)."""
+    _check(_lib().wq_set_side_streams(int(n)), "wq_set_side_streams")
 
 
 def timings(cap=4096):

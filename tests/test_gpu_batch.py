@@ -173,3 +173,27 @@ def test_batch_meshes_against_oracle(batch):
         print(f"[gpu] batch mesh {m}: mass (oracle weights) rel err {em:.2e}, "
               f"stiffness (batch weights) rel err {ek:.2e}", flush=True)
         assert em < 1e-12 and ek < 1e-12
+
+
+def test_side_streams_change_schedule_not_values(batch):
+    """The size buckets' launches on 1, 4 or 8 side streams (wq_set_side_streams): the
+    weights of the whole batch and its solve report are bit-identical (each system is
+    solved by one workgroup; the reports are atomic minima, maxima and counts)."""
+    W, pool, _ = batch
+    got = {}
+    try:
+        for ns in (1, 4, 8):
+            W.set_side_streams(ns)
+            B = W.Batch(pool).build(1 | 2 | 4)
+            got[ns] = ({f: _np(B.weights.weights(f)) for f in (1, 2, 4)}, dict(B.report))
+            B.close()
+        with pytest.raises(W.WQError):
+            W.set_side_streams(0)
+        with pytest.raises(W.WQError):
+            W.set_side_streams(9)
+    finally:
+        W.set_side_streams(4)
+    for ns in (4, 8):
+        for f in (1, 2, 4):
+            assert np.array_equal(got[ns][0][f], got[1][0][f]), (ns, f)
+        assert got[ns][1] == got[1][1], ns
