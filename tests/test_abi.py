@@ -47,6 +47,17 @@ def test_strerror_is_host_only(lib):
     assert lib.wq_strerror(-3).startswith(b"ill-posed")
 
 
+def test_side_streams_setting_is_host_only(lib):
+    """wq_set_side_streams only records the count (1..8) for later calls: no device work."""
+    lib.wq_set_side_streams.argtypes = [ctypes.c_int32]
+    lib.wq_set_side_streams.restype = ctypes.c_int
+    assert lib.wq_set_side_streams(0) != 0 and lib.wq_set_side_streams(9) != 0
+    try:
+        assert lib.wq_set_side_streams(1) == 0 and lib.wq_set_side_streams(8) == 0
+    finally:
+        assert lib.wq_set_side_streams(4) == 0
+
+
 def test_struct_layouts_match_the_binding(tmp_path):
     """Sizes and field offsets of the ABI structs, as a C compiler lays them out from
     include/wq.h, equal the ctypes mirrors of the binding."""
